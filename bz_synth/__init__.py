@@ -1,0 +1,199 @@
+"""Seeded synthetic inputs for the Bezier-family evaluators.
+
+This module is shared by the FP64 oracle side and the GPU side.  It draws
+random numbers and lays them out in the arrays both sides consume; it holds
+none of the evaluation arithmetic (no curve is evaluated here, no encoding
+is performed).  Everything is drawn with numpy's PCG64 in float64 and cast
+to float32 once, so both sides see bit-identical FP32 inputs.
+
+Workload shapes follow the evaluation scenarios the paper motivates
+(Sec. 2: curves, C0 piecewise chains, surfaces, volumes and NURBS; Sec. 5:
+many evaluations per frame).  The paper names no public dataset; every
+input here is synthetic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEEDS = {"plain": 1001, "chain": 1002, "batched": 1003, "patch": 1004,
+         "volume": 1005, "fit": 1006}
+
+KIND_BEZIER = 0
+KIND_RATIONAL = 1
+KIND_NURBS = 2
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+# ---------------------------------------------------------------- curves
+def plain_curves(n_curves=4096, degree=3, dim=3, n_t=256, seed=SEEDS["plain"]):
+    """Independent Bezier curves, control points i.i.d. U[-1,1]^dim.
+
+    Returns ctrl[n_curves][dim][degree+1] (f32) and the shared parameter
+    vector t_j = j/(n_t-1) (inclusive grid, so both endpoints are hit)."""
+    rng = np.random.default_rng(seed)
+    ctrl = _f32(rng.uniform(-1.0, 1.0, size=(n_curves, dim, degree + 1)))
+    t = _f32(np.arange(n_t, dtype=np.float64) / max(n_t - 1, 1))
+    return ctrl, t
+
+
+def random_curves(n_curves, degree, dim, n_t, seed, per_object=True, lo=0.0, hi=1.0):
+    """Bezier curves with U[-1,1] control points and uniform random t."""
+    rng = np.random.default_rng(seed)
+    ctrl = _f32(rng.uniform(-1.0, 1.0, size=(n_curves, dim, degree + 1)))
+    shape = (n_curves, n_t) if per_object else (n_t,)
+    t = _f32(rng.uniform(lo, hi, size=shape))
+    return ctrl, t
+
+
+def log_uniform_weights(rng, size, lo=0.25, hi=4.0):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=size))
+
+
+def rational_curves(n_curves, degree, dim, n_t, seed, per_object=True):
+    rng = np.random.default_rng(seed)
+    ctrl = _f32(rng.uniform(-1.0, 1.0, size=(n_curves, dim, degree + 1)))
+    w = _f32(log_uniform_weights(rng, (n_curves, degree + 1)))
+    shape = (n_curves, n_t) if per_object else (n_t,)
+    t = _f32(rng.uniform(0.0, 1.0, size=shape))
+    return ctrl, w, t
+
+
+# ---------------------------------------------------------------- C0 chain
+def chain_walk(n_seg=1 << 20, dim=3, n_q=1 << 24, step=0.1, seed=SEEDS["chain"]):
+    """C0 quadratic chain: 2*n_seg+1 points of a random walk started at 0
+    with i.i.d. U[-step,step]^dim steps.  Point 2k is the shared endpoint
+    A_k, point 2k+1 is the middle control point M_k of segment k.
+
+    Returns chain[2*n_seg+1][dim] (f32) and n_q global parameters
+    T = f32(U[0,1) * n_seg)."""
+    rng = np.random.default_rng(seed)
+    steps = rng.uniform(-step, step, size=(2 * n_seg, dim))
+    walk = np.zeros((2 * n_seg + 1, dim), dtype=np.float64)
+    np.cumsum(steps, axis=0, out=walk[1:])
+    chain = _f32(walk)
+    del walk, steps
+    T = _f32(rng.uniform(0.0, 1.0, size=n_q) * n_seg)
+    return chain, T
+
+
+# ---------------------------------------------------------------- batched
+@dataclass
+class Batch:
+    """Mixed batch of curves in one flat description.
+
+    kind_degree[o] = kind << 8 | degree   (kind 0 Bezier, 1 rational, 2 NURBS)
+    cp_offset[o]   first control point of object o; ctrl holds, for object o,
+                   a [dim][ncp_o] block starting at float index cp_offset[o]*dim
+    w              one weight per control point (1.0 for integral objects)
+    knot_offset[o] first knot of object o (NURBS only; empty range otherwise)
+    t              [n_obj][n_t] parameters in [0,1)
+    """
+    dim: int
+    n_t: int
+    kind_degree: np.ndarray
+    cp_offset: np.ndarray
+    ctrl: np.ndarray
+    w: np.ndarray
+    knot_offset: np.ndarray
+    knots: np.ndarray
+    t: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_obj(self):
+        return int(self.kind_degree.shape[0])
+
+
+def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_hi=15,
+                knots_lo=8, knots_hi=64, seed=SEEDS["batched"]):
+    """Bezier curves of degree U{deg_lo..deg_hi} (half of them rational with
+    log-uniform weights in [0.25,4]) plus cubic NURBS with a clamped knot
+    vector of K ~ U{knots_lo..knots_hi} knots (interior knots sorted U(0,1)),
+    K-4 control points and log-uniform weights.  Objects are shuffled.
+    Control points are U[-1,1]^dim; n_t parameters U[0,1) per object."""
+    rng = np.random.default_rng(seed)
+    n_obj = n_bezier + n_nurbs
+    deg = rng.integers(deg_lo, deg_hi + 1, size=n_bezier)
+    rational = rng.random(n_bezier) < 0.5
+    kinds = np.where(rational, KIND_RATIONAL, KIND_BEZIER)
+    K = rng.integers(knots_lo, knots_hi + 1, size=n_nurbs)
+    perm = rng.permutation(n_obj)
+    kind_degree = np.empty(n_obj, dtype=np.uint16)
+    ncp = np.empty(n_obj, dtype=np.int64)
+    nknot = np.zeros(n_obj, dtype=np.int64)
+    is_b = perm < n_bezier
+    bidx = perm[is_b]
+    nidx = perm[~is_b] - n_bezier
+    kind_degree[is_b] = (kinds[bidx] << 8 | deg[bidx]).astype(np.uint16)
+    ncp[is_b] = deg[bidx] + 1
+    kind_degree[~is_b] = np.uint16(KIND_NURBS << 8 | 3)
+    ncp[~is_b] = K[nidx] - 4
+    nknot[~is_b] = K[nidx]
+    cp_offset = np.zeros(n_obj + 1, dtype=np.int64)
+    np.cumsum(ncp, out=cp_offset[1:])
+    knot_offset = np.zeros(n_obj + 1, dtype=np.int64)
+    np.cumsum(nknot, out=knot_offset[1:])
+    total_cp = int(cp_offset[-1])
+    # Control points: each object's block is [dim][ncp]; drawing all values
+    # i.i.d. makes the block layout irrelevant to the distribution.
+    ctrl = _f32(rng.uniform(-1.0, 1.0, size=total_cp * dim))
+    w = log_uniform_weights(rng, total_cp)
+    kind = kind_degree >> 8
+    integral = np.repeat(kind == KIND_BEZIER, ncp)
+    w[integral] = 1.0
+    w = _f32(w)
+    # Clamped knot vectors: 4 zeros, K-8 sorted uniforms, 4 ones.
+    total_k = int(knot_offset[-1])
+    knots = np.empty(total_k, dtype=np.float64)
+    nurbs_objs = np.nonzero(kind == KIND_NURBS)[0]
+    inner = rng.random(total_k)
+    for o in nurbs_objs:
+        a, b = knot_offset[o], knot_offset[o + 1]
+        k = b - a
+        v = np.sort(inner[a:a + k - 8])
+        knots[a:a + 4] = 0.0
+        knots[a + 4:b - 4] = v
+        knots[b - 4:b] = 1.0
+    knots = _f32(knots)
+    t = _f32(rng.random((n_obj, n_t)))
+    return Batch(dim=dim, n_t=n_t, kind_degree=kind_degree, cp_offset=cp_offset, ctrl=ctrl,
+                 w=w, knot_offset=knot_offset, knots=knots, t=t,
+                 meta={"n_bezier": n_bezier, "n_nurbs": n_nurbs})
+
+
+# ---------------------------------------------------------------- tensor
+def patches(n_obj=1 << 18, du=3, dv=3, dim=3, seed=SEEDS["patch"]):
+    """Tensor-product surface patches, control points U[-1,1]^dim, stored
+    ctrl[n_obj][dim][(du+1)*(dv+1)] with the u index major."""
+    rng = np.random.default_rng(seed)
+    return _f32(rng.uniform(-1.0, 1.0, size=(n_obj, dim, (du + 1) * (dv + 1))))
+
+
+def volumes(n_obj=1 << 16, d=3, dim=3, n_q=1 << 24, seed=SEEDS["volume"]):
+    """Tensor-product volumes of degree (d,d,d), control points U[-1,1]^dim,
+    ctrl[n_obj][dim][(d+1)^3] (u major, w minor), and n_q random (u,v,w) in
+    U[0,1)^3 split evenly over the volumes: uvw[n_obj][n_q/n_obj][3]."""
+    rng = np.random.default_rng(seed)
+    ctrl = _f32(rng.uniform(-1.0, 1.0, size=(n_obj, dim, (d + 1) ** 3)))
+    n_per = n_q // n_obj
+    uvw = _f32(rng.random((n_obj, n_per, 3)))
+    return ctrl, uvw
+
+
+# ---------------------------------------------------------------- fitting
+def fit_problem(n_curves=65536, n_samples=128, dim=3, degree=3, noise=0.01, seed=SEEDS["fit"]):
+    """Curve-fitting problem: ground-truth control points U[-1,1]^dim,
+    sorted sample parameters tau ~ U(0,1) per curve and Gaussian noise of
+    standard deviation `noise` (one draw per target coordinate, stored
+    [dim][n_curves*n_samples]).  The targets are ground_truth(tau) + noise;
+    each side evaluates the ground-truth curve itself."""
+    rng = np.random.default_rng(seed)
+    gt = _f32(rng.uniform(-1.0, 1.0, size=(n_curves, dim, degree + 1)))
+    tau = _f32(np.sort(rng.random((n_curves, n_samples)), axis=1))
+    eps = _f32(rng.normal(0.0, noise, size=(dim, n_curves * n_samples)))
+    return gt, tau, eps

@@ -1,0 +1,512 @@
+/*
+ * bzo.c -- FP64 CPU oracle for Bezier-family evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code,
+ * header, table or helper with the GPU library; it is a plain, slow,
+ * obviously-correct restatement of the mathematics of Anas & Wolfe,
+ * "A Texture Lookup Approach to Bezier Curve Evaluation on the GPU"
+ * (arXiv 2603.15447), evaluated in double precision.
+ *
+ * Conventions shared with the GPU library's interface (not its code):
+ *   curve control points   ctrl[n][dim][deg+1]
+ *   parameters             t[n_t] (shared) or t[n][n_t] (per object)
+ *   results                out[dim][n*n_t], query q = c*n_t + j
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no -ffast-math,
+ * so every product and sum is rounded exactly as written).
+ *
+ * Parity status: every function below is pinned by a CPU test against an
+ * independent fact (exact rational arithmetic, a closed form, the paper's
+ * printed formulas, or a second algorithm).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define BZO_MAXDEG 63
+
+int bzo_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Exact binomial coefficient (exact in double for n <= 63). */
+static double binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    uint64_t r = 1;
+    for (int i = 0; i < k; ++i) r = r * (uint64_t)(n - i) / (uint64_t)(i + 1);
+    return (double)r;
+}
+
+static double ipow(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+/* Linear interpolation L(a,b,t) = (1-t)a + tb, exact at t = 0 and t = 1. */
+static double lerp(double a, double b, double t) { return (1.0 - t) * a + t * b; }
+
+/* Bernstein basis polynomial B_{i,d}(t) = C(d,i) (1-t)^(d-i) t^i. */
+static double bernstein(int d, int i, double t)
+{
+    if (i < 0 || i > d) return 0.0;
+    return binom(d, i) * ipow(1.0 - t, d - i) * ipow(t, i);
+}
+
+/* ------------------------------------------------------------------ */
+/* Bezier curves: de Casteljau recursive lerps (Sec. 2, first paragraph:
+ * interpolate neighbouring points with the same t until one remains).   */
+static double decasteljau(const double *b, int stride, int deg, double t)
+{
+    double tmp[BZO_MAXDEG + 1];
+    for (int i = 0; i <= deg; ++i) tmp[i] = b[(int64_t)i * stride];
+    for (int r = 1; r <= deg; ++r)
+        for (int i = 0; i <= deg - r; ++i) tmp[i] = lerp(tmp[i], tmp[i + 1], t);
+    return tmp[0];
+}
+
+/* Bernstein polynomial form (the "Polynomial" baseline of Sec. 5):
+ * C(t) = sum_i B_{i,d}(t) b_i. */
+static double bernstein_sum(const double *b, int deg, double t)
+{
+    double acc = 0.0;
+    for (int i = 0; i <= deg; ++i) acc += bernstein(deg, i, t) * b[i];
+    return acc;
+}
+
+static double param(const double *t, int64_t c, int64_t j, int64_t nt, int per_object)
+{
+    return per_object ? t[c * nt + j] : t[j];
+}
+
+void bzo_bezier_decasteljau(const double *ctrl, int64_t n, int deg, int dim, const double *t,
+                            int64_t nt, int per_object, double *out)
+{
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t j = 0; j < nt; ++j) {
+            const double tt = param(t, c, j, nt, per_object);
+            for (int k = 0; k < dim; ++k)
+                out[k * nq + c * nt + j] = decasteljau(ctrl + (c * dim + k) * (deg + 1), 1, deg, tt);
+        }
+}
+
+void bzo_bezier_bernstein(const double *ctrl, int64_t n, int deg, int dim, const double *t,
+                          int64_t nt, int per_object, double *out)
+{
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t j = 0; j < nt; ++j) {
+            const double tt = param(t, c, j, nt, per_object);
+            for (int k = 0; k < dim; ++k)
+                out[k * nq + c * nt + j] = bernstein_sum(ctrl + (c * dim + k) * (deg + 1), deg, tt);
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Seiler interpolation (Sec. 3.1).  C(t) = L(b_0, b_d, t) + (1-t)t D_1(t)
+ * with D_i = 0 when 2i = d+1, d_i when 2i = d, and otherwise
+ * L(d_i, d_{d-i}, t) + (1-t)t D_{i+1}(t).
+ *
+ * Difference terms by peeling: a degree-n polynomial Q with Bernstein
+ * coefficients Q_0..Q_n satisfies Q - L(Q_0,Q_n,t) = (1-t)t Q'(t), where Q'
+ * has degree n-2 and Bernstein coefficients
+ *     Q'_{i-1} = (Q_i - ((n-i)/n) Q_0 - (i/n) Q_n) * C(n,i)/C(n-2,i-1).
+ * Starting from Q = C gives D_1 = Q', whose end coefficients are d_1 and
+ * d_{d-1}; peeling Q' gives D_2, and so on.  For the outer level this
+ * reproduces the paper's d_1 and d_{d-1}; the paper gives closed forms up
+ * to degree 5, peeling covers every degree.
+ *
+ * Storage order per curve and coordinate: [b0, bd, d1, d_{d-1}, d2,
+ * d_{d-2}, ...], d+1 values, the middle term d_{d/2} once for even d.   */
+static void seiler_coeffs(const double *b, int deg, double *out)
+{
+    double Q[BZO_MAXDEG + 1], R[BZO_MAXDEG + 1];
+    for (int i = 0; i <= deg; ++i) Q[i] = b[i];
+    out[0] = b[0];
+    if (deg == 0) return;
+    out[1] = b[deg];
+    int pos = 2, n = deg;
+    while (n >= 2) {
+        for (int i = 1; i <= n - 1; ++i) {
+            const double r = Q[i] - ((double)(n - i) / n * Q[0] + (double)i / n * Q[n]);
+            R[i - 1] = r * (binom(n, i) / binom(n - 2, i - 1));
+        }
+        n -= 2;
+        for (int i = 0; i <= n; ++i) Q[i] = R[i];
+        out[pos++] = Q[0];
+        if (n > 0) out[pos++] = Q[n];
+    }
+}
+
+static double seiler_point(const double *sc, int deg, double t)
+{
+    const double st = (1.0 - t) * t;
+    if (deg == 0) return sc[0];
+    const int npairs = (deg - 1) / 2;
+    double D = (deg % 2 == 0) ? sc[2 + 2 * npairs] : 0.0;
+    for (int i = npairs; i >= 1; --i) D = lerp(sc[2 * i], sc[2 * i + 1], t) + st * D;
+    return lerp(sc[0], sc[1], t) + st * D;
+}
+
+void bzo_seiler_from_bezier(const double *ctrl, int64_t n, int deg, int dim, double *seiler)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int k = 0; k < dim; ++k)
+            seiler_coeffs(ctrl + (c * dim + k) * (deg + 1), deg, seiler + (c * dim + k) * (deg + 1));
+}
+
+void bzo_seiler_eval(const double *seiler, int64_t n, int deg, int dim, const double *t, int64_t nt,
+                     int per_object, double *out)
+{
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t j = 0; j < nt; ++j) {
+            const double tt = param(t, c, j, nt, per_object);
+            for (int k = 0; k < dim; ++k)
+                out[k * nq + c * nt + j] = seiler_point(seiler + (c * dim + k) * (deg + 1), deg, tt);
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* C0 piecewise quadratic chain with the shared-diagonal ("zig-zag")
+ * encoding (Sec. 2.1, Eq. 1-2, Fig. 2).
+ *
+ * chain[2N+1][dim]: A_k = chain[2k] (segment endpoints, shared),
+ *                   M_k = chain[2k+1] (middle control point of segment k).
+ * grid[N+1][2][dim]: column k holds A_k in row r_k = k mod 2 (the sampling
+ * path zig-zags between the rows) and a free texel x_k in the other row.
+ * Segment k is the bilinear patch [A_k x_{k+1}; x_k A_{k+1}] read along its
+ * diagonal, i.e. A s^2 + (x_k + x_{k+1}) s t + A' t^2 (Eq. 1), which is the
+ * quadratic with middle point M_k iff (x_k + x_{k+1})/2 = M_k (Eq. 2).
+ * N constraints, N+1 free texels: fix x_0 = M_0 and x_{k+1} = 2 M_k - x_k.  */
+void bzo_piecewise_encode(const double *chain, int64_t nseg, int dim, double *grid)
+{
+    for (int k = 0; k < dim; ++k) {
+        double x = chain[1 * dim + k]; /* x_0 = M_0 */
+        for (int64_t s = 0; s <= nseg; ++s) {
+            const int r = (int)(s & 1);
+            grid[(s * 2 + r) * dim + k] = chain[(2 * s) * dim + k];
+            grid[(s * 2 + (1 - r)) * dim + k] = x;
+            if (s < nseg) x = 2.0 * chain[(2 * s + 1) * dim + k] - x;
+        }
+    }
+}
+
+/* Decode a global parameter T in [0,N] into (segment k, local t).
+ * T is clamped to [0,N]; T = N maps to (N-1, 1); NaN stays NaN in t.      */
+static int64_t chain_decode(double T, int64_t nseg, double *t)
+{
+    if (isnan(T)) { *t = NAN; return 0; }
+    double Tc = T < 0.0 ? 0.0 : (T > (double)nseg ? (double)nseg : T);
+    int64_t k = (int64_t)floor(Tc);
+    if (k > nseg - 1) k = nseg - 1;
+    *t = Tc - (double)k;
+    return k;
+}
+
+void bzo_piecewise_eval(const double *grid, int64_t nseg, int dim, const double *T, int64_t nq,
+                        double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        double t;
+        const int64_t k = chain_decode(T[q], nseg, &t);
+        const int r = (int)(k & 1);
+        const double s = 1.0 - t;
+        for (int c = 0; c < dim; ++c) {
+            const double A = grid[(k * 2 + r) * dim + c];
+            const double xk = grid[(k * 2 + 1 - r) * dim + c];
+            const double xk1 = grid[((k + 1) * 2 + r) * dim + c];
+            const double D = grid[((k + 1) * 2 + 1 - r) * dim + c];
+            out[c * nq + q] = A * s * s + (xk + xk1) * s * t + D * t * t;
+        }
+    }
+}
+
+/* The chain's plain definition: segment k is the quadratic Bezier curve
+ * (A_k, M_k, A_{k+1}) at local parameter t.                               */
+void bzo_chain_eval(const double *chain, int64_t nseg, int dim, const double *T, int64_t nq,
+                    double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        double t;
+        const int64_t k = chain_decode(T[q], nseg, &t);
+        for (int c = 0; c < dim; ++c) {
+            double b[3] = {chain[(2 * k) * dim + c], chain[(2 * k + 1) * dim + c],
+                           chain[(2 * k + 2) * dim + c]};
+            out[c * nq + q] = decasteljau(b, 1, 2, t);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Rational Bezier curves (Sec. 2.2: one integral spline divided by
+ * another): de Casteljau on homogeneous points (w_i b_i, w_i), then divide. */
+static void rational_point(const double *b, const double *w, int dim, int deg, double t, double *res)
+{
+    double hw[BZO_MAXDEG + 1], h[BZO_MAXDEG + 1];
+    for (int i = 0; i <= deg; ++i) hw[i] = w[i];
+    const double W = decasteljau(hw, 1, deg, t);
+    for (int k = 0; k < dim; ++k) {
+        for (int i = 0; i <= deg; ++i) h[i] = w[i] * b[k * (deg + 1) + i];
+        res[k] = decasteljau(h, 1, deg, t) / W;
+    }
+}
+
+void bzo_rational_eval(const double *ctrl, const double *w, int64_t n, int deg, int dim,
+                       const double *t, int64_t nt, int per_object, double *out)
+{
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t j = 0; j < nt; ++j) {
+            double res[8];
+            rational_point(ctrl + c * dim * (deg + 1), w + c * (deg + 1), dim, deg,
+                           param(t, c, j, nt, per_object), res);
+            for (int k = 0; k < dim; ++k) out[k * nq + c * nt + j] = res[k];
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* NURBS (Sec. 2.2) by the rational de Boor algorithm on homogeneous
+ * points; a different algorithm from Bezier-segment extraction, so the two
+ * check each other.  U[0..ncp+p], clamped; u is clamped to [U_p, U_ncp].  */
+static int nurbs_span(const double *U, int ncp, int p, double u)
+{
+    const int n = ncp - 1;
+    if (u >= U[n + 1]) {
+        int j = n;
+        while (j > p && !(U[j] < U[j + 1])) --j;
+        return j;
+    }
+    int j = p;
+    while (j < n && !(u < U[j + 1])) ++j;
+    return j;
+}
+
+static void nurbs_point(const double *P, int stride_dim, const double *w, const double *U, int ncp,
+                        int p, int dim, double u, double *res)
+{
+    double d[BZO_MAXDEG + 1][9];
+    if (isnan(u)) {
+        for (int k = 0; k < dim; ++k) res[k] = NAN;
+        return;
+    }
+    if (u < U[p]) u = U[p];
+    if (u > U[ncp]) u = U[ncp];
+    const int j = nurbs_span(U, ncp, p, u);
+    for (int i = 0; i <= p; ++i) {
+        const int idx = j - p + i;
+        for (int k = 0; k < dim; ++k) d[i][k] = w[idx] * P[(int64_t)k * stride_dim + idx];
+        d[i][dim] = w[idx];
+    }
+    for (int r = 1; r <= p; ++r)
+        for (int i = p; i >= r; --i) {
+            const int idx = j - p + i;
+            const double a = (u - U[idx]) / (U[idx + p + 1 - r] - U[idx]);
+            for (int k = 0; k <= dim; ++k) d[i][k] = (1.0 - a) * d[i - 1][k] + a * d[i][k];
+        }
+    for (int k = 0; k < dim; ++k) res[k] = d[p][k] / d[p][dim];
+}
+
+/* One NURBS curve: ctrl[dim][ncp], w[ncp], knots[ncp+p+1], u[nu] -> out[dim][nu]. */
+void bzo_nurbs_eval(const double *ctrl, const double *w, const double *knots, int ncp, int p, int dim,
+                    const double *u, int64_t nu, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nu; ++q) {
+        double res[8];
+        nurbs_point(ctrl, ncp, w, knots, ncp, p, dim, u[q], res);
+        for (int k = 0; k < dim; ++k) out[k * nu + q] = res[k];
+    }
+}
+
+/* Mixed batch: kind_degree[o] = kind<<8 | degree (0 Bezier, 1 rational,
+ * 2 NURBS).  Object o's control points are ctrl[cp_offset[o]*dim ...] laid
+ * out [dim][ncp]; w is aligned with control points; NURBS knots at
+ * knots[knot_offset[o] ...].  t[n_obj][nt], out[dim][n_obj*nt].           */
+void bzo_batch_eval(int64_t n_obj, const uint16_t *kind_degree, const int64_t *cp_offset,
+                    const double *ctrl, const double *w, const int64_t *knot_offset,
+                    const double *knots, int dim, const double *t, int64_t nt, double *out)
+{
+    const int64_t nq = n_obj * nt;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t o = 0; o < n_obj; ++o) {
+        const int kind = kind_degree[o] >> 8, deg = kind_degree[o] & 0xff;
+        const int ncp = (int)(cp_offset[o + 1] - cp_offset[o]);
+        const double *P = ctrl + cp_offset[o] * dim;
+        const double *W = w + cp_offset[o];
+        for (int64_t j = 0; j < nt; ++j) {
+            const double tt = t[o * nt + j];
+            double res[8];
+            if (kind == 0) {
+                for (int k = 0; k < dim; ++k) res[k] = decasteljau(P + k * ncp, 1, deg, tt);
+            } else if (kind == 1) {
+                rational_point(P, W, dim, deg, tt, res);
+            } else {
+                nurbs_point(P, ncp, W, knots + knot_offset[o], ncp, deg, dim, tt, res);
+            }
+            for (int k = 0; k < dim; ++k) out[k * nq + o * nt + j] = res[k];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Tensor-product surfaces and volumes (Sec. 2.2): S = sum_ijk B_i(u)
+ * B_j(v) B_k(w) P_ijk, evaluated separably by de Casteljau along w, then v,
+ * then u.  ctrl[n_obj][dim][(du+1)(dv+1)(dw+1)], index (i*(dv+1)+j)*(dw+1)+k.  */
+static double tensor_point(const double *P, int du, int dv, int dw, double u, double v, double w)
+{
+    double row[BZO_MAXDEG + 1], col[BZO_MAXDEG + 1];
+    for (int i = 0; i <= du; ++i) {
+        for (int j = 0; j <= dv; ++j) row[j] = decasteljau(P + (i * (dv + 1) + j) * (dw + 1), 1, dw, w);
+        col[i] = decasteljau(row, 1, dv, v);
+    }
+    return decasteljau(col, 1, du, u);
+}
+
+/* Points mode: uvw[n_obj][n_per][npar] with npar = 2 (surfaces, dw = 0) or
+ * 3 (volumes); out[dim][n_obj*n_per].                                      */
+void bzo_tensor_points(const double *ctrl, int64_t n_obj, int du, int dv, int dw, int dim,
+                       const double *uvw, int64_t n_per, double *out)
+{
+    const int npar = dw > 0 ? 3 : 2;
+    const int ncp = (du + 1) * (dv + 1) * (dw + 1);
+    const int64_t nq = n_obj * n_per;
+#pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < n_obj; ++o)
+        for (int64_t j = 0; j < n_per; ++j) {
+            const double *p = uvw + (o * n_per + j) * npar;
+            const double w = npar == 3 ? p[2] : 0.0;
+            for (int k = 0; k < dim; ++k)
+                out[k * nq + o * n_per + j] = tensor_point(ctrl + (o * dim + k) * ncp, du, dv, dw, p[0], p[1], w);
+        }
+}
+
+/* Grid mode for surfaces: u_a = a/(nu-1), v_b = b/(nv-1) inclusive;
+ * out[dim][n_obj*nu*nv], point index o*nu*nv + a*nv + b.                   */
+void bzo_tensor_grid(const double *ctrl, int64_t n_obj, int du, int dv, int dim, int nu, int nv,
+                     double *out)
+{
+    const int ncp = (du + 1) * (dv + 1);
+    const int64_t per = (int64_t)nu * nv, nq = n_obj * per;
+#pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < n_obj; ++o)
+        for (int a = 0; a < nu; ++a)
+            for (int b = 0; b < nv; ++b) {
+                const double u = nu > 1 ? (double)a / (nu - 1) : 0.0;
+                const double v = nv > 1 ? (double)b / (nv - 1) : 0.0;
+                for (int k = 0; k < dim; ++k)
+                    out[k * nq + o * per + a * nv + b] = tensor_point(ctrl + (o * dim + k) * ncp, du, dv, 0, u, v, 0.0);
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of curve evaluation.  For C(t) = H(t)/W(t) with H = sum w_i b_i
+ * B_i, W = sum w_i B_i (W = 1, w_i = 1 for integral curves):
+ *   dC/db_i = w_i B_i / W,   dC/dw_i = B_i (b_i - C) / W,
+ *   dC/dt   = (H' - C W') / W, with the hodograph
+ *   H' = d sum_{i<d} (w_{i+1} b_{i+1} - w_i b_i) B_{i,d-1}(t).
+ * Given grad_out[dim][n*nt] (dL/dC) this accumulates
+ *   grad_ctrl[n][dim][deg+1], grad_w[n][deg+1] (rational only) and
+ *   grad_t[n][nt] (per-object t only).  Outputs are overwritten.           */
+void bzo_bezier_adjoint(const double *ctrl, const double *w, int64_t n, int deg, int dim,
+                        const double *t, int64_t nt, int per_object, const double *gout,
+                        double *gctrl, double *gw, double *gt)
+{
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        const double *b = ctrl + c * dim * (deg + 1);
+        const double *wc = w ? w + c * (deg + 1) : 0;
+        double *gb = gctrl ? gctrl + c * dim * (deg + 1) : 0;
+        double *gwc = gw ? gw + c * (deg + 1) : 0;
+        if (gb) memset(gb, 0, sizeof(double) * dim * (deg + 1));
+        if (gwc) memset(gwc, 0, sizeof(double) * (deg + 1));
+        for (int64_t j = 0; j < nt; ++j) {
+            const double tt = param(t, c, j, nt, per_object);
+            double B[BZO_MAXDEG + 1], Bm[BZO_MAXDEG + 1];
+            for (int i = 0; i <= deg; ++i) B[i] = bernstein(deg, i, tt);
+            for (int i = 0; i < deg; ++i) Bm[i] = bernstein(deg - 1, i, tt);
+            double W = 1.0, Wp = 0.0;
+            if (wc) {
+                W = 0.0;
+                for (int i = 0; i <= deg; ++i) W += wc[i] * B[i];
+                for (int i = 0; i < deg; ++i) Wp += deg * (wc[i + 1] - wc[i]) * Bm[i];
+            }
+            double dt_acc = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                const double *bk = b + k * (deg + 1);
+                const double g = gout[k * nq + c * nt + j];
+                double H = 0.0, Hp = 0.0;
+                for (int i = 0; i <= deg; ++i) H += (wc ? wc[i] : 1.0) * bk[i] * B[i];
+                for (int i = 0; i < deg; ++i) {
+                    const double wi1 = wc ? wc[i + 1] : 1.0, wi = wc ? wc[i] : 1.0;
+                    Hp += deg * (wi1 * bk[i + 1] - wi * bk[i]) * Bm[i];
+                }
+                const double C = H / W;
+                dt_acc += g * (Hp - C * Wp) / W;
+                if (gb)
+                    for (int i = 0; i <= deg; ++i) gb[k * (deg + 1) + i] += g * (wc ? wc[i] : 1.0) * B[i] / W;
+                if (gwc)
+                    for (int i = 0; i <= deg; ++i) gwc[i] += g * B[i] * (bk[i] - C) / W;
+            }
+            if (gt && per_object) gt[c * nt + j] = dt_acc;
+        }
+    }
+}
+
+/* Least-squares fit of integral curves to targets y[dim][n*nt]:
+ *   L = (1/M) sum_q |C(t_q) - y_q|^2, M = n*nt.
+ * Returns L and writes dL/dctrl[n][dim][deg+1] and dL/dt[n][nt].           */
+double bzo_fit_loss_grad(const double *ctrl, int64_t n, int deg, int dim, const double *t, int64_t nt,
+                         const double *y, double *gctrl, double *gt)
+{
+    const int64_t nq = n * nt;
+    double *C = (double *)malloc(sizeof(double) * (size_t)(nq * dim));
+    double *g = (double *)malloc(sizeof(double) * (size_t)(nq * dim));
+    bzo_bezier_decasteljau(ctrl, n, deg, dim, t, nt, 1, C);
+    double L = 0.0;
+    for (int64_t i = 0; i < nq * dim; ++i) {
+        const double r = C[i] - y[i];
+        L += r * r;
+        g[i] = 2.0 * r / (double)nq;
+    }
+    bzo_bezier_adjoint(ctrl, 0, n, deg, dim, t, nt, 1, g, gctrl, 0, gt);
+    free(C);
+    free(g);
+    return L / (double)nq;
+}
+
+/* Adam (Kingma & Ba 2015) with bias correction, step counted from 1;
+ * after the update each parameter is clamped to [lo,hi] when lo <= hi.     */
+void bzo_adam(double *p, double *m, double *v, const double *g, int64_t n, int step, double lr,
+              double b1, double b2, double eps, double lo, double hi)
+{
+    const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        const double mh = m[i] / c1, vh = v[i] / c2;
+        p[i] -= lr * mh / (sqrt(vh) + eps);
+        if (lo <= hi) p[i] = p[i] < lo ? lo : (p[i] > hi ? hi : p[i]);
+    }
+}
