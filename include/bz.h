@@ -1,0 +1,219 @@
+/*
+ * bz.h -- C ABI of the MI355X (gfx950) Bezier-family evaluation library.
+ *
+ * Evaluates Bezier curves, surfaces and volumes (integral and rational),
+ * C0 piecewise quadratic chains in the shared-diagonal encoding and cubic
+ * NURBS at many parameter values, following Anas & Wolfe, "A Texture Lookup
+ * Approach to Bezier Curve Evaluation on the GPU" (arXiv 2603.15447), with
+ * hand-written HIP kernels instead of texture filtering.
+ *
+ * General conventions (apply to every entry point below):
+ *  - Every array argument is a DEVICE pointer owned by the caller.  The
+ *    library never frees it and keeps no reference to it after the call
+ *    returns (plans copy what they need).
+ *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
+ *    stream) and never synchronises the device, except bz_batch_plan_create.
+ *  - Every entry point returns a bz_status.  Arguments are validated before
+ *    anything is launched, so an error leaves no partial work behind.  A
+ *    zero-size call returns BZ_OK without launching.  No C++ exception
+ *    crosses the ABI.  bz_last_error() gives a thread-local message for the
+ *    most recent failure on the calling thread.
+ *  - Parameters outside [0,1] extrapolate the polynomial.  NaN in gives NaN
+ *    out.  Results are FP32.
+ *  - Curve layout: ctrl[n][dim][degree+1] (coordinate-major per curve).
+ *    Parameters t[n_t] (BZ_T_SHARED: the same n_t values for every curve) or
+ *    t[n][n_t] (BZ_T_PER_OBJECT).  Results are planar, out[dim][n*n_t], with
+ *    query q = c*n_t + j.
+ *  - Limits: 1 <= degree <= 15, 1 <= dim <= 4, counts >= 0.  Pointers to
+ *    FP32 data need 4-byte alignment, FP16/BF16 data 2-byte alignment.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *bz_stream; /* hipStream_t */
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_ERR_NULL = 1,        /* a required pointer is NULL */
+    BZ_ERR_SHAPE = 2,       /* degree, dim or a count is out of range */
+    BZ_ERR_DTYPE = 3,       /* unknown storage type */
+    BZ_ERR_UNSUPPORTED = 4, /* valid but not implemented combination */
+    BZ_ERR_ALIGN = 5,       /* pointer misaligned for its element type */
+    BZ_ERR_HIP = 6,         /* the HIP runtime reported an error */
+    BZ_ERR_NOMEM = 7,       /* a device allocation failed */
+    BZ_ERR_INTERNAL = 8     /* unexpected internal failure */
+} bz_status;
+
+typedef enum { BZ_F32 = 0, BZ_F16 = 1, BZ_BF16 = 2 } bz_dtype; /* control-point / weight storage */
+
+typedef enum { BZ_DECASTELJAU = 0, BZ_BERNSTEIN = 1, BZ_SEILER = 2 } bz_method;
+
+typedef enum { BZ_T_SHARED = 0, BZ_T_PER_OBJECT = 1 } bz_tmode;
+
+typedef enum {
+    BZ_TP_VALU = 0,      /* separable FP32 vector evaluation */
+    BZ_TP_MFMA_F32 = 1,  /* basis-matrix contraction on FP32 matrix cores */
+    BZ_TP_MFMA_BF16 = 2, /* BF16 operands, FP32 accumulation */
+    BZ_TP_MFMA_F16 = 3   /* FP16 operands, FP32 accumulation */
+} bz_tp_engine;
+
+int bz_version(void);
+const char *bz_status_string(int code);
+const char *bz_last_error(void);
+
+/* Number of compute units of the current device (0 on failure). */
+int bz_device_cu_count(void);
+
+/*
+ * Bezier curves (Sec. 2: de Casteljau recursive lerps; Sec. 3: Seiler
+ * interpolation; Sec. 5: the Bernstein polynomial form).
+ * ctrl: [n_curves][dim][degree+1] in ctrl_dtype.  t: see t_mode.
+ * method: BZ_DECASTELJAU (d(d+1)/2 lerps), BZ_BERNSTEIN (basis + d+1 FMAs per
+ * coordinate) or BZ_SEILER (difference terms derived per evaluation, then
+ * d lerps).  out: [dim][n_curves*n_t] FP32.
+ */
+int bz_eval_bezier(const void *ctrl, int ctrl_dtype, int64_t n_curves, int degree, int dim, const float *t,
+                   int64_t n_t, int t_mode, int method, float *out, bz_stream stream);
+
+/*
+ * Seiler difference terms (Sec. 3.1: C = L(b0,bd,t) + (1-t)t D_1 with the
+ * recursive D_i).  Writes, per curve and coordinate, d+1 FP32 values
+ * [b0, bd, d1, d_{d-1}, d2, d_{d-2}, ...] (the middle term d_{d/2} once for
+ * even d) to seiler[n_curves][dim][degree+1].
+ */
+int bz_bezier_to_seiler(const void *ctrl, int ctrl_dtype, int64_t n_curves, int degree, int dim, float *seiler,
+                        bz_stream stream);
+
+/* Evaluate curves given by Seiler terms (layout as produced above). */
+int bz_eval_seiler(const float *seiler, int64_t n_curves, int degree, int dim, const float *t, int64_t n_t,
+                   int t_mode, float *out, bz_stream stream);
+
+/*
+ * Rational Bezier curves (Sec. 2.2: one integral spline divided by
+ * another): the chosen method is applied to the homogeneous points
+ * (w_i b_i, w_i) and the result divided by the weight.
+ * w: [n_curves][degree+1] in the same dtype as ctrl.
+ * A point whose conditioning number sum|w_i|B_i / |sum w_i B_i| exceeds
+ * kappa (or whose weight sum is 0 or not finite) is recomputed in FP64 by de
+ * Casteljau.  With all weights positive the number is 1 and no point is
+ * recomputed.  kappa <= 0 disables the recomputation.  n_fixed (nullable,
+ * device, one uint32) is incremented by the number of recomputed points.
+ */
+int bz_eval_rational(const void *ctrl, const void *w, int dtype, int64_t n_curves, int degree, int dim,
+                     const float *t, int64_t n_t, int t_mode, int method, float kappa, float *out,
+                     uint32_t *n_fixed, bz_stream stream);
+
+/*
+ * C0 piecewise quadratic chain, shared-diagonal ("zig-zag") encoding
+ * (Sec. 2.1, Eq. 1-2, Fig. 2).
+ * chain: [2*n_seg+1][dim], A_k = chain[2k] the shared endpoints and
+ *        M_k = chain[2k+1] the middle control point of segment k.
+ * grid:  [n_seg+1][2][dim], 2(n_seg+1) texels.  Column k holds A_k in row
+ *        k mod 2 and a free texel x_k in the other row, with x_0 = M_0 and
+ *        (x_k + x_{k+1})/2 = M_k (the diagonal texels of segment k average
+ *        to its middle control point).  The free texels are formed by an
+ *        FP64 alternating prefix sum and rounded once to FP32.
+ * Uses a small stream-ordered device workspace (hipMallocAsync).
+ */
+int bz_encode_piecewise(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream);
+
+/*
+ * Evaluate the chain at global parameters T[n_q]: T is clamped to
+ * [0, n_seg], segment k = min(floor(T), n_seg-1), local t = T - k, and the
+ * point is the bilinear read of the 2x2 window [A_k x_{k+1}; x_k A_{k+1}]
+ * along its diagonal.  out: [dim][n_q].
+ */
+int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                      bz_stream stream);
+
+/*
+ * Tensor-product surfaces and volumes (Sec. 2.2: per-axis order split).
+ * ctrl: [n_obj][dim][(du+1)(dv+1)(dw+1)] in dtype, index (i*(dv+1)+j)*(dw+1)+k
+ * (u major).  dw = 0 for surfaces.  Degrees 1..4 per axis (dw 0..4).
+ * Grid mode (uvw == NULL, surfaces only): nu x nv inclusive uniform grid,
+ *   u_a = a/(nu-1), v_b = b/(nv-1); out[dim][n_obj*nu*nv], point o*nu*nv +
+ *   a*nv + b.  engine selects VALU or an MFMA contraction (the MFMA engines
+ *   require du = dv = 3, nu = nv = 32 and FP32 storage).
+ * Points mode (uvw != NULL): uvw[n_obj][n_per][2 or 3], out[dim][n_obj*n_per];
+ *   engine must be BZ_TP_VALU.
+ */
+int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, int du, int dv, int dw, int dim,
+                         const float *uvw, int64_t n_per, int nu, int nv, int engine, float *out,
+                         bz_stream stream);
+
+/*
+ * Mixed batches in one persistent launch: integral and rational Bezier
+ * curves of degree 1..15 and cubic NURBS (Sec. 2.2: B-splines are converted
+ * to rational Bezier segments by knot insertion).  All descriptor arrays are
+ * device pointers:
+ *   kind_degree[n_obj]   kind << 8 | degree; kind 0 Bezier, 1 rational,
+ *                        2 NURBS (degree must be 3)
+ *   cp_offset[n_obj+1]   first control point of each object; object o's
+ *                        points are ctrl[cp_offset[o]*dim ...] as [dim][ncp]
+ *   ctrl, w              in dtype; w aligned with control points (ignored
+ *                        for kind 0; may be NULL if no object is rational
+ *                        or NURBS)
+ *   knot_offset[n_obj+1], knots (FP32): NURBS knot vectors, clamped, of
+ *                        length ncp+4; may be NULL if there is no NURBS
+ *   n_t                  parameters per object
+ * The plan reads the descriptor (synchronously), sorts objects into
+ * uniform classes, converts NURBS to segments and keeps its own copies; the
+ * caller's descriptor arrays may be freed afterwards.  Parameters t[n_obj][n_t]
+ * (NURBS parameters are clamped to the knot range) and out[dim][n_obj*n_t]
+ * are passed per evaluation.  method: BZ_DECASTELJAU or BZ_BERNSTEIN.
+ */
+typedef struct bz_plan_s *bz_plan;
+int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64_t *cp_offset, const void *ctrl,
+                         const void *w, int dtype, int dim, const int64_t *knot_offset, const float *knots,
+                         int64_t n_t, int method, bz_stream stream, bz_plan *plan);
+int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
+/* Plan statistics: n_classes, n_tiles, n_segments (NURBS), workgroups. */
+int bz_batch_plan_info(bz_plan plan, int64_t *info4);
+int bz_plan_destroy(bz_plan plan);
+
+/*
+ * Adjoint of curve evaluation (the derivative of Sec. 2's curves): given
+ * grad_out[dim][n_curves*n_t] = dL/dC, writes (overwrites)
+ *   grad_ctrl[n_curves][dim][degree+1]  dL/db_i = sum_j g_j w_i B_i(t_j)/W
+ *   grad_w[n_curves][degree+1]          dL/dw_i = sum_j g_j.(b_i - C_j) B_i(t_j)/W
+ *   grad_t[n_curves][n_t]               dL/dt_j = g_j . C'(t_j) (hodograph)
+ * w NULL means integral curves (grad_w must then be NULL).  Any gradient
+ * pointer may be NULL to skip it.  grad_t requires t_mode BZ_T_PER_OBJECT.
+ * The per-curve sums over j are wave reductions: no atomics, deterministic.
+ */
+int bz_adjoint_bezier(const float *ctrl, const float *w, int64_t n_curves, int degree, int dim, const float *t,
+                      int64_t n_t, int t_mode, const float *grad_out, float *grad_ctrl, float *grad_w,
+                      float *grad_t, bz_stream stream);
+
+/*
+ * One fused least-squares fitting step for integral curves with per-curve
+ * parameters: loss L = (1/M) sum_q |C(t_q) - y_q|^2 (M = n_curves*n_t), its
+ * gradients by the adjoint above, and an Adam update (bias-corrected, step
+ * counted from 1) of ctrl and t in place, t clamped to [0,1].
+ * y: [dim][n_curves*n_t].  m_*, v_*: Adam moments, same shapes as ctrl / t.
+ * loss_part (nullable): [n_curves] per-curve contributions to L before the
+ * update.  Requires n_t <= 1024.
+ */
+int bz_fit_adam_step(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
+                     float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int step, float lr, float beta1,
+                     float beta2, float eps, float *loss_part, bz_stream stream);
+
+/*
+ * n_steps consecutive fitting steps (steps first_step .. first_step+n_steps-1)
+ * captured once into a HIP graph and replayed as one launch on `stream`.
+ */
+int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
+                    float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int first_step, int n_steps, float lr,
+                    float beta1, float beta2, float eps, float *loss_part, bz_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BZ_H */

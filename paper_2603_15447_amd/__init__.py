@@ -1,0 +1,298 @@
+"""Python binding of libbz, the gfx950 Bezier-family evaluation library.
+
+Argument marshalling only: every function passes tensor data pointers and
+torch's current HIP stream to the C ABI declared in ``include/bz.h``; all
+arithmetic runs in the library's HIP kernels.  PyTorch provides device memory
+and streams.  There is no fallback: if ``libbz.so`` is missing or fails to
+load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbz.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "bz.h")
+
+OK, ERR_NULL, ERR_SHAPE, ERR_DTYPE, ERR_UNSUPPORTED, ERR_ALIGN, ERR_HIP, ERR_NOMEM, ERR_INTERNAL = range(9)
+F32, F16, BF16 = 0, 1, 2
+DECASTELJAU, BERNSTEIN, SEILER = 0, 1, 2
+T_SHARED, T_PER_OBJECT = 0, 1
+TP_VALU, TP_MFMA_F32, TP_MFMA_BF16, TP_MFMA_F16 = 0, 1, 2, 3
+
+METHODS = {"decasteljau": DECASTELJAU, "bernstein": BERNSTEIN, "seiler": SEILER}
+ENGINES = {"valu": TP_VALU, "mfma_f32": TP_MFMA_F32, "mfma_bf16": TP_MFMA_BF16, "mfma_f16": TP_MFMA_F16}
+_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+_lib = None
+
+
+class BzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+_P, _I64, _I, _F = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float
+
+_SIGS = {
+    "bz_version": (_I, []),
+    "bz_status_string": (ctypes.c_char_p, [_I]),
+    "bz_last_error": (ctypes.c_char_p, []),
+    "bz_device_cu_count": (_I, []),
+    "bz_eval_bezier": (_I, [_P, _I, _I64, _I, _I, _P, _I64, _I, _I, _P, _P]),
+    "bz_bezier_to_seiler": (_I, [_P, _I, _I64, _I, _I, _P, _P]),
+    "bz_eval_seiler": (_I, [_P, _I64, _I, _I, _P, _I64, _I, _P, _P]),
+    "bz_eval_rational": (_I, [_P, _P, _I, _I64, _I, _I, _P, _I64, _I, _I, _F, _P, _P, _P]),
+    "bz_encode_piecewise": (_I, [_P, _I64, _I, _P, _P]),
+    "bz_eval_piecewise": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_eval_tensor_patch": (_I, [_P, _I, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
+    "bz_batch_plan_create": (_I, [_I64, _P, _P, _P, _P, _I, _I, _P, _P, _I64, _I, _P, ctypes.POINTER(_P)]),
+    "bz_batch_eval": (_I, [_P, _P, _P, _P]),
+    "bz_batch_plan_info": (_I, [_P, _P]),
+    "bz_plan_destroy": (_I, [_P]),
+    "bz_adjoint_bezier": (_I, [_P, _P, _I64, _I, _I, _P, _I64, _I, _P, _P, _P, _P, _P]),
+    "bz_fit_adam_step": (_I, [_P, _P, _P, _I64, _I, _I, _I64, _P, _P, _P, _P, _I, _F, _F, _F, _F, _P, _P]),
+    "bz_fit_adam_run": (_I, [_P, _P, _P, _I64, _I, _I, _I64, _P, _P, _P, _P, _I, _I, _F, _F, _F, _F, _P, _P]),
+}
+
+
+def header_symbols():
+    """Every function name the C header declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(bz_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def lib():
+    """Load libbz.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbz.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().bz_last_error().decode()
+
+
+def status_string(code):
+    return lib().bz_status_string(code).decode()
+
+
+def check(rc):
+    if rc != OK:
+        raise BzError(rc, "%s: %s" % (status_string(rc), last_error()))
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    assert x.is_cuda and x.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return x.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dtype(x):
+    try:
+        return _DT[x.dtype]
+    except KeyError:
+        raise BzError(ERR_DTYPE, "unsupported storage dtype %s" % x.dtype)
+
+
+def _tmode(t, n):
+    if t.dim() == 1:
+        return T_SHARED, t.shape[0]
+    assert t.dim() == 2 and t.shape[0] == n, "t must be [n_t] or [n_curves, n_t]"
+    return T_PER_OBJECT, t.shape[1]
+
+
+def _f32_out(shape, device, out):
+    if out is None:
+        return torch.empty(shape, dtype=torch.float32, device=device)
+    assert out.dtype == torch.float32 and tuple(out.shape) == tuple(shape) and out.is_contiguous()
+    return out
+
+
+# ---------------------------------------------------------------- curves
+def eval_bezier(ctrl, t, method="decasteljau", out=None):
+    """ctrl[n, dim, d+1] (f32/f16/bf16), t[n_t] or [n, n_t] f32 -> out[dim, n*n_t]."""
+    n, dim, dp1 = ctrl.shape
+    mode, nt = _tmode(t, n)
+    out = _f32_out((dim, n * nt), ctrl.device, out)
+    check(lib().bz_eval_bezier(_ptr(ctrl), _dtype(ctrl), n, dp1 - 1, dim, _ptr(t), nt, mode, METHODS[method],
+                               _ptr(out), _stream()))
+    return out
+
+
+def bezier_to_seiler(ctrl, out=None):
+    n, dim, dp1 = ctrl.shape
+    out = _f32_out((n, dim, dp1), ctrl.device, out)
+    check(lib().bz_bezier_to_seiler(_ptr(ctrl), _dtype(ctrl), n, dp1 - 1, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_seiler(seiler, t, out=None):
+    n, dim, dp1 = seiler.shape
+    mode, nt = _tmode(t, n)
+    out = _f32_out((dim, n * nt), seiler.device, out)
+    check(lib().bz_eval_seiler(_ptr(seiler), n, dp1 - 1, dim, _ptr(t), nt, mode, _ptr(out), _stream()))
+    return out
+
+
+def eval_rational(ctrl, w, t, method="decasteljau", kappa=64.0, out=None, n_fixed=None):
+    """Rational curves; n_fixed (optional int32 device tensor of one element)
+    is incremented by the number of points recomputed in FP64."""
+    n, dim, dp1 = ctrl.shape
+    assert w.shape == (n, dp1) and w.dtype == ctrl.dtype
+    mode, nt = _tmode(t, n)
+    out = _f32_out((dim, n * nt), ctrl.device, out)
+    check(lib().bz_eval_rational(_ptr(ctrl), _ptr(w), _dtype(ctrl), n, dp1 - 1, dim, _ptr(t), nt, mode,
+                                 METHODS[method], float(kappa), _ptr(out), _ptr(n_fixed), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- chains
+def encode_piecewise(chain, out=None):
+    """chain[2N+1, dim] -> zig-zag grid[N+1, 2, dim]."""
+    m, dim = chain.shape
+    nseg = (m - 1) // 2
+    assert m == 2 * nseg + 1
+    out = _f32_out((nseg + 1, 2, dim), chain.device, out)
+    check(lib().bz_encode_piecewise(_ptr(chain), nseg, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise(grid, T, out=None):
+    """grid[N+1, 2, dim], T[n_q] -> out[dim, n_q]."""
+    nseg = grid.shape[0] - 1
+    dim = grid.shape[2]
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), grid.device, out)
+    check(lib().bz_eval_piecewise(_ptr(grid), nseg, dim, _ptr(T), nq, _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- tensor
+def eval_tensor_patch(ctrl, du, dv, dw=0, uvw=None, nu=0, nv=0, engine="valu", out=None):
+    n, dim, _ = ctrl.shape
+    if uvw is None:
+        nq, n_per = n * nu * nv, 0
+    else:
+        n_per = uvw.shape[1]
+        nq = n * n_per
+    out = _f32_out((dim, nq), ctrl.device, out)
+    check(lib().bz_eval_tensor_patch(_ptr(ctrl), _dtype(ctrl), n, du, dv, dw, dim, _ptr(uvw), n_per, nu, nv,
+                                     ENGINES[engine], _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- batched
+class BatchPlan:
+    """Plan for a mixed batch (see bz_batch_plan_create)."""
+
+    def __init__(self, kind_degree, cp_offset, ctrl, w, dim, knot_offset, knots, n_t, method="bernstein"):
+        self.n_obj = kind_degree.shape[0]
+        self.dim, self.n_t = dim, n_t
+        self.device = ctrl.device
+        h = _P()
+        check(lib().bz_batch_plan_create(self.n_obj, _ptr(kind_degree), _ptr(cp_offset), _ptr(ctrl), _ptr(w),
+                                         _dtype(ctrl), dim, _ptr(knot_offset), _ptr(knots), n_t, METHODS[method],
+                                         _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        buf = (ctypes.c_int64 * 4)()
+        check(lib().bz_batch_plan_info(self._h, ctypes.cast(buf, _P)))
+        return {"n_classes": buf[0], "n_tiles": buf[1], "n_segments": buf[2], "workgroups": buf[3]}
+
+    def __call__(self, t, out=None):
+        assert t.shape == (self.n_obj, self.n_t)
+        out = _f32_out((self.dim, self.n_obj * self.n_t), self.device, out)
+        check(lib().bz_batch_eval(self._h, _ptr(t), _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bz_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- adjoint
+def adjoint_bezier(ctrl, t, grad_out, w=None, need_ctrl=True, need_w=None, need_t=True):
+    """Returns (grad_ctrl, grad_w, grad_t); entries not requested are None."""
+    n, dim, dp1 = ctrl.shape
+    mode, nt = _tmode(t, n)
+    need_w = (w is not None) if need_w is None else need_w
+    dev = ctrl.device
+    gc = torch.empty_like(ctrl) if need_ctrl else None
+    gw = torch.empty((n, dp1), dtype=torch.float32, device=dev) if need_w else None
+    gt = torch.empty((n, nt), dtype=torch.float32, device=dev) if need_t else None
+    check(lib().bz_adjoint_bezier(_ptr(ctrl), _ptr(w), n, dp1 - 1, dim, _ptr(t), nt, mode, _ptr(grad_out), _ptr(gc),
+                                  _ptr(gw), _ptr(gt), _stream()))
+    return gc, gw, gt
+
+
+def fit_adam_step(ctrl, t, y, m_ctrl, v_ctrl, m_t, v_t, step, lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
+                  loss_part=None):
+    n, dim, dp1 = ctrl.shape
+    nt = t.shape[1]
+    check(lib().bz_fit_adam_step(_ptr(ctrl), _ptr(t), _ptr(y), n, dp1 - 1, dim, nt, _ptr(m_ctrl), _ptr(v_ctrl),
+                                 _ptr(m_t), _ptr(v_t), step, lr, betas[0], betas[1], eps, _ptr(loss_part),
+                                 _stream()))
+
+
+def fit_adam_run(ctrl, t, y, m_ctrl, v_ctrl, m_t, v_t, first_step, n_steps, lr=1e-2, betas=(0.9, 0.999),
+                 eps=1e-8, loss_part=None):
+    n, dim, dp1 = ctrl.shape
+    nt = t.shape[1]
+    check(lib().bz_fit_adam_run(_ptr(ctrl), _ptr(t), _ptr(y), n, dp1 - 1, dim, nt, _ptr(m_ctrl), _ptr(v_ctrl),
+                                _ptr(m_t), _ptr(v_t), first_step, n_steps, lr, betas[0], betas[1], eps,
+                                _ptr(loss_part), _stream()))
+
+
+class BezierCurve(torch.autograd.Function):
+    """Differentiable curve evaluation: forward by eval_bezier (rational when
+    w is given), backward by the hand-written adjoint kernel.  t must be per
+    curve ([n, n_t]) to receive a gradient."""
+
+    @staticmethod
+    def forward(ctx, ctrl, t, w=None, method="decasteljau"):
+        ctx.save_for_backward(ctrl, t, w)
+        if w is None:
+            return eval_bezier(ctrl, t, method)
+        return eval_rational(ctrl, w, t, method)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        ctrl, t, w = ctx.saved_tensors
+        need_t = ctx.needs_input_grad[1]
+        if need_t and t.dim() != 2:
+            raise BzError(ERR_UNSUPPORTED, "gradient w.r.t. a shared t is not provided; pass t as [n, n_t]")
+        gc, gw, gt = adjoint_bezier(ctrl, t, grad_out.contiguous(), w=w, need_ctrl=ctx.needs_input_grad[0],
+                                    need_w=w is not None and ctx.needs_input_grad[2], need_t=need_t)
+        return gc, gt, gw, None
+
+
+def bezier_curve(ctrl, t, w=None, method="decasteljau"):
+    return BezierCurve.apply(ctrl, t, w, method)

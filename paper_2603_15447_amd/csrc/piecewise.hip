@@ -1,0 +1,251 @@
+// C0 piecewise quadratic chains in the shared-diagonal ("zig-zag") encoding
+// (Sec. 2.1, Eq. 1-2, Fig. 2): encoder and random-access evaluator.
+//
+// Grid layout in HBM: grid[n_seg+1][2][dim] FP32, one 2*dim*4-byte column per
+// chain vertex, so segment k reads one contiguous 16*dim-byte window (columns
+// k and k+1).  The evaluator is a gather: each thread takes QPT queries, issues
+// all their parameter loads, then all their window loads (8-byte vector loads,
+// cached: the grid is re-read by many queries), then evaluates and streams the
+// results out with non-temporal stores so they do not evict the grid from the
+// L2 and the Infinity Cache.
+#include <cstdlib>
+
+#include "common.h"
+
+namespace bzi {
+namespace {
+
+constexpr int kEncPerThread = 8;
+constexpr int kEncPerBlock = kBlock * kEncPerThread;
+
+// Element e_k = (-1)^(k+1) * 2 M_k of the alternating sum: the free texels are
+// x_k = (-1)^k y_k with y_k = M_0 + sum_{j<k} e_j, which is x_{k+1} = 2M_k - x_k.
+__device__ __forceinline__ double enc_elem(const float *__restrict__ chain, int dim, int c, int64_t k, int64_t n_seg) {
+    if (k >= n_seg) return 0.0;
+    const double m = static_cast<double>(chain[(2 * k + 1) * dim + c]);
+    return (k & 1) ? 2.0 * m : -2.0 * m;
+}
+
+// Inclusive scan of one double per thread over the block (four waves).
+__device__ double block_scan_incl(double v, double *lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    double pre = 0.0;
+    for (int w = 0; w < wave; ++w) pre += lds[w];
+    __syncthreads();
+    return v + pre;
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_partials(const float *__restrict__ chain, int64_t n_seg, int dim,
+                                                         double *__restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
+    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kEncPerBlock + threadIdx.x * kEncPerThread;
+    for (int c = 0; c < dim; ++c) {
+        double s = 0.0;
+        for (int i = 0; i < kEncPerThread; ++i) s += enc_elem(chain, dim, c, k0 + i, n_seg);
+        const double tot = block_scan_incl(s, lds);
+        if (threadIdx.x == kBlock - 1) partial[static_cast<int64_t>(blockIdx.x) * dim + c] = tot;
+    }
+}
+
+// Exclusive scan of the block partials (one block, serial over chunks),
+// seeded with y_0 = M_0.
+__global__ __launch_bounds__(kBlock) void k_enc_offsets(const float *__restrict__ chain, int64_t nb, int dim,
+                                                        double *__restrict__ partial) {
+    __shared__ double lds[kBlock / 64];
+    __shared__ double total;
+    for (int c = 0; c < dim; ++c) {
+        double carry = static_cast<double>(chain[1 * dim + c]);
+        for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+            const int64_t b = b0 + threadIdx.x;
+            const double v = b < nb ? partial[b * dim + c] : 0.0;
+            const double incl = block_scan_incl(v, lds);
+            if (b < nb) partial[b * dim + c] = carry + (incl - v);
+            if (threadIdx.x == kBlock - 1) total = incl;
+            __syncthreads();
+            carry += total;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_enc_write(const float *__restrict__ chain, int64_t n_seg, int dim,
+                                                      const double *__restrict__ offsets, float *__restrict__ grid) {
+    __shared__ double lds[kBlock / 64];
+    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kEncPerBlock + threadIdx.x * kEncPerThread;
+    for (int c = 0; c < dim; ++c) {
+        double e[kEncPerThread];
+        double s = 0.0;
+        for (int i = 0; i < kEncPerThread; ++i) {
+            e[i] = enc_elem(chain, dim, c, k0 + i, n_seg);
+            s += e[i];
+        }
+        const double incl = block_scan_incl(s, lds);
+        double y = offsets[static_cast<int64_t>(blockIdx.x) * dim + c] + (incl - s);
+        for (int i = 0; i < kEncPerThread; ++i) {
+            const int64_t k = k0 + i;
+            if (k > n_seg) break;
+            const int r = static_cast<int>(k & 1);
+            const double x = r ? -y : y;
+            grid[(k * 2 + r) * dim + c] = chain[(2 * k) * dim + c];
+            grid[(k * 2 + 1 - r) * dim + c] = static_cast<float>(x);
+            y += e[i];
+        }
+    }
+}
+
+template <int DIM, int QPT>
+__global__ __launch_bounds__(kBlock) void k_piecewise_eval(const float *__restrict__ grid, uint32_t n_seg,
+                                                           const float *__restrict__ T, uint32_t nq,
+                                                           float *__restrict__ out, int64_t plane) {
+    const uint32_t base = blockIdx.x * (kBlock * QPT) + threadIdx.x;
+    const float nf = static_cast<float>(n_seg);
+    const float nm1 = static_cast<float>(n_seg - 1);
+    // No branches: tail lanes (q >= nq) redo query nq-1 and store the same
+    // value to the same place, so every query's gather stays in flight at once.
+    float tl[QPT];
+    uint32_t kk[QPT];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+        const float Tq = ld_stream(T + q);
+        float Tc = Tq < 0.0f ? 0.0f : Tq;  // NaN passes both clamps
+        Tc = Tc > nf ? nf : Tc;
+        const float kf = __builtin_fminf(__builtin_floorf(Tc), nm1);  // NaN -> n_seg-1
+        const uint32_t k = min(static_cast<uint32_t>(kf), n_seg - 1);
+        kk[i] = k;
+        tl[i] = Tc - static_cast<float>(k);
+    }
+    // Window of segment k: columns k and k+1, 4*DIM floats, 8-byte aligned.
+    float2 g[QPT][2 * DIM];
+    const float2 *__restrict__ g2 = reinterpret_cast<const float2 *>(grid);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+        for (int j = 0; j < 2 * DIM; ++j) g[i][j] = g2[static_cast<size_t>(kk[i]) * DIM + j];
+    float v[QPT][DIM];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        float f[4 * DIM];
+#pragma unroll
+        for (int j = 0; j < 2 * DIM; ++j) {
+            f[2 * j] = g[i][j].x;
+            f[2 * j + 1] = g[i][j].y;
+        }
+        const bool odd = kk[i] & 1;
+        const float t = tl[i];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const float c0r0 = f[c], c0r1 = f[DIM + c], c1r0 = f[2 * DIM + c], c1r1 = f[3 * DIM + c];
+            // on-path texels A_k (row k mod 2 of column k) and A_{k+1}; off-path x_k, x_{k+1}
+            const float A = odd ? c0r1 : c0r0, xk = odd ? c0r0 : c0r1;
+            const float xk1 = odd ? c1r1 : c1r0, A1 = odd ? c1r0 : c1r1;
+            // bilinear read along the diagonal: L(L(A, x_{k+1}), L(x_k, A_{k+1})) (Eq. 1)
+            v[i][c] = lerp(lerp(A, xk1, t), lerp(xk, A1, t), t);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) st_stream(out + c * plane + q, v[i][c]);
+    }
+}
+
+// Queries per thread; BZ_PIECEWISE_QPT (1, 2, 4 or 8) overrides the default.
+int piecewise_qpt() {
+    static const int q = [] {
+        const char *e = getenv("BZ_PIECEWISE_QPT");
+        const int v = e ? atoi(e) : 4;
+        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 4;
+    }();
+    return q;
+}
+
+template <int DIM, int QPT>
+int launch_eval_q(const float *grid, uint32_t n_seg, const float *T, uint32_t nq, float *out, int64_t plane,
+                  hipStream_t s) {
+    const uint32_t per_block = kBlock * QPT;
+    const uint32_t blocks = (nq + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_piecewise_eval<DIM, QPT>), dim3(blocks), dim3(kBlock), 0, s, grid, n_seg, T, nq, out, plane);
+    BZ_CHECK_LAUNCH("k_piecewise_eval");
+    return BZ_OK;
+}
+
+template <int DIM>
+int launch_eval(const float *grid, uint32_t n_seg, const float *T, uint32_t nq, float *out, int64_t plane,
+                hipStream_t s) {
+    switch (piecewise_qpt()) {
+        case 1: return launch_eval_q<DIM, 1>(grid, n_seg, T, nq, out, plane, s);
+        case 2: return launch_eval_q<DIM, 2>(grid, n_seg, T, nq, out, plane, s);
+        case 8: return launch_eval_q<DIM, 8>(grid, n_seg, T, nq, out, plane, s);
+        default: return launch_eval_q<DIM, 4>(grid, n_seg, T, nq, out, plane, s);
+    }
+}
+
+}  // namespace
+}  // namespace bzi
+
+using namespace bzi;
+
+extern "C" {
+
+int bz_encode_piecewise(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream) {
+    return guarded("bz_encode_piecewise", [&]() -> int {
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "bz_encode_piecewise: dim %d", dim);
+        if (n_seg < 0 || n_seg > (int64_t(1) << 40)) return fail(BZ_ERR_SHAPE, "bz_encode_piecewise: n_seg %lld", (long long)n_seg);
+        if (n_seg == 0) return BZ_OK;
+        if (!chain || !grid) return fail(BZ_ERR_NULL, "bz_encode_piecewise: chain and grid are required");
+        if (!aligned(chain, 4) || !aligned(grid, 4)) return fail(BZ_ERR_ALIGN, "bz_encode_piecewise: misaligned");
+        const hipStream_t s = as_stream(stream);
+        const int64_t nb = (n_seg + 1 + kEncPerBlock - 1) / kEncPerBlock;
+        double *partial = nullptr;
+        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * nb * dim, s);
+        if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "bz_encode_piecewise: workspace");
+        BZ_CHECK_HIP(e);
+        hipLaunchKernelGGL(k_enc_partials, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, chain, n_seg, dim, partial);
+        hipLaunchKernelGGL(k_enc_offsets, dim3(1), dim3(kBlock), 0, s, chain, nb, dim, partial);
+        hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, chain, n_seg, dim, partial, grid);
+        const hipError_t le = hipGetLastError();
+        BZ_CHECK_HIP(hipFreeAsync(partial, s));
+        if (le != hipSuccess) return hip_fail(le, "bz_encode_piecewise kernels");
+        return BZ_OK;
+    });
+}
+
+int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                      bz_stream stream) {
+    return guarded("bz_eval_piecewise", [&]() -> int {
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "bz_eval_piecewise: dim %d", dim);
+        if (n_q < 0) return fail(BZ_ERR_SHAPE, "bz_eval_piecewise: n_q %lld", (long long)n_q);
+        if (n_seg < 1 || n_seg > (int64_t(1) << 31))
+            return fail(BZ_ERR_SHAPE, "bz_eval_piecewise: n_seg %lld not in 1..2^31", (long long)n_seg);
+        if (n_q == 0) return BZ_OK;
+        if (!grid || !T || !out) return fail(BZ_ERR_NULL, "bz_eval_piecewise: grid, T and out are required");
+        if (!aligned(grid, 8) || !aligned(T, 4) || !aligned(out, 4))
+            return fail(BZ_ERR_ALIGN, "bz_eval_piecewise: grid needs 8-byte, T and out 4-byte alignment");
+        const hipStream_t s = as_stream(stream);
+        const int64_t per = int64_t(1) << 30;
+        for (int64_t q0 = 0; q0 < n_q; q0 += per) {
+            const uint32_t nq = static_cast<uint32_t>(std::min(per, n_q - q0));
+            const uint32_t ns = static_cast<uint32_t>(n_seg);
+            int rc;
+            switch (dim) {
+                case 1: rc = launch_eval<1>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
+                case 2: rc = launch_eval<2>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
+                case 3: rc = launch_eval<3>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
+                default: rc = launch_eval<4>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
+            }
+            if (rc) return rc;
+        }
+        return BZ_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""CPU-only checks of the C ABI: the library loads without a GPU, exports
+every symbol the header declares, and rejects bad arguments with the
+documented status codes before anything is launched."""
+import ctypes
+
+import pytest
+
+import paper_2603_15447_amd as bz
+
+FAKE = 0x10000  # a non-NULL, 256-byte aligned address; never dereferenced
+ODD = 0x10002
+
+
+@pytest.fixture(scope="module")
+def L():
+    return bz.lib()
+
+
+def test_exports_every_header_symbol(L):
+    syms = bz.header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(bz._SIGS)
+
+
+def test_status_strings(L):
+    assert L.bz_version() >= 10000
+    for code in range(9):
+        assert bz.status_string(code)
+    assert bz.status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("degree,dim,code", [(0, 3, bz.ERR_SHAPE), (16, 3, bz.ERR_SHAPE), (3, 0, bz.ERR_SHAPE),
+                                             (3, 5, bz.ERR_SHAPE)])
+def test_bezier_shape_errors(L, degree, dim, code):
+    rc = L.bz_eval_bezier(FAKE, bz.F32, 4, degree, dim, FAKE, 8, bz.T_SHARED, bz.BERNSTEIN, FAKE, None)
+    assert rc == code
+    assert "bz_eval_bezier" in bz.last_error()
+
+
+def test_bezier_other_errors(L):
+    assert L.bz_eval_bezier(FAKE, 7, 4, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.ERR_DTYPE
+    assert L.bz_eval_bezier(FAKE, 0, 4, 3, 3, FAKE, 8, 0, 9, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_eval_bezier(FAKE, 0, 4, 3, 3, FAKE, 8, 5, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_bezier(None, 0, 4, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_bezier(FAKE, 0, 4, 3, 3, FAKE, 8, 0, 0, None, None) == bz.ERR_NULL
+    assert L.bz_eval_bezier(ODD, 0, 4, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_bezier(FAKE, 0, -1, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.ERR_SHAPE
+    # F16 storage needs only 2-byte alignment
+    assert L.bz_eval_bezier(ODD, 1, 0, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.OK
+
+
+def test_zero_size_calls_launch_nothing(L):
+    # NULL pointers are fine when there is nothing to do
+    assert L.bz_eval_bezier(None, 0, 0, 3, 3, None, 8, 0, 0, None, None) == bz.OK
+    assert L.bz_eval_bezier(None, 0, 5, 3, 3, None, 0, 0, 0, None, None) == bz.OK
+    assert L.bz_eval_seiler(None, 0, 3, 3, None, 4, 0, None, None) == bz.OK
+    assert L.bz_eval_rational(None, None, 0, 0, 3, 3, None, 4, 0, 0, 64.0, None, None, None) == bz.OK
+    assert L.bz_bezier_to_seiler(None, 0, 0, 3, 3, None, None) == bz.OK
+    assert L.bz_encode_piecewise(None, 0, 3, None, None) == bz.OK
+    assert L.bz_eval_piecewise(None, 4, 3, None, 0, None, None) == bz.OK
+
+
+def test_rational_and_seiler_errors(L):
+    assert L.bz_eval_rational(FAKE, None, 0, 4, 3, 3, FAKE, 8, 0, 0, 64.0, FAKE, None, None) == bz.ERR_NULL
+    assert L.bz_eval_rational(FAKE, FAKE, 3, 4, 3, 3, FAKE, 8, 0, 0, 64.0, FAKE, None, None) == bz.ERR_DTYPE
+    assert L.bz_eval_rational(FAKE, FAKE, 0, 4, 3, 3, FAKE, 8, 0, 0, 64.0, FAKE, ODD, None) == bz.ERR_ALIGN
+    assert L.bz_eval_seiler(FAKE, 4, 16, 3, FAKE, 8, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_bezier_to_seiler(FAKE, 0, 4, 3, 9, FAKE, None) == bz.ERR_SHAPE
+
+
+def test_piecewise_errors(L):
+    assert L.bz_eval_piecewise(FAKE, 0, 3, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise(FAKE, 4, 5, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise(FAKE + 4, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise(None, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_NULL
+    assert L.bz_encode_piecewise(FAKE, -2, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_encode_piecewise(FAKE, 4, 3, None, None) == bz.ERR_NULL
+
+
+def test_product_path_has_no_fallback(monkeypatch, tmp_path):
+    """The binding raises when the library is missing; it never computes on the CPU."""
+    monkeypatch.setattr(bz, "_lib", None)
+    monkeypatch.setattr(bz, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        bz.lib()

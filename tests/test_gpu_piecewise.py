@@ -1,0 +1,81 @@
+"""GPU parity: zig-zag encoding and random-access evaluation of C0
+quadratic chains (Sec. 2.1) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import bz_synth
+import paper_2603_15447_amd as bz
+from tests._gpu import TOL_F32, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _chain_extent(chain):
+    c = np.asarray(chain, np.float64)
+    return float((c.max(axis=0) - c.min(axis=0)).max())
+
+
+@pytest.mark.parametrize("n_seg,dim", [(1, 3), (2, 1), (1000, 3), (4097, 2), (3001, 4)])
+def test_encode_parity(orc, n_seg, dim):
+    chain, _ = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=1, seed=n_seg)
+    grid = host(bz.encode_piecewise(to_dev(chain)))
+    ref = orc.piecewise_encode(chain)
+    assert grid.shape == (n_seg + 1, 2, dim)
+    ext = _chain_extent(chain)
+    # on-path texels are copies: bit-exact
+    for k in range(n_seg + 1):
+        np.testing.assert_array_equal(grid[k, k & 1], chain[2 * k])
+    # free texels: one FP32 rounding of an FP64 alternating sum
+    assert np.abs(grid - ref).max() <= 1e-6 * max(ext, np.abs(ref).max())
+    x = np.array([grid[k, 1 - (k & 1)] for k in range(n_seg + 1)])
+    np.testing.assert_allclose((x[:-1] + x[1:]) / 2, chain[1::2][:n_seg], rtol=0,
+                               atol=2e-7 * max(1.0, np.abs(x).max()))
+
+
+@pytest.mark.parametrize("n_seg,dim,n_q", [(1, 3, 100), (5, 1, 1000), (1000, 3, 5003), (2048, 2, 70001),
+                                           (777, 4, 4099)])
+def test_eval_parity(orc, n_seg, dim, n_q):
+    chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=n_q, seed=3 * n_seg + dim)
+    grid = orc.piecewise_encode(chain).astype(np.float32)
+    got = host(bz.eval_piecewise(to_dev(grid), to_dev(T)))
+    ref = orc.piecewise_eval(grid, T)
+    ext = _chain_extent(chain)
+    assert np.abs(got - ref).max() <= TOL_F32 * ext
+    # same answer as the chain's plain definition
+    ref2 = orc.chain_eval(chain, T)
+    assert np.abs(got - ref2).max() <= TOL_F32 * ext
+
+
+def test_eval_edges(orc):
+    """Clamping, T = N, integer T (exact vertices), NaN."""
+    n_seg = 64
+    chain, _ = bz_synth.chain_walk(n_seg=n_seg, dim=3, n_q=1, seed=5)
+    grid = bz.encode_piecewise(to_dev(chain))
+    T = np.array([-5.0, 0.0, 64.0, 70.0, np.inf, -np.inf, np.nan, 0.5, 63.999996] + list(range(65)), np.float32)
+    got = host(bz.eval_piecewise(grid, to_dev(T)))
+    np.testing.assert_array_equal(got[:, 0], chain[0])
+    np.testing.assert_array_equal(got[:, 1], chain[0])
+    np.testing.assert_array_equal(got[:, 2], chain[2 * n_seg])
+    np.testing.assert_array_equal(got[:, 3], chain[2 * n_seg])
+    np.testing.assert_array_equal(got[:, 4], chain[2 * n_seg])
+    np.testing.assert_array_equal(got[:, 5], chain[0])
+    assert np.isnan(got[:, 6]).all()
+    # C0: at every integer T the chain passes exactly through the shared vertex
+    np.testing.assert_array_equal(got[:, 9:].T, chain[0::2])
+    ref = orc.piecewise_eval(host(grid), T[7:9])
+    np.testing.assert_allclose(got[:, 7:9], ref, rtol=0, atol=1e-5)
+
+
+def test_encode_then_eval_full_chain_config(orc):
+    """2^20 segments, 2^24 random global parameters: GPU encode + GPU eval
+    against the oracle's chain definition at every query."""
+    chain, T = bz_synth.chain_walk()
+    grid = bz.encode_piecewise(to_dev(chain))
+    got = host(bz.eval_piecewise(grid, to_dev(T)))
+    ref = orc.chain_eval(chain, T)
+    ext = _chain_extent(chain)
+    err = np.abs(got - ref).max() / ext
+    assert err <= TOL_F32, err
+    del got, ref
+    # storage: 2(N+1) texels
+    assert grid.shape[0] * grid.shape[1] == 2 * ((chain.shape[0] - 1) // 2 + 1)
