@@ -34,6 +34,20 @@ def chain_bytes(n_seg, dim, n_q):
     return (n_seg + 1) * 2 * dim * 4 + n_q * 4 + n_q * dim * 4
 
 
+def recorded_traffic(name="chain_eval_counters.json"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            d = json.load(f)
+        with open(os.path.join(ROOT, d["kernel_source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return d["traffic_bytes_per_dispatch"] if sha == d["kernel_source_sha256"] else None
+
+
 def event_time_ms(fn, iters, torch):
     """Average device time of fn() over `iters` back-to-back launches, with
     HIP events recorded on the stream the kernels are launched on."""
@@ -146,7 +160,7 @@ def main():
                                "%d uniform random global T, 3D, FP32" % (args.n_seg, args.n_q),
                    "n_seg": args.n_seg, "n_q": args.n_q, "dim": dim},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic()},
         "kernel": "k_piecewise_eval",
         "kernel_ms": kern_ms,
         "algorithmic_bytes": nbytes,

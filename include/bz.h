@@ -10,7 +10,8 @@
  * General conventions (apply to every entry point below):
  *  - Every array argument is a DEVICE pointer owned by the caller.  The
  *    library never frees it and keeps no reference to it after the call
- *    returns (plans copy what they need).
+ *    returns, except the control points and weights of a batch plan (see
+ *    bz_batch_plan_create).
  *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
  *    stream) and never synchronises the device, except bz_batch_plan_create.
  *  - Every entry point returns a bz_status.  Arguments are validated before
@@ -133,6 +134,21 @@ int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T,
                       bz_stream stream);
 
 /*
+ * Cache-line-tiled placement of the same zig-zag texels: 128-byte tiles of
+ * C = 128/(8*dim) consecutive grid columns (16, 8, 5, 4 for dim 1..4),
+ * consecutive tiles overlapping by one column, so tile j holds segments
+ * [j*(C-1), (j+1)*(C-1)) and each segment's 2x2 window lies in one 128-byte
+ * line.  Unused tile bytes are zero.  bz_piecewise_tiled_floats gives the
+ * buffer size in floats (0 for invalid arguments; host function, no device
+ * access).  tiles must be 128-byte aligned.  bz_eval_piecewise_tiled has the
+ * semantics of bz_eval_piecewise.
+ */
+int64_t bz_piecewise_tiled_floats(int64_t n_seg, int dim);
+int bz_tile_piecewise(const float *grid, int64_t n_seg, int dim, float *tiles, bz_stream stream);
+int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                            bz_stream stream);
+
+/*
  * Tensor-product surfaces and volumes (Sec. 2.2: per-axis order split).
  * ctrl: [n_obj][dim][(du+1)(dv+1)(dw+1)] in dtype, index (i*(dv+1)+j)*(dw+1)+k
  * (u major).  dw = 0 for surfaces.  Degrees 1..4 per axis (dw 0..4).
@@ -163,16 +179,29 @@ int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, int du, int
  *                        length ncp+4; may be NULL if there is no NURBS
  *   n_t                  parameters per object
  * The plan reads the descriptor (synchronously), sorts objects into
- * uniform classes, converts NURBS to segments and keeps its own copies; the
- * caller's descriptor arrays may be freed afterwards.  Parameters t[n_obj][n_t]
- * (NURBS parameters are clamped to the knot range) and out[dim][n_obj*n_t]
- * are passed per evaluation.  method: BZ_DECASTELJAU or BZ_BERNSTEIN.
+ * uniform classes, extracts the rational Bezier segments of every NURBS on the
+ * GPU and keeps its own copies of all of that, so kind_degree, cp_offset,
+ * knot_offset and knots may be freed afterwards.  ctrl and w are referenced,
+ * not copied: they must stay allocated while the plan is used (values of
+ * Bezier objects may change between evaluations; NURBS changes need a new
+ * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the
+ * knot range) and out[dim][n_obj*n_t] are passed per evaluation.  method:
+ * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects are evaluated in FP32
+ * (no FP64 recomputation: use bz_eval_rational for signed weights).
+ * n_obj*n_t must stay below 2^32.
  */
 typedef struct bz_plan_s *bz_plan;
 int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64_t *cp_offset, const void *ctrl,
                          const void *w, int dtype, int dim, const int64_t *knot_offset, const float *knots,
                          int64_t n_t, int method, bz_stream stream, bz_plan *plan);
 int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
+/*
+ * Autotuner: times the persistent launch on (t, out) for 3 tile sizes (1, 2
+ * or 4 x 256 queries per tile) x 3 grid sizes (0.5, 1, 2 x CUs x occupancy)
+ * and keeps the fastest in the plan.  Synchronises the stream.  best4
+ * (nullable, host): workgroups, tile multiple, microseconds per launch, tiles.
+ */
+int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best4);
 /* Plan statistics: n_classes, n_tiles, n_segments (NURBS), workgroups. */
 int bz_batch_plan_info(bz_plan plan, int64_t *info4);
 int bz_plan_destroy(bz_plan plan);

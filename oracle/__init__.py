@@ -201,8 +201,9 @@ def bezier_adjoint(ctrl, t, gout, w=None, per_object=True):
     return gc, gw, gt
 
 
-def fit_loss_grad(ctrl, t, y):
-    """L2 fitting loss (mean over samples of squared distance) and its gradients."""
+def fit_loss_grad(ctrl, t, y, m_total=None):
+    """L2 fitting loss (sum of squared distances over M, M = number of samples
+    unless m_total is given) and its gradients."""
     ctrl = _d(ctrl)
     n, dim, dp1 = ctrl.shape
     t, y = _d(t), _d(y)
@@ -210,7 +211,7 @@ def fit_loss_grad(ctrl, t, y):
     gc = np.empty_like(ctrl)
     gt = np.empty((n, nt))
     L = lib().bzo_fit_loss_grad(_ptr(ctrl), _I64(n), ctypes.c_int(dp1 - 1), ctypes.c_int(dim), _ptr(t), _I64(nt),
-                                _ptr(y), _ptr(gc), _ptr(gt))
+                                _ptr(y), ctypes.c_double(m_total or 0.0), _ptr(gc), _ptr(gt))
     return L, gc, gt
 
 
@@ -224,11 +225,10 @@ def adam(p, m, v, g, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, lo=1.0, hi=0.0):
                    ctypes.c_double(hi))
 
 
-def fit_reference(gt_ctrl, tau, eps, steps, lr=1e-2):
-    """The whole fitting experiment in FP64: targets y = G(tau) + eps, start
-    from t_j = j/(n_t-1) and the straight line from y_0 to y_{n_t-1} (control
-    point i at i/d), then `steps` Adam steps on control points and t (t
-    clamped to [0,1]).  Returns (ctrl, t, losses)."""
+def fit_init(gt_ctrl, tau, eps):
+    """Targets y = G(tau) + eps and the starting point of the fit: t_j =
+    j/(n_t-1) and the straight line from y_0 to y_{n_t-1} (control point i at
+    i/d).  Returns (y, ctrl0, t0) in float64."""
     n, dim, dp1 = gt_ctrl.shape
     deg = dp1 - 1
     nt = tau.shape[1]
@@ -236,15 +236,29 @@ def fit_reference(gt_ctrl, tau, eps, steps, lr=1e-2):
     y3 = y.reshape(dim, n, nt)
     first, last = y3[:, :, 0].T, y3[:, :, -1].T
     frac = np.arange(dp1) / deg
-    ctrl = first[:, :, None] * (1.0 - frac) + last[:, :, None] * frac
-    ctrl = np.ascontiguousarray(ctrl)
+    ctrl = np.ascontiguousarray(first[:, :, None] * (1.0 - frac) + last[:, :, None] * frac)
     t = np.ascontiguousarray(np.tile(np.arange(nt) / (nt - 1), (n, 1)))
+    return y, ctrl, t
+
+
+def fit_steps(y, ctrl, t, steps, lr=1e-2, m_total=None, first_step=1):
+    """Adam steps on (ctrl, t) in place (t clamped to [0,1]); returns losses."""
     mc, vc = np.zeros_like(ctrl), np.zeros_like(ctrl)
     mt, vt = np.zeros_like(t), np.zeros_like(t)
     losses = []
-    for s in range(1, steps + 1):
-        L, gc, gtt = fit_loss_grad(ctrl, t, y)
+    for s in range(first_step, first_step + steps):
+        L, gc, gtt = fit_loss_grad(ctrl, t, y, m_total)
         losses.append(L)
         adam(ctrl, mc, vc, gc, s, lr)
         adam(t, mt, vt, gtt, s, lr, lo=0.0, hi=1.0)
+    return losses
+
+
+def fit_reference(gt_ctrl, tau, eps, steps, lr=1e-2):
+    """The whole fitting experiment in FP64: targets y = G(tau) + eps, start
+    from t_j = j/(n_t-1) and the straight line from y_0 to y_{n_t-1} (control
+    point i at i/d), then `steps` Adam steps on control points and t (t
+    clamped to [0,1]).  Returns (ctrl, t, losses)."""
+    y, ctrl, t = fit_init(gt_ctrl, tau, eps)
+    losses = fit_steps(y, ctrl, t, steps, lr)
     return ctrl, t, losses

@@ -475,12 +475,14 @@ void bzo_bezier_adjoint(const double *ctrl, const double *w, int64_t n, int deg,
 }
 
 /* Least-squares fit of integral curves to targets y[dim][n*nt]:
- *   L = (1/M) sum_q |C(t_q) - y_q|^2, M = n*nt.
+ *   L = (1/M) sum_q |C(t_q) - y_q|^2, M = m_total (n*nt when m_total <= 0;
+ *   a larger M lets a subset of curves reproduce a bigger problem's scale).
  * Returns L and writes dL/dctrl[n][dim][deg+1] and dL/dt[n][nt].           */
 double bzo_fit_loss_grad(const double *ctrl, int64_t n, int deg, int dim, const double *t, int64_t nt,
-                         const double *y, double *gctrl, double *gt)
+                         const double *y, double m_total, double *gctrl, double *gt)
 {
     const int64_t nq = n * nt;
+    const double M = m_total > 0.0 ? m_total : (double)nq;
     double *C = (double *)malloc(sizeof(double) * (size_t)(nq * dim));
     double *g = (double *)malloc(sizeof(double) * (size_t)(nq * dim));
     bzo_bezier_decasteljau(ctrl, n, deg, dim, t, nt, 1, C);
@@ -488,12 +490,12 @@ double bzo_fit_loss_grad(const double *ctrl, int64_t n, int deg, int dim, const 
     for (int64_t i = 0; i < nq * dim; ++i) {
         const double r = C[i] - y[i];
         L += r * r;
-        g[i] = 2.0 * r / (double)nq;
+        g[i] = 2.0 * r / M;
     }
     bzo_bezier_adjoint(ctrl, 0, n, deg, dim, t, nt, 1, g, gctrl, 0, gt);
     free(C);
     free(g);
-    return L / (double)nq;
+    return L / M;
 }
 
 /* Adam (Kingma & Ba 2015) with bias correction, step counted from 1;

@@ -50,9 +50,13 @@ _SIGS = {
     "bz_eval_rational": (_I, [_P, _P, _I, _I64, _I, _I, _P, _I64, _I, _I, _F, _P, _P, _P]),
     "bz_encode_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
+    "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
+    "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
     "bz_eval_tensor_patch": (_I, [_P, _I, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
     "bz_batch_plan_create": (_I, [_I64, _P, _P, _P, _P, _I, _I, _P, _P, _I64, _I, _P, ctypes.POINTER(_P)]),
     "bz_batch_eval": (_I, [_P, _P, _P, _P]),
+    "bz_batch_plan_autotune": (_I, [_P, _P, _P, _P, _P]),
     "bz_batch_plan_info": (_I, [_P, _P]),
     "bz_plan_destroy": (_I, [_P]),
     "bz_adjoint_bezier": (_I, [_P, _P, _I64, _I, _I, _P, _I64, _I, _P, _P, _P, _P, _P]),
@@ -187,6 +191,25 @@ def eval_piecewise(grid, T, out=None):
     return out
 
 
+def tile_piecewise(grid, out=None):
+    """Zig-zag grid[N+1, 2, dim] -> cache-line tiles (flat float32, 128-byte aligned)."""
+    nseg = grid.shape[0] - 1
+    dim = grid.shape[2]
+    n = lib().bz_piecewise_tiled_floats(nseg, dim)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=grid.device)
+    assert out.numel() == n and out.data_ptr() % 128 == 0
+    check(lib().bz_tile_piecewise(_ptr(grid), nseg, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_tiled(tiles, n_seg, dim, T, out=None):
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), tiles.device, out)
+    check(lib().bz_eval_piecewise_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
+    return out
+
+
 # ---------------------------------------------------------------- tensor
 def eval_tensor_patch(ctrl, du, dv, dw=0, uvw=None, nu=0, nv=0, engine="valu", out=None):
     n, dim, _ = ctrl.shape
@@ -219,6 +242,11 @@ class BatchPlan:
         buf = (ctypes.c_int64 * 4)()
         check(lib().bz_batch_plan_info(self._h, ctypes.cast(buf, _P)))
         return {"n_classes": buf[0], "n_tiles": buf[1], "n_segments": buf[2], "workgroups": buf[3]}
+
+    def autotune(self, t, out):
+        buf = (ctypes.c_int64 * 4)()
+        check(lib().bz_batch_plan_autotune(self._h, _ptr(t), _ptr(out), _stream(), ctypes.cast(buf, _P)))
+        return {"workgroups": buf[0], "tile_multiple": buf[1], "us_per_launch": buf[2], "n_tiles": buf[3]}
 
     def __call__(self, t, out=None):
         assert t.shape == (self.n_obj, self.n_t)

@@ -1,0 +1,400 @@
+// Adjoint of curve evaluation and a fused least-squares fitting step (loss,
+// gradients through the hodograph, Adam) for gfx950.
+//
+// One wavefront per curve: the 64 lanes walk the curve's n_t parameters, each
+// lane accumulating its share of dL/db (and dL/dw) in registers; a butterfly
+// of cross-lane shuffles then sums the partials, so the per-curve reduction is
+// deterministic and needs no atomics.  dL/dt is per query and is written by
+// the lane that owns the query.
+#include <cmath>
+
+#include "curves_impl.h"
+
+namespace bzi {
+namespace {
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+struct AdjArgs {
+    const float *ctrl;
+    const float *w;
+    const float *t;
+    const float *gout;
+    float *gctrl;
+    float *gw;
+    float *gt;
+    int64_t n_curves;
+    int64_t n_t;
+    int64_t plane;
+    int per_object;
+};
+
+// Per query: value C, derivative C' (hodograph), and the basis B.
+template <int D, int DIM, bool RAT>
+__device__ __forceinline__ void curve_and_derivative(const float (&b)[DIM][D + 1], const float (&wv)[D + 1], float t,
+                                                     float (&B)[D + 1], float &W, float (&C)[DIM], float (&dC)[DIM]) {
+    bernstein_basis<D>(t, B);
+    float Bm[D];
+    bernstein_basis<D - 1>(t, Bm);
+    if constexpr (!RAT) {
+        W = 1.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            C[k] = dot_basis<D>(B, b[k]);
+            float d = 0.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) d = __builtin_fmaf(b[k][i + 1] - b[k][i], Bm[i], d);
+            dC[k] = static_cast<float>(D) * d;
+        }
+    } else {
+        float wB[D + 1];
+        W = 0.0f;
+        float Wp = 0.0f;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            wB[i] = wv[i] * B[i];
+            W += wB[i];
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) Wp = __builtin_fmaf(wv[i + 1] - wv[i], Bm[i], Wp);
+        Wp *= static_cast<float>(D);
+        const float iW = 1.0f / W;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float H = dot_basis<D>(wB, b[k]);
+            float Hp = 0.0f;
+#pragma unroll
+            for (int i = 0; i < D; ++i) Hp = __builtin_fmaf(wv[i + 1] * b[k][i + 1] - wv[i] * b[k][i], Bm[i], Hp);
+            Hp *= static_cast<float>(D);
+            C[k] = H * iW;
+            dC[k] = (Hp - C[k] * Wp) * iW;
+        }
+    }
+}
+
+template <int D, int DIM, bool RAT>
+__global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    if (c >= a.n_curves) return;
+    float b[DIM][D + 1], wv[D + 1];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i <= D; ++i) b[k][i] = a.ctrl[(c * DIM + k) * (D + 1) + i];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) wv[i] = RAT ? a.w[c * (D + 1) + i] : 1.0f;
+    float gb[DIM][D + 1] = {}, gwv[D + 1] = {};
+    for (int64_t j = lane; j < a.n_t; j += 64) {
+        const int64_t q = c * a.n_t + j;
+        const float t = a.per_object ? a.t[q] : a.t[j];
+        float B[D + 1], W, C[DIM], dC[DIM], g[DIM];
+        curve_and_derivative<D, DIM, RAT>(b, wv, t, B, W, C, dC);
+        float dt = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            g[k] = a.gout[k * a.plane + q];
+            dt = __builtin_fmaf(g[k], dC[k], dt);
+        }
+        if (a.gt) a.gt[q] = dt;
+        const float iW = RAT ? 1.0f / W : 1.0f;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            const float s = RAT ? wv[i] * B[i] * iW : B[i];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) gb[k][i] = __builtin_fmaf(g[k], s, gb[k][i]);
+            if constexpr (RAT) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) acc = __builtin_fmaf(g[k], b[k][i] - C[k], acc);
+                gwv[i] = __builtin_fmaf(B[i] * iW, acc, gwv[i]);
+            }
+        }
+    }
+    if (a.gctrl) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                const float v = wave_sum(gb[k][i]);
+                if (lane == 0) a.gctrl[(c * DIM + k) * (D + 1) + i] = v;
+            }
+    }
+    if (RAT && a.gw) {
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            const float v = wave_sum(gwv[i]);
+            if (lane == 0) a.gw[c * (D + 1) + i] = v;
+        }
+    }
+}
+
+struct FitArgs {
+    float *ctrl, *t;
+    const float *y;
+    float *m_c, *v_c, *m_t, *v_t;
+    float *loss_part;
+    int64_t n_curves, n_t, plane;
+    float inv_m;        // 1 / (n_curves * n_t)
+    float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+};
+
+__device__ __forceinline__ float adam(float p, float g, float *m, float *v, const FitArgs &a) {
+    const float mm = __builtin_fmaf(a.b1, *m, (1.0f - a.b1) * g);
+    const float vv = __builtin_fmaf(a.b2, *v, (1.0f - a.b2) * g * g);
+    *m = mm;
+    *v = vv;
+    const float mh = mm / a.c1, vh = vv / a.c2;
+    return p - a.lr * mh / (__builtin_sqrtf(vh) + a.eps);
+}
+
+// Fused step: L = (1/M) sum |C(t) - y|^2, gradients, Adam on t (clamped to
+// [0,1]) and on the control points.  All gradients use the parameters as they
+// were at the start of the step.
+template <int D, int DIM>
+__global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    if (c >= a.n_curves) return;
+    constexpr int NP = DIM * (D + 1);
+    float b[DIM][D + 1], wv[D + 1] = {};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i <= D; ++i) b[k][i] = a.ctrl[c * NP + k * (D + 1) + i];
+    float gb[DIM][D + 1] = {};
+    float loss = 0.0f;
+    for (int64_t j = lane; j < a.n_t; j += 64) {
+        const int64_t q = c * a.n_t + j;
+        const float t = a.t[q];
+        float B[D + 1], W, C[DIM], dC[DIM];
+        curve_and_derivative<D, DIM, false>(b, wv, t, B, W, C, dC);
+        float dt = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float r = C[k] - a.y[k * a.plane + q];
+            loss = __builtin_fmaf(r, r, loss);
+            const float g = 2.0f * r * a.inv_m;
+            dt = __builtin_fmaf(g, dC[k], dt);
+#pragma unroll
+            for (int i = 0; i <= D; ++i) gb[k][i] = __builtin_fmaf(g, B[i], gb[k][i]);
+        }
+        float mt = a.m_t[q], vt = a.v_t[q];
+        float tn = adam(t, dt, &mt, &vt, a);
+        tn = tn < 0.0f ? 0.0f : (tn > 1.0f ? 1.0f : tn);
+        a.t[q] = tn;
+        a.m_t[q] = mt;
+        a.v_t[q] = vt;
+    }
+    loss = wave_sum(loss);
+    if (a.loss_part && lane == 0) a.loss_part[c] = loss * a.inv_m;
+    // lane p updates control-point parameter p (NP <= 64)
+    float mine = 0.0f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            const float v = wave_sum(gb[k][i]);
+            if (lane == k * (D + 1) + i) mine = v;
+        }
+    if (lane < NP) {
+        const int64_t idx = c * NP + lane;
+        float m = a.m_c[idx], v = a.v_c[idx];
+        const float pn = adam(a.ctrl[idx], mine, &m, &v, a);
+        a.ctrl[idx] = pn;
+        a.m_c[idx] = m;
+        a.v_c[idx] = v;
+    }
+}
+
+template <int D, bool RAT>
+int launch_adj_d(int dim, const AdjArgs &a, hipStream_t s, uint32_t blocks) {
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_adjoint<D, 1, RAT>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_adjoint<D, 2, RAT>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_adjoint<D, 3, RAT>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_adjoint<D, 4, RAT>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
+    BZ_CHECK_LAUNCH("k_adjoint");
+    return BZ_OK;
+}
+
+template <bool RAT>
+int launch_adj(int degree, int dim, const AdjArgs &a, hipStream_t s, uint32_t blocks) {
+    switch (degree) {
+        case 1: return launch_adj_d<1, RAT>(dim, a, s, blocks);
+        case 2: return launch_adj_d<2, RAT>(dim, a, s, blocks);
+        case 3: return launch_adj_d<3, RAT>(dim, a, s, blocks);
+        case 4: return launch_adj_d<4, RAT>(dim, a, s, blocks);
+        case 5: return launch_adj_d<5, RAT>(dim, a, s, blocks);
+        case 6: return launch_adj_d<6, RAT>(dim, a, s, blocks);
+        case 7: return launch_adj_d<7, RAT>(dim, a, s, blocks);
+        case 8: return launch_adj_d<8, RAT>(dim, a, s, blocks);
+        case 9: return launch_adj_d<9, RAT>(dim, a, s, blocks);
+        case 10: return launch_adj_d<10, RAT>(dim, a, s, blocks);
+        case 11: return launch_adj_d<11, RAT>(dim, a, s, blocks);
+        case 12: return launch_adj_d<12, RAT>(dim, a, s, blocks);
+        case 13: return launch_adj_d<13, RAT>(dim, a, s, blocks);
+        case 14: return launch_adj_d<14, RAT>(dim, a, s, blocks);
+        default: return launch_adj_d<15, RAT>(dim, a, s, blocks);
+    }
+}
+
+template <int D>
+int launch_fit_d(int dim, const FitArgs &a, hipStream_t s, uint32_t blocks) {
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_fit_step<D, 1>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_fit_step<D, 2>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_fit_step<D, 3>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_fit_step<D, 4>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
+    BZ_CHECK_LAUNCH("k_fit_step");
+    return BZ_OK;
+}
+
+int launch_fit(int degree, int dim, const FitArgs &a, hipStream_t s) {
+    const uint32_t blocks = static_cast<uint32_t>((a.n_curves + 3) / 4);
+    switch (degree) {
+        case 1: return launch_fit_d<1>(dim, a, s, blocks);
+        case 2: return launch_fit_d<2>(dim, a, s, blocks);
+        case 3: return launch_fit_d<3>(dim, a, s, blocks);
+        case 4: return launch_fit_d<4>(dim, a, s, blocks);
+        case 5: return launch_fit_d<5>(dim, a, s, blocks);
+        case 6: return launch_fit_d<6>(dim, a, s, blocks);
+        case 7: return launch_fit_d<7>(dim, a, s, blocks);
+        case 8: return launch_fit_d<8>(dim, a, s, blocks);
+        case 9: return launch_fit_d<9>(dim, a, s, blocks);
+        case 10: return launch_fit_d<10>(dim, a, s, blocks);
+        case 11: return launch_fit_d<11>(dim, a, s, blocks);
+        case 12: return launch_fit_d<12>(dim, a, s, blocks);
+        case 13: return launch_fit_d<13>(dim, a, s, blocks);
+        case 14: return launch_fit_d<14>(dim, a, s, blocks);
+        default: return launch_fit_d<15>(dim, a, s, blocks);
+    }
+}
+
+int check_fit(const char *fn, float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
+              float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, float lr, float beta1, float beta2, float eps) {
+    if (degree < 1 || degree > kMaxDegree || dim < 1 || dim > kMaxDim)
+        return fail(BZ_ERR_SHAPE, "%s: degree %d / dim %d out of range", fn, degree, dim);
+    if (n_curves < 0 || n_t < 0 || n_t > 1024) return fail(BZ_ERR_SHAPE, "%s: need 0 <= n_t <= 1024", fn);
+    if (n_curves > (int64_t(1) << 31) - 1) return fail(BZ_ERR_SHAPE, "%s: too many curves", fn);
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return fail(BZ_ERR_SHAPE, "%s: bad Adam hyper-parameters", fn);
+    if (n_curves == 0 || n_t == 0) return BZ_OK;
+    if (!ctrl || !t || !y || !m_ctrl || !v_ctrl || !m_t || !v_t) return fail(BZ_ERR_NULL, "%s: missing array", fn);
+    return BZ_OK;
+}
+
+FitArgs make_fit_args(float *ctrl, float *t, const float *y, int64_t n_curves, int64_t n_t, float *m_ctrl,
+                      float *v_ctrl, float *m_t, float *v_t, int step, float lr, float beta1, float beta2, float eps,
+                      float *loss_part) {
+    FitArgs a;
+    a.ctrl = ctrl;
+    a.t = t;
+    a.y = y;
+    a.m_c = m_ctrl;
+    a.v_c = v_ctrl;
+    a.m_t = m_t;
+    a.v_t = v_t;
+    a.loss_part = loss_part;
+    a.n_curves = n_curves;
+    a.n_t = n_t;
+    a.plane = n_curves * n_t;
+    a.inv_m = static_cast<float>(1.0 / static_cast<double>(n_curves * n_t));
+    a.lr = lr;
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
+    a.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+    return a;
+}
+
+}  // namespace
+}  // namespace bzi
+
+using namespace bzi;
+
+extern "C" {
+
+int bz_adjoint_bezier(const float *ctrl, const float *w, int64_t n_curves, int degree, int dim, const float *t,
+                      int64_t n_t, int t_mode, const float *grad_out, float *grad_ctrl, float *grad_w, float *grad_t,
+                      bz_stream stream) {
+    return guarded("bz_adjoint_bezier", [&]() -> int {
+        const char *fn = "bz_adjoint_bezier";
+        if (degree < 1 || degree > kMaxDegree || dim < 1 || dim > kMaxDim)
+            return fail(BZ_ERR_SHAPE, "%s: degree %d / dim %d out of range", fn, degree, dim);
+        if (n_curves < 0 || n_t < 0) return fail(BZ_ERR_SHAPE, "%s: negative count", fn);
+        if (t_mode != BZ_T_SHARED && t_mode != BZ_T_PER_OBJECT) return fail(BZ_ERR_SHAPE, "%s: bad t_mode", fn);
+        if (grad_t && t_mode != BZ_T_PER_OBJECT) return fail(BZ_ERR_UNSUPPORTED, "%s: grad_t needs per-object t", fn);
+        if (grad_w && !w) return fail(BZ_ERR_NULL, "%s: grad_w needs w", fn);
+        if (n_curves > (int64_t(1) << 31) - 1) return fail(BZ_ERR_SHAPE, "%s: too many curves", fn);
+        if (n_curves == 0 || n_t == 0) return BZ_OK;
+        if (!ctrl || !t || !grad_out) return fail(BZ_ERR_NULL, "%s: ctrl, t and grad_out are required", fn);
+        AdjArgs a{ctrl, w, t, grad_out, grad_ctrl, grad_w, grad_t, n_curves, n_t, n_curves * n_t,
+                  t_mode == BZ_T_PER_OBJECT};
+        const uint32_t blocks = static_cast<uint32_t>((n_curves + 3) / 4);
+        const hipStream_t s = as_stream(stream);
+        return w ? launch_adj<true>(degree, dim, a, s, blocks) : launch_adj<false>(degree, dim, a, s, blocks);
+    });
+}
+
+int bz_fit_adam_step(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
+                     float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int step, float lr, float beta1, float beta2,
+                     float eps, float *loss_part, bz_stream stream) {
+    return guarded("bz_fit_adam_step", [&]() -> int {
+        int rc = check_fit("bz_fit_adam_step", ctrl, t, y, n_curves, degree, dim, n_t, m_ctrl, v_ctrl, m_t, v_t, lr,
+                           beta1, beta2, eps);
+        if (rc || n_curves == 0 || n_t == 0) return rc;
+        if (step < 1) return fail(BZ_ERR_SHAPE, "bz_fit_adam_step: step counts from 1");
+        const FitArgs a = make_fit_args(ctrl, t, y, n_curves, n_t, m_ctrl, v_ctrl, m_t, v_t, step, lr, beta1, beta2,
+                                        eps, loss_part);
+        return launch_fit(degree, dim, a, as_stream(stream));
+    });
+}
+
+int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
+                    float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int first_step, int n_steps, float lr,
+                    float beta1, float beta2, float eps, float *loss_part, bz_stream stream) {
+    return guarded("bz_fit_adam_run", [&]() -> int {
+        const char *fn = "bz_fit_adam_run";
+        int rc = check_fit(fn, ctrl, t, y, n_curves, degree, dim, n_t, m_ctrl, v_ctrl, m_t, v_t, lr, beta1, beta2, eps);
+        if (rc || n_curves == 0 || n_t == 0 || n_steps == 0) return rc;
+        if (first_step < 1 || n_steps < 0) return fail(BZ_ERR_SHAPE, "%s: steps count from 1", fn);
+        const hipStream_t s = as_stream(stream);
+        // capture the steps on a private stream that follows `stream`
+        hipStream_t cap;
+        BZ_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < n_steps && rc == BZ_OK; ++i) {
+                const FitArgs a = make_fit_args(ctrl, t, y, n_curves, n_t, m_ctrl, v_ctrl, m_t, v_t, first_step + i,
+                                                lr, beta1, beta2, eps, loss_part);
+                rc = launch_fit(degree, dim, a, cap);
+            }
+            const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+            if (rc == BZ_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
+        } else {
+            rc = hip_fail(e, "begin capture");
+        }
+        if (rc == BZ_OK) {
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) rc = hip_fail(e, "graph launch");
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        return rc;
+    });
+}
+
+}  // extern "C"

@@ -158,6 +158,100 @@ __global__ __launch_bounds__(kBlock) void k_piecewise_eval(const float *__restri
     }
 }
 
+// ------------------------------------------------------------------ tiled
+// Cache-line tiling of the zig-zag grid: 128-byte tiles of C = 128/(8*dim)
+// consecutive columns, consecutive tiles overlapping by one column, so tile j
+// holds the S = C-1 segments [jS, jS+S) and every segment's 2x2 window lies in
+// one 128-byte line (as a texture is stored in cache-line tiles).  The texels
+// are those of the zig-zag grid; only their placement differs.
+template <int DIM>
+struct TileGeom {
+    static constexpr int C = 128 / (8 * DIM);  // columns per tile
+    static constexpr int S = C - 1;            // segments per tile
+};
+
+__global__ __launch_bounds__(kBlock) void k_tile_grid(const float *__restrict__ grid, int64_t n_seg, int dim, int cols,
+                                                      int segs, int64_t n_tiles, float *__restrict__ tiles) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n_tiles * 32) return;
+    const int64_t j = i >> 5;
+    const int f = static_cast<int>(i & 31);
+    const int c = f / (2 * dim), within = f - c * 2 * dim;
+    const int64_t col = j * segs + c;
+    tiles[i] = (c < cols && col <= n_seg) ? grid[col * 2 * dim + within] : 0.0f;
+}
+
+template <int DIM, int QPT>
+__global__ __launch_bounds__(kBlock) void k_piecewise_eval_tiled(const float *__restrict__ tiles, uint32_t n_seg,
+                                                                 const float *__restrict__ T, uint32_t nq,
+                                                                 float *__restrict__ out, int64_t plane) {
+    constexpr int S = TileGeom<DIM>::S;
+    const uint32_t base = blockIdx.x * (kBlock * QPT) + threadIdx.x;
+    const float nf = static_cast<float>(n_seg);
+    const float nm1 = static_cast<float>(n_seg - 1);
+    float tl[QPT];
+    uint32_t kk[QPT];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+        const float Tq = ld_stream(T + q);
+        float Tc = Tq < 0.0f ? 0.0f : Tq;
+        Tc = Tc > nf ? nf : Tc;
+        const float kf = __builtin_fminf(__builtin_floorf(Tc), nm1);
+        const uint32_t k = min(static_cast<uint32_t>(kf), n_seg - 1);
+        kk[i] = k;
+        tl[i] = Tc - static_cast<float>(k);
+    }
+    float2 g[QPT][2 * DIM];
+    const float2 *__restrict__ g2 = reinterpret_cast<const float2 *>(tiles);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t j = kk[i] / S, r = kk[i] - j * S;
+        const size_t off = static_cast<size_t>(j) * 16 + r * DIM;  // in float2 units
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) g[i][e] = g2[off + e];
+    }
+    float v[QPT][DIM];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        float f[4 * DIM];
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) {
+            f[2 * e] = g[i][e].x;
+            f[2 * e + 1] = g[i][e].y;
+        }
+        const bool odd = kk[i] & 1;
+        const float t = tl[i];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const float c0r0 = f[c], c0r1 = f[DIM + c], c1r0 = f[2 * DIM + c], c1r1 = f[3 * DIM + c];
+            const float A = odd ? c0r1 : c0r0, xk = odd ? c0r0 : c0r1;
+            const float xk1 = odd ? c1r1 : c1r0, A1 = odd ? c1r0 : c1r1;
+            v[i][c] = lerp(lerp(A, xk1, t), lerp(xk, A1, t), t);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) st_stream(out + c * plane + q, v[i][c]);
+    }
+}
+
+template <int DIM>
+int launch_eval_tiled(const float *tiles, uint32_t n_seg, const float *T, uint32_t nq, float *out, int64_t plane,
+                      hipStream_t s) {
+    constexpr int Q = 4;
+    const uint32_t per_block = kBlock * Q;
+    const uint32_t blocks = (nq + per_block - 1) / per_block;
+    hipLaunchKernelGGL((k_piecewise_eval_tiled<DIM, Q>), dim3(blocks), dim3(kBlock), 0, s, tiles, n_seg, T, nq, out,
+                       plane);
+    BZ_CHECK_LAUNCH("k_piecewise_eval_tiled");
+    return BZ_OK;
+}
+
+int tile_segs(int dim) { return 128 / (8 * dim) - 1; }
+
 // Queries per thread; BZ_PIECEWISE_QPT (1, 2, 4 or 8) overrides the default.
 int piecewise_qpt() {
     static const int q = [] {
@@ -241,6 +335,59 @@ int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T,
                 case 2: rc = launch_eval<2>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
                 case 3: rc = launch_eval<3>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
                 default: rc = launch_eval<4>(grid, ns, T + q0, nq, out + q0, n_q, s); break;
+            }
+            if (rc) return rc;
+        }
+        return BZ_OK;
+    });
+}
+
+int64_t bz_piecewise_tiled_floats(int64_t n_seg, int dim) {
+    if (dim < 1 || dim > kMaxDim || n_seg < 1) return 0;
+    const int64_t S = tile_segs(dim);
+    return (n_seg + S - 1) / S * 32;
+}
+
+int bz_tile_piecewise(const float *grid, int64_t n_seg, int dim, float *tiles, bz_stream stream) {
+    return guarded("bz_tile_piecewise", [&]() -> int {
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "bz_tile_piecewise: dim %d", dim);
+        if (n_seg < 0 || n_seg > (int64_t(1) << 31)) return fail(BZ_ERR_SHAPE, "bz_tile_piecewise: n_seg");
+        if (n_seg == 0) return BZ_OK;
+        if (!grid || !tiles) return fail(BZ_ERR_NULL, "bz_tile_piecewise: grid and tiles are required");
+        if (!aligned(grid, 4) || !aligned(tiles, 128)) return fail(BZ_ERR_ALIGN, "bz_tile_piecewise: tiles need 128-byte alignment");
+        const int S = tile_segs(dim);
+        const int64_t n_tiles = (n_seg + S - 1) / S;
+        const int64_t n = n_tiles * 32;
+        const uint32_t blocks = static_cast<uint32_t>((n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_tile_grid, dim3(blocks), dim3(kBlock), 0, as_stream(stream), grid, n_seg, dim, S + 1, S,
+                           n_tiles, tiles);
+        BZ_CHECK_LAUNCH("k_tile_grid");
+        return BZ_OK;
+    });
+}
+
+int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                            bz_stream stream) {
+    return guarded("bz_eval_piecewise_tiled", [&]() -> int {
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "bz_eval_piecewise_tiled: dim %d", dim);
+        if (n_q < 0) return fail(BZ_ERR_SHAPE, "bz_eval_piecewise_tiled: n_q");
+        if (n_seg < 1 || n_seg > (int64_t(1) << 31))
+            return fail(BZ_ERR_SHAPE, "bz_eval_piecewise_tiled: n_seg %lld not in 1..2^31", (long long)n_seg);
+        if (n_q == 0) return BZ_OK;
+        if (!tiles || !T || !out) return fail(BZ_ERR_NULL, "bz_eval_piecewise_tiled: tiles, T and out are required");
+        if (!aligned(tiles, 128) || !aligned(T, 4) || !aligned(out, 4))
+            return fail(BZ_ERR_ALIGN, "bz_eval_piecewise_tiled: tiles need 128-byte, T and out 4-byte alignment");
+        const hipStream_t s = as_stream(stream);
+        const int64_t per = int64_t(1) << 30;
+        for (int64_t q0 = 0; q0 < n_q; q0 += per) {
+            const uint32_t nq = static_cast<uint32_t>(std::min(per, n_q - q0));
+            const uint32_t ns = static_cast<uint32_t>(n_seg);
+            int rc;
+            switch (dim) {
+                case 1: rc = launch_eval_tiled<1>(tiles, ns, T + q0, nq, out + q0, n_q, s); break;
+                case 2: rc = launch_eval_tiled<2>(tiles, ns, T + q0, nq, out + q0, n_q, s); break;
+                case 3: rc = launch_eval_tiled<3>(tiles, ns, T + q0, nq, out + q0, n_q, s); break;
+                default: rc = launch_eval_tiled<4>(tiles, ns, T + q0, nq, out + q0, n_q, s); break;
             }
             if (rc) return rc;
         }

@@ -1,0 +1,373 @@
+// Tensor-product Bezier surfaces and volumes (Sec. 2.2: the order splits
+// over the parameter axes) for gfx950.
+//
+//  k_tensor_grid   one patch per workgroup, nu x nv uniform grid.  When the
+//                  block size is a multiple of nv every thread keeps one grid
+//                  column b, contracts the control net with the v basis once
+//                  (isoline control points R_i(v_b)) and then needs only the
+//                  u basis and du+1 FMAs per coordinate for each of its points.
+//  k_tensor_points one object per workgroup, random (u,v[,w]) per query,
+//                  separable contraction w -> v -> u.
+//  k_tensor_mfma   bicubic 32x32 grids as a dense contraction on the matrix
+//                  cores: D[(patch,coord)][grid pt] = P[(patch,coord)][16] x
+//                  K[16][grid pt] with K the Kronecker product of the u and v
+//                  Bernstein bases, one 32x32 output tile per MFMA group.
+#include "curves_impl.h"
+
+namespace bzi {
+namespace {
+
+template <int D>
+__device__ __forceinline__ void basis_at(float x, float (&B)[D + 1]) {
+    bernstein_basis<D>(x, B);
+}
+
+// ------------------------------------------------------------------ VALU grid
+template <int DU, int DV, int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_tensor_grid(const T *__restrict__ ctrl, int nu, int nv,
+                                                        float *__restrict__ out, int64_t plane, int64_t o0) {
+    constexpr int NCP = (DU + 1) * (DV + 1);
+    const uint32_t o = blockIdx.x;
+    const T *__restrict__ P = ctrl + static_cast<size_t>(o) * DIM * NCP;
+    const int npts = nu * nv;
+    float *__restrict__ ob = out + (o0 + o) * static_cast<int64_t>(npts);
+    const float du_den = nu > 1 ? static_cast<float>(nu - 1) : 1.0f;
+    const float dv_den = nv > 1 ? static_cast<float>(nv - 1) : 1.0f;
+    if (kBlock % nv == 0) {
+        const int b = threadIdx.x % nv;
+        const int astep = kBlock / nv;
+        float Bv[DV + 1];
+        basis_at<DV>(static_cast<float>(b) / dv_den, Bv);
+        float R[DIM][DU + 1];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) {
+                float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
+#pragma unroll
+                for (int j = 1; j <= DV; ++j) acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
+                R[c][i] = acc;
+            }
+        for (int a = threadIdx.x / nv; a < nu; a += astep) {
+            float Bu[DU + 1];
+            basis_at<DU>(static_cast<float>(a) / du_den, Bu);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) st_stream(ob + c * plane + a * nv + b, dot_basis<DU>(Bu, R[c]));
+        }
+    } else {
+        for (int p = threadIdx.x; p < npts; p += kBlock) {
+            const int a = p / nv, b = p - (p / nv) * nv;
+            float Bu[DU + 1], Bv[DV + 1];
+            basis_at<DU>(static_cast<float>(a) / du_den, Bu);
+            basis_at<DV>(static_cast<float>(b) / dv_den, Bv);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                float Ri[DU + 1];
+#pragma unroll
+                for (int i = 0; i <= DU; ++i) {
+                    float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
+#pragma unroll
+                    for (int j = 1; j <= DV; ++j)
+                        acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
+                    Ri[i] = acc;
+                }
+                st_stream(ob + c * plane + p, dot_basis<DU>(Bu, Ri));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ VALU points
+template <int DU, int DV, int DW, int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_tensor_points(const T *__restrict__ ctrl, const float *__restrict__ uvw,
+                                                          int64_t n_per, float *__restrict__ out, int64_t plane,
+                                                          int64_t o0) {
+    constexpr int NCP = (DU + 1) * (DV + 1) * (DW + 1);
+    constexpr int NPAR = DW > 0 ? 3 : 2;
+    const uint32_t o = blockIdx.x;
+    const T *__restrict__ P = ctrl + static_cast<size_t>(o) * DIM * NCP;
+    for (int64_t j = threadIdx.x; j < n_per; j += kBlock) {
+        const int64_t q = (o0 + o) * n_per + j;
+        const float *__restrict__ p = uvw + q * NPAR;
+        float Bu[DU + 1], Bv[DV + 1], Bw[DW + 1];
+        basis_at<DU>(p[0], Bu);
+        basis_at<DV>(p[1], Bv);
+        if constexpr (DW > 0) basis_at<DW>(p[2], Bw);
+        else Bw[0] = 1.0f;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            float Ri[DU + 1];
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) {
+                float Qj[DV + 1];
+#pragma unroll
+                for (int jj = 0; jj <= DV; ++jj) {
+                    const int base = c * NCP + (i * (DV + 1) + jj) * (DW + 1);
+                    float acc = Bw[0] * to_f32<T>(P[base]);
+#pragma unroll
+                    for (int k = 1; k <= DW; ++k) acc = __builtin_fmaf(Bw[k], to_f32<T>(P[base + k]), acc);
+                    Qj[jj] = acc;
+                }
+                Ri[i] = dot_basis<DV>(Bv, Qj);
+            }
+            st_stream(out + c * plane + q, dot_basis<DU>(Bu, Ri));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ MFMA grid
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2 };
+
+// Bicubic patches on a 32 x 32 grid.  Rows of the contraction are the
+// (patch, coordinate) pairs, i.e. the control-point array read as
+// [n_obj*dim][16]; each wave owns 32 rows and sweeps the 32 grid rows a,
+// issuing per grid row the MFMA(s) of a 32 x 32 x 16 product and storing the
+// 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
+// Output-tile layout of the 32x32 MFMAs: lane l holds column l%32 and, in
+// accumulator register r, row 8*(r/4) + 4*(l/32) + r%4.
+template <int ENG>
+__global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_rows, FastDiv div_dim,
+                                                        float *__restrict__ out, int64_t plane, int64_t o0) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t row0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 32;
+    if (row0 >= n_rows) return;
+    const int col = lane & 31, kh = lane >> 5;
+    const uint32_t arow = min(row0 + col, n_rows - 1);
+    float A[16];
+    const float4 *__restrict__ a4 = reinterpret_cast<const float4 *>(ctrl + static_cast<size_t>(arow) * 16);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float4 v = a4[e];
+        A[4 * e] = v.x;
+        A[4 * e + 1] = v.y;
+        A[4 * e + 2] = v.z;
+        A[4 * e + 3] = v.w;
+    }
+    float Bv[4];
+    bernstein_basis<3>(static_cast<float>(col) / 31.0f, Bv);
+    // output addresses of this lane's 16 rows (clamped rows are never stored)
+    int64_t obase[16];
+    bool ok[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const uint32_t row = row0 + 8 * (r / 4) + 4 * kh + (r % 4);
+        ok[r] = row < n_rows;
+        const uint32_t o = fdiv(row, div_dim);
+        const uint32_t c = row - o * div_dim.d;
+        obase[r] = c * plane + (o0 + o) * 1024 + col;
+    }
+    v8bf Ab;
+    v8h Ah;
+    if constexpr (ENG == MF_BF16) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Ab[e] = static_cast<__bf16>(A[8 * kh + e]);
+    } else if constexpr (ENG == MF_F16) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Ah[e] = static_cast<_Float16>(A[8 * kh + e]);
+    }
+    for (int a = 0; a < 32; ++a) {
+        float Bu[4];
+        bernstein_basis<3>(static_cast<float>(a) / 31.0f, Bu);
+        v16f acc = {};
+        if constexpr (ENG == MF_F32) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int k = 2 * s + kh;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[k], Bu[k >> 2] * Bv[k & 3], acc, 0, 0, 0);
+            }
+        } else if constexpr (ENG == MF_BF16) {
+            v8bf Bb;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * kh + e;
+                Bb[e] = static_cast<__bf16>(Bu[k >> 2] * Bv[k & 3]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ab, Bb, acc, 0, 0, 0);
+        } else {
+            v8h Bh;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * kh + e;
+                Bh[e] = static_cast<_Float16>(Bu[k >> 2] * Bv[k & 3]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, Bh, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (ok[r]) st_stream(out + obase[r] + a * 32, acc[r]);
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <typename T, int DU, int DV, int DIM>
+void launch_grid3(const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0, uint32_t blocks,
+                  hipStream_t s) {
+    hipLaunchKernelGGL((k_tensor_grid<DU, DV, DIM, T>), dim3(blocks), dim3(kBlock), 0, s,
+                       static_cast<const T *>(ctrl), nu, nv, out, plane, o0);
+}
+
+template <typename T, int DU, int DV>
+int launch_grid2(int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0, uint32_t blocks,
+                 hipStream_t s) {
+    switch (dim) {
+        case 1: launch_grid3<T, DU, DV, 1>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
+        case 2: launch_grid3<T, DU, DV, 2>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
+        case 3: launch_grid3<T, DU, DV, 3>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
+        default: launch_grid3<T, DU, DV, 4>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
+    }
+    return BZ_OK;
+}
+
+template <typename T, int DU>
+int launch_grid1(int dv, int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0,
+                 uint32_t blocks, hipStream_t s) {
+    switch (dv) {
+        case 1: return launch_grid2<T, DU, 1>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        case 2: return launch_grid2<T, DU, 2>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        case 3: return launch_grid2<T, DU, 3>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        default: return launch_grid2<T, DU, 4>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+    }
+}
+
+template <typename T>
+int launch_grid(int du, int dv, int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0,
+                uint32_t blocks, hipStream_t s) {
+    switch (du) {
+        case 1: return launch_grid1<T, 1>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        case 2: return launch_grid1<T, 2>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        case 3: return launch_grid1<T, 3>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+        default: return launch_grid1<T, 4>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
+    }
+}
+
+template <typename T, int DU, int DV, int DW>
+int launch_pts3(int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane, int64_t o0,
+                uint32_t blocks, hipStream_t s) {
+    const T *p = static_cast<const T *>(ctrl);
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 1, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
+        case 2: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 2, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
+        case 3: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 3, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
+        default: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 4, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
+    }
+    return BZ_OK;
+}
+
+template <typename T, int DU, int DV>
+int launch_pts2(int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane,
+                int64_t o0, uint32_t blocks, hipStream_t s) {
+    switch (dw) {
+        case 0: return launch_pts3<T, DU, DV, 0>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 1: return launch_pts3<T, DU, DV, 1>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 2: return launch_pts3<T, DU, DV, 2>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 3: return launch_pts3<T, DU, DV, 3>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        default: return launch_pts3<T, DU, DV, 4>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+    }
+}
+
+template <typename T, int DU>
+int launch_pts1(int dv, int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane,
+                int64_t o0, uint32_t blocks, hipStream_t s) {
+    switch (dv) {
+        case 1: return launch_pts2<T, DU, 1>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 2: return launch_pts2<T, DU, 2>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 3: return launch_pts2<T, DU, 3>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        default: return launch_pts2<T, DU, 4>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+    }
+}
+
+template <typename T>
+int launch_pts(int du, int dv, int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out,
+               int64_t plane, int64_t o0, uint32_t blocks, hipStream_t s) {
+    switch (du) {
+        case 1: return launch_pts1<T, 1>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 2: return launch_pts1<T, 2>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        case 3: return launch_pts1<T, 3>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+        default: return launch_pts1<T, 4>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
+    }
+}
+
+}  // namespace
+}  // namespace bzi
+
+using namespace bzi;
+
+extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, int du, int dv, int dw, int dim,
+                                    const float *uvw, int64_t n_per, int nu, int nv, int engine, float *out,
+                                    bz_stream stream) {
+    return guarded("bz_eval_tensor_patch", [&]() -> int {
+        const char *fn = "bz_eval_tensor_patch";
+        if (du < 1 || du > 4 || dv < 1 || dv > 4 || dw < 0 || dw > 4)
+            return fail(BZ_ERR_SHAPE, "%s: degrees (%d,%d,%d) outside 1..4 (dw 0..4)", fn, du, dv, dw);
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_obj < 0) return fail(BZ_ERR_SHAPE, "%s: n_obj %lld", fn, (long long)n_obj);
+        const int es = dtype_size(dtype);
+        if (es == 0) return fail(BZ_ERR_DTYPE, "%s: dtype %d", fn, dtype);
+        if (engine < BZ_TP_VALU || engine > BZ_TP_MFMA_F16) return fail(BZ_ERR_UNSUPPORTED, "%s: engine %d", fn, engine);
+        const int ncp = (du + 1) * (dv + 1) * (dw + 1);
+        const hipStream_t s = as_stream(stream);
+        if (uvw == nullptr) {  // grid mode
+            if (dw != 0) return fail(BZ_ERR_UNSUPPORTED, "%s: grid mode is for surfaces (dw = 0)", fn);
+            if (nu < 1 || nv < 1 || static_cast<int64_t>(nu) * nv > (1 << 24))
+                return fail(BZ_ERR_SHAPE, "%s: grid %d x %d", fn, nu, nv);
+            if (engine != BZ_TP_VALU && (du != 3 || dv != 3 || nu != 32 || nv != 32 || dtype != BZ_F32))
+                return fail(BZ_ERR_UNSUPPORTED, "%s: MFMA engines need bicubic FP32 patches on a 32x32 grid", fn);
+            if (n_obj == 0) return BZ_OK;
+            if (!ctrl || !out) return fail(BZ_ERR_NULL, "%s: ctrl and out are required", fn);
+            if (!aligned(ctrl, engine == BZ_TP_VALU ? es : 16) || !aligned(out, 4))
+                return fail(BZ_ERR_ALIGN, "%s: misaligned pointer (MFMA engines read ctrl as 16-byte rows)", fn);
+            const int64_t npts = static_cast<int64_t>(nu) * nv;
+            const int64_t plane = n_obj * npts;
+            if (engine == BZ_TP_VALU) {
+                const int64_t per = int64_t(1) << 22;
+                for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
+                    const uint32_t blocks = static_cast<uint32_t>(std::min(per, n_obj - o0));
+                    const char *c0 = static_cast<const char *>(ctrl) + o0 * dim * ncp * es;
+                    if (dtype == BZ_F32) launch_grid<float>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    else if (dtype == BZ_F16) launch_grid<_Float16>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    else launch_grid<bf16_t>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    BZ_CHECK_LAUNCH("k_tensor_grid");
+                }
+            } else {
+                const int64_t rows_per = (int64_t(1) << 24) / dim * dim;  // whole patches per launch
+                const int64_t rows = n_obj * dim;
+                const FastDiv dd = make_fastdiv(static_cast<uint32_t>(dim));
+                for (int64_t r0 = 0; r0 < rows; r0 += rows_per) {
+                    const uint32_t nr = static_cast<uint32_t>(std::min(rows_per, rows - r0));
+                    const uint32_t blocks = (nr + 127) / 128;
+                    const float *c0 = static_cast<const float *>(ctrl) + r0 * 16;
+                    const int64_t o0 = r0 / dim;
+                    if (engine == BZ_TP_MFMA_F32)
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                    else if (engine == BZ_TP_MFMA_BF16)
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                    else
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                    BZ_CHECK_LAUNCH("k_tensor_mfma");
+                }
+            }
+            return BZ_OK;
+        }
+        // points mode
+        if (engine != BZ_TP_VALU) return fail(BZ_ERR_UNSUPPORTED, "%s: points mode runs on the VALU engine", fn);
+        if (n_per < 0) return fail(BZ_ERR_SHAPE, "%s: n_per %lld", fn, (long long)n_per);
+        if (n_obj == 0 || n_per == 0) return BZ_OK;
+        if (!ctrl || !out) return fail(BZ_ERR_NULL, "%s: ctrl and out are required", fn);
+        if (!aligned(ctrl, es) || !aligned(uvw, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "%s: misaligned", fn);
+        const int64_t plane = n_obj * n_per;
+        const int64_t per = int64_t(1) << 22;
+        for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
+            const uint32_t blocks = static_cast<uint32_t>(std::min(per, n_obj - o0));
+            const char *c0 = static_cast<const char *>(ctrl) + o0 * dim * ncp * es;
+            if (dtype == BZ_F32) launch_pts<float>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            else if (dtype == BZ_F16) launch_pts<_Float16>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            else launch_pts<bf16_t>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            BZ_CHECK_LAUNCH("k_tensor_points");
+        }
+        return BZ_OK;
+    });
+}

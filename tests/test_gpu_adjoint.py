@@ -1,0 +1,161 @@
+"""GPU parity: the hand-written adjoint (dL/dP, dL/dw, dL/dt through the
+hodograph), the autograd Function, and the fused fitting step (loss +
+adjoint + Adam) against the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import bz_synth
+import paper_2603_15447_amd as bz
+from tests._gpu import dev, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(got, ref):
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30))
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 5, 9, 15])
+@pytest.mark.parametrize("rational", [False, True])
+def test_adjoint_vs_oracle(orc, degree, rational):
+    for dim, nt in ((3, 128), (2, 70), (4, 1)):
+        rng = np.random.default_rng(degree + 100 * dim + rational)
+        n = 41
+        ctrl = rng.uniform(-1, 1, size=(n, dim, degree + 1)).astype(np.float32)
+        w = np.exp(rng.uniform(np.log(0.25), np.log(4), size=(n, degree + 1))).astype(np.float32) if rational else None
+        t = rng.random((n, nt)).astype(np.float32)
+        g = rng.normal(size=(dim, n * nt)).astype(np.float32)
+        gc, gw, gt = bz.adjoint_bezier(to_dev(ctrl), to_dev(t), to_dev(g), w=to_dev(w) if rational else None)
+        rc, rw, rt = orc.bezier_adjoint(ctrl, t, g, w=w)
+        assert _rel(host(gc), rc) < 2e-5
+        assert _rel(host(gt), rt) < 2e-5 * degree
+        if rational:
+            assert _rel(host(gw), rw) < 2e-5
+
+
+def test_adjoint_shared_t_and_null_outputs(orc):
+    ctrl, t = bz_synth.plain_curves(n_curves=30, n_t=50)
+    g = np.random.default_rng(1).normal(size=(3, 30 * 50)).astype(np.float32)
+    gc, _, gt = bz.adjoint_bezier(to_dev(ctrl), to_dev(t), to_dev(g), need_t=False)
+    assert gt is None
+    rc, _, _ = orc.bezier_adjoint(ctrl, t, g, per_object=False)
+    assert _rel(host(gc), rc) < 2e-5
+    with pytest.raises(bz.BzError) as e:
+        bz.adjoint_bezier(to_dev(ctrl), to_dev(t), to_dev(g), need_t=True)
+    assert e.value.code == bz.ERR_UNSUPPORTED
+
+
+def test_autograd_function_matches_oracle_and_fd(orc):
+    rng = np.random.default_rng(2)
+    n, d, nt = 8, 4, 20
+    ctrl = rng.uniform(-1, 1, size=(n, 3, d + 1)).astype(np.float32)
+    w = rng.uniform(0.5, 2, size=(n, d + 1)).astype(np.float32)
+    t = rng.uniform(0.1, 0.9, size=(n, nt)).astype(np.float32)
+    G = rng.normal(size=(3, n * nt)).astype(np.float32)
+    c_d = to_dev(ctrl).requires_grad_(True)
+    w_d = to_dev(w).requires_grad_(True)
+    t_d = to_dev(t).requires_grad_(True)
+    G_d = to_dev(G)
+    loss = (bz.bezier_curve(c_d, t_d, w_d) * G_d).sum()
+    loss.backward()
+    rc, rw, rt = orc.bezier_adjoint(ctrl, t, G, w=w)
+    assert _rel(host(c_d.grad), rc) < 2e-5
+    assert _rel(host(w_d.grad), rw) < 2e-5
+    assert _rel(host(t_d.grad), rt) < 1e-4
+
+    # central finite differences of the GPU forward itself (FP32, so loose)
+    def L(cc, ww, tt):
+        return float((bz.eval_rational(cc, ww, tt) * G_d).sum().item())
+
+    h = 1e-2
+    base_c, base_w, base_t = to_dev(ctrl), to_dev(w), to_dev(t)
+    for (idx, which) in (((3, 1, 2), "c"), ((5, 0), "w"), ((2, 7), "t")):
+        args = [base_c.clone(), base_w.clone(), base_t.clone()]
+        k = "cwt".index(which)
+        args[k][idx] += h
+        lp = L(*args)
+        args[k][idx] -= 2 * h
+        lm = L(*args)
+        fd = (lp - lm) / (2 * h)
+        an = {"c": c_d.grad, "w": w_d.grad, "t": t_d.grad}[which][idx].item()
+        assert abs(fd - an) <= 2e-2 * max(1.0, abs(an)), (which, fd, an)
+
+
+def _fit_setup(orc, n, nt, seed):
+    gt_ctrl, tau, eps = bz_synth.fit_problem(n_curves=n, n_samples=nt, seed=seed)
+    y, c0, t0 = orc.fit_init(gt_ctrl, tau, eps)
+    return y, c0, t0
+
+
+def _gpu_state(y, c0, t0):
+    s = {"y": to_dev(y), "ctrl": to_dev(c0), "t": to_dev(t0)}
+    for k in ("m_ctrl", "v_ctrl"):
+        s[k] = torch.zeros_like(s["ctrl"])
+    for k in ("m_t", "v_t"):
+        s[k] = torch.zeros_like(s["t"])
+    s["loss"] = torch.zeros(c0.shape[0], device=dev())
+    return s
+
+
+def test_fit_steps_match_oracle(orc):
+    """10 fused steps (loss, adjoint, Adam on control points and t) follow the
+    FP64 oracle's steps."""
+    n, nt = 96, 128
+    y, c0, t0 = _fit_setup(orc, n, nt, 3)
+    s = _gpu_state(y, c0, t0)
+    # both sides start from the same FP32 values
+    ref_c = c0.astype(np.float32).astype(np.float64)
+    ref_t = t0.astype(np.float32).astype(np.float64)
+    ref_losses = orc.fit_steps(y.astype(np.float32).astype(np.float64), ref_c, ref_t, 10)
+    for step in range(1, 11):
+        bz.fit_adam_step(s["ctrl"], s["t"], s["y"], s["m_ctrl"], s["v_ctrl"], s["m_t"], s["v_t"], step,
+                         loss_part=s["loss"])
+        if step == 1:
+            assert abs(host(s["loss"]).sum() - ref_losses[0]) <= 1e-5 * ref_losses[0]
+    assert np.abs(host(s["ctrl"]) - ref_c).max() < 2e-3
+    assert np.abs(host(s["t"]) - ref_t).max() < 2e-3
+    assert abs(host(s["loss"]).sum() - ref_losses[-1]) <= 1e-2 * ref_losses[-1]
+
+
+def test_fit_graph_equals_eager(orc):
+    n, nt = 64, 100
+    y, c0, t0 = _fit_setup(orc, n, nt, 4)
+    a, b = _gpu_state(y, c0, t0), _gpu_state(y, c0, t0)
+    for step in range(1, 21):
+        bz.fit_adam_step(a["ctrl"], a["t"], a["y"], a["m_ctrl"], a["v_ctrl"], a["m_t"], a["v_t"], step,
+                         loss_part=a["loss"])
+    bz.fit_adam_run(b["ctrl"], b["t"], b["y"], b["m_ctrl"], b["v_ctrl"], b["m_t"], b["v_t"], 1, 20,
+                    loss_part=b["loss"])
+    for k in ("ctrl", "t", "m_ctrl", "v_t", "loss"):
+        np.testing.assert_array_equal(host(a[k]), host(b[k]))
+    # a second replayed run continues from step 21 exactly like eager steps
+    for step in range(21, 26):
+        bz.fit_adam_step(a["ctrl"], a["t"], a["y"], a["m_ctrl"], a["v_ctrl"], a["m_t"], a["v_t"], step,
+                         loss_part=a["loss"])
+    bz.fit_adam_run(b["ctrl"], b["t"], b["y"], b["m_ctrl"], b["v_ctrl"], b["m_t"], b["v_t"], 21, 5,
+                    loss_part=b["loss"])
+    np.testing.assert_array_equal(host(a["ctrl"]), host(b["ctrl"]))
+
+
+def test_fit_config_full_size(orc):
+    """65536 cubic 3D curves x 128 noisy samples, 200 Adam steps in one graph;
+    the loss falls toward the noise floor and the first 256 curves track the
+    FP64 oracle run with the same global normalisation."""
+    n, nt = 65536, 128
+    gt_ctrl, tau, eps = bz_synth.fit_problem()
+    y, c0, t0 = orc.fit_init(gt_ctrl, tau, eps)
+    s = _gpu_state(y, c0, t0)
+    bz.fit_adam_step(s["ctrl"], s["t"], s["y"], s["m_ctrl"], s["v_ctrl"], s["m_t"], s["v_t"], 1, loss_part=s["loss"])
+    loss0 = host(s["loss"]).sum()
+    bz.fit_adam_run(s["ctrl"], s["t"], s["y"], s["m_ctrl"], s["v_ctrl"], s["m_t"], s["v_t"], 2, 199,
+                    loss_part=s["loss"])
+    loss_end = host(s["loss"]).sum()
+    assert loss_end < 0.5 * loss0
+    k = 256
+    y3 = y.reshape(3, n, nt)[:, :k].reshape(3, -1).astype(np.float32).astype(np.float64)
+    rc = c0[:k].astype(np.float32).astype(np.float64)
+    rt = t0[:k].astype(np.float32).astype(np.float64)
+    ref_losses = orc.fit_steps(y3, rc, rt, 200, m_total=float(n * nt))
+    got_part = host(s["loss"])[:k].sum()
+    assert abs(got_part - ref_losses[-1]) <= 0.05 * ref_losses[-1]

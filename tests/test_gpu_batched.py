@@ -1,0 +1,160 @@
+"""GPU parity: mixed batches (integral / rational Bezier of degree 1..15 and
+cubic NURBS) in one persistent launch, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import bz_synth
+import paper_2603_15447_amd as bz
+from tests._gpu import TOL_F32, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _extents(b, ctrl=None):
+    """Per-object normaliser (largest bounding-box side, floored by the
+    largest |coordinate|, as for single curves)."""
+    c = np.asarray(b.ctrl if ctrl is None else ctrl, np.float64)
+    ext = np.empty(b.n_obj)
+    for o in range(b.n_obj):
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        P = c[a0 * b.dim:a1 * b.dim].reshape(b.dim, a1 - a0)
+        ext[o] = max((P.max(axis=1) - P.min(axis=1)).max(), np.abs(P).max(), 1e-30)
+    return ext
+
+
+def _err(got, ref, ext, n_t):
+    d = np.abs(got - ref)
+    if np.isnan(d).any():
+        return np.inf
+    return float((d.max(axis=0).reshape(-1, n_t).max(axis=1) / ext).max())
+
+
+def _plan(b, dtype=torch.float32, method="bernstein"):
+    dev = {
+        "kind_degree": torch.from_numpy(b.kind_degree.astype(np.int16)).cuda(),
+        "cp_offset": torch.from_numpy(b.cp_offset).cuda(),
+        "ctrl": to_dev(b.ctrl).to(dtype),
+        "w": to_dev(b.w).to(dtype),
+        "knot_offset": torch.from_numpy(b.knot_offset).cuda(),
+        "knots": to_dev(b.knots if b.knots.size else np.zeros(1, np.float32)),
+    }
+    plan = bz.BatchPlan(dev["kind_degree"], dev["cp_offset"], dev["ctrl"], dev["w"], b.dim, dev["knot_offset"],
+                        dev["knots"], b.n_t, method)
+    return plan, dev
+
+
+def _subbatch(b, n):
+    """The first n objects of a batch, re-based."""
+    cp = b.cp_offset[:n + 1]
+    ko = b.knot_offset[:n + 1]
+    return bz_synth.Batch(dim=b.dim, n_t=b.n_t, kind_degree=b.kind_degree[:n], cp_offset=cp,
+                          ctrl=b.ctrl[:cp[-1] * b.dim], w=b.w[:cp[-1]], knot_offset=ko, knots=b.knots[:ko[-1]],
+                          t=b.t[:n])
+
+
+@pytest.mark.parametrize("method", ["bernstein", "decasteljau"])
+@pytest.mark.parametrize("n_t", [16, 1, 37])
+def test_mixed_batch(orc, method, n_t):
+    b = bz_synth.mixed_batch(n_bezier=3000, n_nurbs=400, n_t=n_t, deg_lo=1, seed=11 + n_t)
+    plan, dev = _plan(b, method=method)
+    info = plan.info()
+    assert info["n_classes"] == len(set(b.kind_degree.tolist()))
+    t = to_dev(b.t)
+    got = host(plan(t))
+    ref = orc.batch_eval(b)
+    assert _err(got, ref, _extents(b), n_t) <= TOL_F32
+    # repeated launches reuse the self-resetting work counter
+    again = host(plan(t))
+    np.testing.assert_array_equal(again, got)
+
+
+def test_mixed_batch_dims_and_kinds(orc):
+    for dim in (1, 2, 4):
+        b = bz_synth.mixed_batch(n_bezier=500, n_nurbs=60, dim=dim, n_t=8, seed=dim)
+        plan, _ = _plan(b)
+        got = host(plan(to_dev(b.t)))
+        assert _err(got, orc.batch_eval(b), _extents(b), 8) <= TOL_F32
+    b = bz_synth.mixed_batch(n_bezier=700, n_nurbs=0, n_t=5, seed=4)  # no NURBS, no knots needed
+    plan, _ = _plan(b)
+    assert _err(host(plan(to_dev(b.t))), orc.batch_eval(b), _extents(b), 5) <= TOL_F32
+    b = bz_synth.mixed_batch(n_bezier=0, n_nurbs=333, n_t=7, knots_lo=8, knots_hi=8, seed=5)  # single-span NURBS
+    plan, _ = _plan(b)
+    assert _err(host(plan(to_dev(b.t))), orc.batch_eval(b), _extents(b), 7) <= TOL_F32
+
+
+def test_nurbs_clamp_and_ends(orc):
+    b = bz_synth.mixed_batch(n_bezier=0, n_nurbs=50, n_t=4, seed=6)
+    b.t[:, 0] = -0.5
+    b.t[:, 1] = 0.0
+    b.t[:, 2] = 1.0
+    b.t[:, 3] = 7.0
+    plan, _ = _plan(b)
+    got = host(plan(to_dev(b.t))).reshape(3, 50, 4)
+    ref = orc.batch_eval(b).reshape(3, 50, 4)
+    for o in range(50):
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        P = b.ctrl[a0 * 3:a1 * 3].reshape(3, a1 - a0)
+        np.testing.assert_allclose(got[:, o, :2], P[:, :1].repeat(2, 1), atol=2e-6)
+        np.testing.assert_allclose(got[:, o, 2:], P[:, -1:].repeat(2, 1), atol=2e-6)
+    np.testing.assert_allclose(got, ref, atol=2e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_low_precision_storage(orc, dtype):
+    """FP16/BF16 control points and weights, FP32 arithmetic: within FP32
+    rounding of the oracle on the rounded inputs."""
+    b = bz_synth.mixed_batch(n_bezier=2000, n_nurbs=200, n_t=16, seed=7)
+    plan, dev = _plan(b, dtype=dtype)
+    got = host(plan(to_dev(b.t)))
+    rb = bz_synth.Batch(**{**b.__dict__})
+    rb.ctrl = dev["ctrl"].float().cpu().numpy()
+    rb.w = dev["w"].float().cpu().numpy()
+    assert _err(got, orc.batch_eval(rb), _extents(rb), 16) <= TOL_F32
+
+
+def test_autotune_keeps_results(orc):
+    b = bz_synth.mixed_batch(n_bezier=20000, n_nurbs=2000, n_t=16, seed=8)
+    plan, _ = _plan(b)
+    t = to_dev(b.t)
+    out = torch.empty((3, b.n_obj * 16), device=t.device)
+    best = plan.autotune(t, out)
+    assert best["workgroups"] >= 1 and best["tile_multiple"] in (1, 2, 4)
+    got = host(plan(t))
+    assert _err(got, orc.batch_eval(b), _extents(b), 16) <= TOL_F32
+
+
+def test_plan_errors():
+    b = bz_synth.mixed_batch(n_bezier=10, n_nurbs=3, n_t=2, seed=9)
+    bad = b.knots.copy()
+    k0 = b.knot_offset[np.nonzero(b.kind_degree >> 8 == 2)[0][0]]
+    bad[k0] = -1.0  # breaks the clamped start
+    b2 = bz_synth.Batch(**{**b.__dict__, "knots": bad})
+    with pytest.raises(bz.BzError) as e:
+        _plan(b2)
+    assert e.value.code == bz.ERR_SHAPE
+    kd = b.kind_degree.copy()
+    kd[np.nonzero(kd >> 8 == 2)[0][0]] = (2 << 8) | 2
+    with pytest.raises(bz.BzError) as e:
+        _plan(bz_synth.Batch(**{**b.__dict__, "kind_degree": kd}))
+    assert e.value.code == bz.ERR_UNSUPPORTED
+
+
+def test_config_batched_full_size_sampled(orc):
+    """2^20 Bezier curves (degree 2..15, half rational) + 2^16 cubic NURBS,
+    16 random t each, FP32 and FP16 storage; the first 65536 objects checked."""
+    b = bz_synth.mixed_batch()
+    sub = _subbatch(b, 65536)
+    ref = orc.batch_eval(sub)
+    ext = _extents(sub)
+    for dtype in (torch.float32, torch.float16):
+        plan, dev = _plan(b, dtype=dtype)
+        got = host(plan(to_dev(b.t))[:, :65536 * 16])
+        if dtype == torch.float32:
+            assert _err(got, ref, ext, 16) <= TOL_F32
+        else:
+            rsub = bz_synth.Batch(**{**sub.__dict__})
+            rsub.ctrl = dev["ctrl"][:len(sub.ctrl)].float().cpu().numpy()
+            rsub.w = dev["w"][:len(sub.w)].float().cpu().numpy()
+            assert _err(got, orc.batch_eval(rsub), _extents(rsub), 16) <= TOL_F32
+        plan.close()
