@@ -1,20 +1,26 @@
-"""Benchmark: random-access evaluation of a C0 quadratic chain in the
-shared-diagonal (zig-zag) encoding on one MI355X.
+"""Benchmark of the Bezier-family evaluators on one MI355X.
 
-Workload: a chain of 2^20 quadratic segments (control points a random walk
-with U[-0.1,0.1]^3 steps), encoded once into the 2 x (N+1) zig-zag grid, then
-evaluated at 2^24 uniform random global parameters T in [0, 2^20) per step.
-One step is one bz_eval_piecewise call over all 2^24 queries (parameter
-decode, grid gather, bilinear diagonal read, store), inputs resident in HBM.
+Headline workload (the JSON line's `value`): random-access evaluation of a C0
+quadratic chain in the shared-diagonal (zig-zag) encoding.  A chain of 2^20
+quadratic segments (control points a random walk with U[-0.1,0.1]^3 steps) is
+encoded once into the 2 x (N+1) zig-zag texels, then one step evaluates it at
+2^24 uniform random global parameters T in [0, 2^20) (parameter decode,
+texel gather, bilinear diagonal read, store), inputs resident in HBM.
 
-Prints one JSON line: throughput in G curve-point evaluations/s, the HBM
-roofline of the kernel (algorithmic bytes per launch over its event-timed
-average duration), the max error against the FP64 oracle on a sample, and the
-oracle's own throughput on the host cores.
+`suite` adds the other workloads, each with its own kernel time, roofline and
+a CPU-baseline leg (the FP64 oracle timed on a bounded sample, whose outputs
+also give the GPU's max error on that sample): plain cubic curves (three
+forms), the mixed batch in one persistent launch (FP32 vs FP16 storage),
+bicubic patch tessellation (VALU vs FP32/BF16/FP16 MFMA), tricubic volumes at
+random points, and the fitting loop (fused loss + adjoint + Adam, 200 steps
+replayed from one HIP graph).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,18 +32,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak for code built without packed-FP32 instructions:
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "G curve-point evals/s and % HBM roofline, plain FP32 vs batched/FP16 at max err"
+COUNTER_FILES = {"grid": "chain_eval_counters.json", "tiled": "chain_eval_tiled_counters.json"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def chain_bytes(n_seg, dim, n_q):
-    """Algorithmic HBM bytes of one evaluation launch: the grid once, T in, points out."""
+    """Algorithmic HBM bytes of one evaluation launch: the texels once, T in, points out."""
     return (n_seg + 1) * 2 * dim * 4 + n_q * 4 + n_q * dim * 4
 
 
-def recorded_traffic(name="chain_eval_counters.json"):
+def recorded_traffic(name):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source has changed since the counters were taken."""
-    import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
@@ -61,22 +74,246 @@ def event_time_ms(fn, iters, torch):
     return a.elapsed_time(b) / iters
 
 
-def cpu_baseline(chain, T, budget_s=10.0):
-    import oracle
-    n = T.shape[0]
-    sample = T[: min(n, 1 << 22)]
+def timed(fn, torch, iters=20, warmup=3):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    return event_time_ms(fn, iters, torch)
+
+
+def hbm_roof(nbytes, ms):
+    a = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
+
+
+def oracle_timed(fn, budget_s=10.0, max_reps=8):
+    """Run an oracle call repeatedly for up to budget_s; returns (result, seconds per call, calls)."""
     t0 = time.perf_counter()
-    reps = 0
+    reps, res = 0, None
     while True:
-        oracle.chain_eval(chain, sample)
+        res = fn()
         reps += 1
         el = time.perf_counter() - t0
-        if el > budget_s or reps >= 8:
-            break
-    rate = reps * sample.shape[0] / el / 1e9
-    return {"value": rate, "unit": "G evals/s", "cores": oracle.max_threads(), "kind": "oracle",
+        if el > budget_s or reps >= max_reps:
+            return res, el / reps, reps
+
+
+def max_err_bbox(got, ref, ext, per_obj):
+    d = np.abs(np.asarray(got, np.float64) - ref)
+    if np.isnan(d).any():
+        return float("inf")
+    return float((d.max(axis=0).reshape(-1, per_obj).max(axis=1) / ext).max())
+
+
+def extents(ctrl):
+    c = np.asarray(ctrl, np.float64)
+    side = (c.max(axis=2) - c.min(axis=2)).max(axis=1)
+    return np.maximum(np.maximum(side, np.abs(c).max(axis=(1, 2))), 1e-30)
+
+
+# ---------------------------------------------------------------- headline
+def cpu_baseline_chain(chain, T, out_dev, budget_s=10.0):
+    """CPU-baseline leg: the oracle's chain definition on the first 4M queries,
+    timed on the host cores; its outputs also give the GPU's error there."""
+    import oracle
+    m = min(T.shape[0], 1 << 22)
+    ref, sec, reps = oracle_timed(lambda: oracle.chain_eval(chain, T[:m]), budget_s)
+    got = out_dev[:, :m].cpu().numpy().astype(np.float64)
+    ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+    err = float(np.abs(got - ref).max() / ext)
+    return {"value": m / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%d x %d random T of the same 2^20-segment chain (FP64 chain definition, OpenMP)"
-                      % (reps, sample.shape[0])}
+                      % (reps, m)}, err
+
+
+# ---------------------------------------------------------------- suite
+def suite_plain(torch, bz, bz_synth, cpu):
+    log("suite: plain curves")
+    ctrl, t = bz_synth.plain_curves()
+    res = {}
+    c_d, t_d = torch.from_numpy(ctrl).cuda(), torch.from_numpy(t).cuda()
+    out = torch.empty((3, ctrl.shape[0] * t.shape[0]), device="cuda")
+    ref = None
+    if cpu:
+        import oracle
+        ref, sec, _ = oracle_timed(lambda: oracle.bezier_decasteljau(ctrl, t), 2.0)
+        res["cpu_baseline"] = {"value": out.shape[1] / sec / 1e9, "unit": "G evals/s",
+                               "cores": oracle.max_threads(), "kind": "oracle", "sample": "all 4096 x 256 points"}
+    nbytes = out.numel() * 4 + ctrl.nbytes + t.nbytes
+    for m in ("decasteljau", "bernstein", "seiler"):
+        ms = timed(lambda: bz.eval_bezier(c_d, t_d, m, out=out), torch, iters=50)
+        e = {"kernel_ms": ms, "value": out.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms)}
+        if ref is not None:
+            e["max_err_bbox"] = max_err_bbox(out.cpu().numpy(), ref, extents(ctrl), 256)
+        res[m] = e
+    # x16 curves: past the launch-bound regime
+    c16 = torch.from_numpy(bz_synth.plain_curves(n_curves=1 << 16)[0]).cuda()
+    o16 = torch.empty((3, (1 << 16) * 256), device="cuda")
+    n16 = o16.numel() * 4 + c16.numel() * 4 + t.nbytes
+    for m in ("decasteljau", "bernstein", "seiler"):
+        ms = timed(lambda: bz.eval_bezier(c16, t_d, m, out=o16), torch)
+        res[m + "_x16"] = {"kernel_ms": ms, "value": o16.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(n16, ms)}
+    return {"workload": "4096 cubic 3D Bezier curves x 256 shared t (1M points), FP32; *_x16: 65536 curves",
+            "unit": "G evals/s", **res}
+
+
+def batch_bytes(b, es, n_segs, dim):
+    """Algorithmic bytes of one batched launch: control points (and weights of
+    rational objects) once, NURBS segments and breakpoints once, per-object
+    indices, and per query the parameter in and the point out."""
+    kind = b.kind_degree >> 8
+    ncp = np.diff(b.cp_offset)
+    bez = kind != 2
+    rd = int((ncp[bez] * dim * es).sum() + (ncp[kind == 1] * es).sum())
+    rd += n_segs * 4 * (dim + 1) * 4 + int((kind == 2).sum()) * 12 + n_segs * 4
+    rd += b.n_obj * 12
+    return rd + b.n_obj * b.n_t * (4 + 4 * dim)
+
+
+def suite_batched(torch, bz, bz_synth, cpu):
+    log("suite: batched (generating 2^20 + 2^16 objects)")
+    b = bz_synth.mixed_batch()
+    n_q = b.n_obj * b.n_t
+    kd = torch.from_numpy(b.kind_degree.astype(np.int16)).cuda()
+    cpo = torch.from_numpy(b.cp_offset).cuda()
+    ko = torch.from_numpy(b.knot_offset).cuda()
+    kn = torch.from_numpy(b.knots).cuda()
+    t = torch.from_numpy(b.t).cuda()
+    out = torch.empty((3, n_q), device="cuda")
+    res = {}
+    sub_n = 16384
+    ref = sub = ext = None
+    if cpu:
+        import oracle
+        cp, kk = b.cp_offset[:sub_n + 1], b.knot_offset[:sub_n + 1]
+        sub = bz_synth.Batch(dim=3, n_t=16, kind_degree=b.kind_degree[:sub_n], cp_offset=cp, ctrl=b.ctrl[:cp[-1] * 3],
+                             w=b.w[:cp[-1]], knot_offset=kk, knots=b.knots[:kk[-1]], t=b.t[:sub_n])
+        ref, sec, _ = oracle_timed(lambda: oracle.batch_eval(sub), 5.0)
+        res["cpu_baseline"] = {"value": sub_n * 16 / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "first %d objects x 16 t (de Casteljau / de Boor)" % sub_n}
+        ext = np.empty(sub_n)
+        for o in range(sub_n):
+            P = sub.ctrl[cp[o] * 3:cp[o + 1] * 3].reshape(3, -1).astype(np.float64)
+            ext[o] = max((P.max(1) - P.min(1)).max(), np.abs(P).max())
+    for dt, name in ((torch.float32, "fp32"), (torch.float16, "fp16")):
+        ctrl = torch.from_numpy(b.ctrl).cuda().to(dt)
+        w = torch.from_numpy(b.w).cuda().to(dt)
+        plan = bz.BatchPlan(kd, cpo, ctrl, w, 3, ko, kn, 16, "bernstein")
+        tune = plan.autotune(t, out)
+        ms = timed(lambda: plan(t, out=out), torch)
+        info = plan.info()
+        nbytes = batch_bytes(b, 4 if dt == torch.float32 else 2, info["n_segments"], 3)
+        e = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms),
+             "algorithmic_bytes": nbytes, "autotune": tune, "plan": info}
+        if ref is not None:
+            got = out[:, :sub_n * 16].cpu().numpy()
+            if name == "fp32":
+                e["max_err_bbox"] = max_err_bbox(got, ref, ext, 16)
+            else:
+                import oracle
+                rsub = bz_synth.Batch(**{**sub.__dict__})
+                rsub.ctrl = ctrl[:len(sub.ctrl)].float().cpu().numpy()
+                rsub.w = w[:len(sub.w)].float().cpu().numpy()
+                e["max_err_bbox_vs_rounded_inputs"] = max_err_bbox(got, oracle.batch_eval(rsub), ext, 16)
+                e["max_err_bbox_vs_fp32_inputs"] = max_err_bbox(got, ref, ext, 16)
+        plan.close()
+        res[name] = e
+    return {"workload": "2^20 Bezier curves (degree U{2..15}, half rational) + 2^16 cubic NURBS (8-64 knots), "
+                        "16 random t each, one persistent launch, Bernstein form", "unit": "G evals/s", **res}
+
+
+def suite_patches(torch, bz, bz_synth, cpu):
+    log("suite: patches")
+    n = 1 << 18
+    P = bz_synth.patches(n_obj=n)
+    Pd = torch.from_numpy(P).cuda()
+    out = torch.empty((3, n * 1024), device="cuda")
+    nbytes = out.numel() * 4 + P.nbytes
+    res = {}
+    pick = np.arange(0, n, n // 1024)
+    ref = None
+    if cpu:
+        import oracle
+        ref, sec, _ = oracle_timed(lambda: oracle.tensor_grid(P[pick], 3, 3, 32, 32), 3.0)
+        res["cpu_baseline"] = {"value": len(pick) * 1024 / sec / 1e9, "unit": "G points/s",
+                               "cores": oracle.max_threads(), "kind": "oracle", "sample": "1024 patches x 32x32"}
+    for eng in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16"):
+        ms = timed(lambda: bz.eval_tensor_patch(Pd, 3, 3, nu=32, nv=32, engine=eng, out=out), torch, iters=10)
+        e = {"kernel_ms": ms, "value": n * 1024 / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms)}
+        if ref is not None:
+            got = out.view(3, n, 1024)[:, torch.from_numpy(pick).cuda()].cpu().numpy().reshape(3, -1)
+            e["max_err_bbox"] = max_err_bbox(got, ref, extents(P[pick]), 1024)
+        res[eng] = e
+    del out
+    return {"workload": "2^18 bicubic 3D patches tessellated on a 32x32 grid (2^28 points)", "unit": "G points/s",
+            **res}
+
+
+def suite_volumes(torch, bz, bz_synth, cpu):
+    log("suite: volumes")
+    ctrl, uvw = bz_synth.volumes()
+    n, per = ctrl.shape[0], uvw.shape[1]
+    c_d, u_d = torch.from_numpy(ctrl).cuda(), torch.from_numpy(uvw).cuda()
+    out = torch.empty((3, n * per), device="cuda")
+    ms = timed(lambda: bz.eval_tensor_patch(c_d, 3, 3, 3, uvw=u_d, out=out), torch)
+    nbytes = ctrl.nbytes + uvw.nbytes + out.numel() * 4
+    # per query: three cubic bases (~15 ops each) and, per coordinate, 64 + 16 + 4 multiply-adds
+    flop = n * per * (3 * 15 + 3 * 84 * 2)
+    tf = flop / (ms * 1e-3) / 1e12
+    res = {"kernel_ms": ms, "value": n * per / (ms * 1e-3) / 1e9, "hbm": hbm_roof(nbytes, ms),
+           "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP32_VALU_PEAK_TFLOPS}}
+    if cpu:
+        import oracle
+        k = 512
+        ref, sec, _ = oracle_timed(lambda: oracle.tensor_points(ctrl[:k], 3, 3, 3, uvw[:k]), 3.0)
+        res["cpu_baseline"] = {"value": k * per / sec / 1e9, "unit": "G points/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "first 512 volumes x 256 points"}
+        got = out.view(3, n, per)[:, :k].cpu().numpy().reshape(3, -1)
+        res["max_err_bbox"] = max_err_bbox(got, ref, extents(ctrl[:k]), per)
+    return {"workload": "2^16 tricubic 3D volumes at 2^24 random (u,v,w)", "unit": "G points/s", **res}
+
+
+def suite_fit(torch, bz, bz_synth, cpu):
+    log("suite: fit")
+    gt_ctrl, tau, eps = bz_synth.fit_problem()
+    n, nt = tau.shape
+    res = {}
+    # targets y = G(tau) + noise, evaluated by the curve kernel
+    y = bz.eval_bezier(torch.from_numpy(gt_ctrl).cuda(), torch.from_numpy(tau).cuda())
+    y += torch.from_numpy(eps).cuda()
+    y3 = y.view(3, n, nt)
+    frac = torch.arange(4, device="cuda", dtype=torch.float32) / 3.0
+    ctrl = (y3[:, :, 0].T[:, :, None] * (1 - frac) + y3[:, :, -1].T[:, :, None] * frac).contiguous()
+    t = torch.arange(nt, device="cuda", dtype=torch.float32).div(nt - 1).repeat(n, 1).contiguous()
+    mc, vc, mt, vt = (torch.zeros_like(ctrl), torch.zeros_like(ctrl), torch.zeros_like(t), torch.zeros_like(t))
+    loss = torch.zeros(n, device="cuda")
+    bz.fit_adam_step(ctrl, t, y, mc, vc, mt, vt, 1, loss_part=loss)
+    loss0 = float(loss.sum())
+    s = torch.cuda.current_stream()
+    a, bb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    bz.fit_adam_run(ctrl, t, y, mc, vc, mt, vt, 2, 199, loss_part=loss)
+    bb.record(s)
+    bb.synchronize()
+    ms_199 = a.elapsed_time(bb)
+    ms_step = ms_199 / 199
+    per_sample = 4 * 2 + 12 + 16  # t read+write, y, Adam moments of t read+write
+    nbytes = n * nt * per_sample + n * 12 * 4 * 6 + n * 4
+    res.update({"ms_per_step": ms_step, "graph_ms_199_steps": ms_199,
+                "value": n * nt / (ms_step * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms_step),
+                "loss_step1": loss0, "loss_step200": float(loss.sum())})
+    if cpu:
+        import oracle
+        yh = y.cpu().numpy().astype(np.float64)
+        c0 = np.zeros((n, 3, 4))
+        t0 = np.tile(np.arange(nt) / (nt - 1), (n, 1))
+        _, sec, _ = oracle_timed(lambda: oracle.fit_loss_grad(c0, t0, yh), 1.0, 1)
+        res["cpu_baseline"] = {"value": n * nt / sec / 1e9, "unit": "G sample-steps/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "one full loss+gradient evaluation (65536 x 128), "
+                                                           "i.e. one of the 200 steps"}
+    return {"workload": "fit 65536 cubic 3D curves to 128 noisy samples each: fused L2 loss + adjoint + Adam, "
+                        "200 steps (HIP graph)", "unit": "G sample-steps/s", **res}
 
 
 def main():
@@ -86,7 +323,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n-seg", type=int, default=1 << 20)
     ap.add_argument("--n-q", type=int, default=1 << 24)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
+    ap.add_argument("--no-suite", action="store_true", help="headline workload only")
+    ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
+                    help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -111,6 +351,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
         return
     dim = 3
+    log("headline: generating the chain")
     chain, T = bz_synth.chain_walk(n_seg=args.n_seg, dim=dim, n_q=args.n_q)
     chain_d = torch.from_numpy(chain).to(dev)
     T_d = torch.from_numpy(T).to(dev)
@@ -119,8 +360,14 @@ def main():
     bz.encode_piecewise(chain_d, out=grid)
     torch.cuda.synchronize()
     enc_ms = event_time_ms(lambda: bz.encode_piecewise(chain_d, out=grid), 5, torch)
-
-    step = lambda: bz.eval_piecewise(grid, T_d, out=out)
+    tiles = bz.tile_piecewise(grid)
+    steps = {"grid": lambda: bz.eval_piecewise(grid, T_d, out=out),
+             "tiled": lambda: bz.eval_piecewise_tiled(tiles, args.n_seg, dim, T_d, out=out)}
+    other = "grid" if args.layout == "tiled" else "tiled"
+    for _ in range(3):
+        steps[other]()
+    other_ms = event_time_ms(steps[other], max(10, args.steps // 4), torch)
+    step = steps[args.layout]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -131,18 +378,11 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     kern_ms = event_time_ms(step, args.steps, torch)
-
-    # parity on a sample of outputs, every one recomputed by the FP64 oracle
-    import oracle
-    rng = np.random.default_rng(7)
-    idx = np.sort(rng.choice(args.n_q, size=min(args.n_q, 1 << 16), replace=False))
-    got = out[:, torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
-    ref = oracle.chain_eval(chain, T[idx])
-    ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
-    max_err = float(np.abs(got - ref).max() / ext)
+    log("headline: %.2f G evals/s" % (args.n_q / (ms_per_step * 1e-3) / 1e9))
 
     nbytes = chain_bytes(args.n_seg, dim, args.n_q)
-    achieved = nbytes / (kern_ms * 1e-3) / 1e9
+    roof = hbm_roof(nbytes, kern_ms)
+    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout])
     rec = {
         "metric": METRIC,
         "value": args.n_q / (ms_per_step * 1e-3) / 1e9,
@@ -158,17 +398,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": "C0 piecewise quadratic chain, zig-zag encoded (E=(B+C)/2), %d segments, "
                                "%d uniform random global T, 3D, FP32" % (args.n_seg, args.n_q),
-                   "n_seg": args.n_seg, "n_q": args.n_q, "dim": dim},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic()},
-        "kernel": "k_piecewise_eval",
+                   "n_seg": args.n_seg, "n_q": args.n_q, "dim": dim, "layout": args.layout},
+        "roofline": roof,
+        "kernel": "k_piecewise_eval_tiled" if args.layout == "tiled" else "k_piecewise_eval",
         "kernel_ms": kern_ms,
         "algorithmic_bytes": nbytes,
-        "max_err_bbox": max_err,
+        "other_layout": {"layout": other, "kernel_ms": other_ms, "value": args.n_q / (other_ms * 1e-3) / 1e9},
         "encode_ms": enc_ms,
     }
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(chain, T)
+        log("headline: CPU baseline")
+        rec["cpu_baseline"], rec["max_err_bbox"] = cpu_baseline_chain(chain, T, out)
+    del out, grid, tiles, T_d, chain_d
+    torch.cuda.empty_cache()
+    if not args.no_suite:
+        suite = {}
+        for name, fn in (("plain", suite_plain), ("batched", suite_batched), ("patches", suite_patches),
+                         ("volumes", suite_volumes), ("fit", suite_fit)):
+            suite[name] = fn(torch, bz, bz_synth, not args.no_cpu)
+            torch.cuda.empty_cache()
+        rec["suite"] = suite
     print(json.dumps(rec), flush=True)
 
 

@@ -79,3 +79,44 @@ def test_encode_then_eval_full_chain_config(orc):
     del got, ref
     # storage: 2(N+1) texels
     assert grid.shape[0] * grid.shape[1] == 2 * ((chain.shape[0] - 1) // 2 + 1)
+
+
+def _tiles_reference(grid):
+    """Host re-tiling of a grid (plain index arithmetic): 128-byte tiles of
+    C = 128/(8*dim) columns overlapping by one column, zero padded."""
+    n_seg, dim = grid.shape[0] - 1, grid.shape[2]
+    C = 128 // (8 * dim)
+    S = C - 1
+    n_tiles = -(-n_seg // S)
+    tiles = np.zeros((n_tiles, 32), np.float32)
+    flat = grid.reshape(n_seg + 1, 2 * dim)
+    for j in range(n_tiles):
+        cols = flat[j * S: j * S + C]
+        tiles[j, :cols.size] = cols.reshape(-1)
+    return tiles.reshape(-1)
+
+
+@pytest.mark.parametrize("n_seg,dim", [(1, 3), (4, 3), (5, 3), (1000, 3), (77, 1), (300, 2), (129, 4)])
+def test_tiled_layout_and_eval(orc, n_seg, dim):
+    chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=3001, seed=7 * n_seg + dim)
+    grid = bz.encode_piecewise(to_dev(chain))
+    tiles = bz.tile_piecewise(grid)
+    np.testing.assert_array_equal(host(tiles), _tiles_reference(host(grid)))
+    T = np.concatenate([T, np.array([0, n_seg, -1, n_seg + 3, np.nan], np.float32),
+                        np.arange(n_seg + 1, dtype=np.float32)])
+    got = host(bz.eval_piecewise_tiled(tiles, n_seg, dim, to_dev(T)))
+    ref_grid = host(bz.eval_piecewise(grid, to_dev(T)))
+    np.testing.assert_array_equal(got, ref_grid)  # same texels, same arithmetic
+    ok = ~np.isnan(T)
+    ref = orc.chain_eval(chain, T[ok])
+    assert np.abs(got[:, ok] - ref).max() <= TOL_F32 * _chain_extent(chain)
+    assert np.isnan(got[:, ~ok]).all()
+
+
+def test_tiled_full_chain_config(orc):
+    chain, T = bz_synth.chain_walk()
+    grid = bz.encode_piecewise(to_dev(chain))
+    tiles = bz.tile_piecewise(grid)
+    got = host(bz.eval_piecewise_tiled(tiles, grid.shape[0] - 1, 3, to_dev(T)))
+    ref = orc.chain_eval(chain, T)
+    assert np.abs(got - ref).max() / _chain_extent(chain) <= TOL_F32
