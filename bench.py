@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--n-q", type=int, default=1 << 24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
+    ap.add_argument("--suite-only", choices=["plain", "batched", "patches", "volumes", "fit"], default=None,
+                    help="run one suite workload only (no headline) and print its record")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
                     help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -349,6 +351,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
+    suites = {"plain": suite_plain, "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
+              "fit": suite_fit}
+    if args.suite_only:
+        print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}), flush=True)
         return
     dim = 3
     log("headline: generating the chain")
@@ -413,8 +420,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_suite:
         suite = {}
-        for name, fn in (("plain", suite_plain), ("batched", suite_batched), ("patches", suite_patches),
-                         ("volumes", suite_volumes), ("fit", suite_fit)):
+        for name, fn in suites.items():
             suite[name] = fn(torch, bz, bz_synth, not args.no_cpu)
             torch.cuda.empty_cache()
         rec["suite"] = suite

@@ -10,8 +10,7 @@
  * General conventions (apply to every entry point below):
  *  - Every array argument is a DEVICE pointer owned by the caller.  The
  *    library never frees it and keeps no reference to it after the call
- *    returns, except the control points and weights of a batch plan (see
- *    bz_batch_plan_create).
+ *    returns (a batch plan keeps its own copies).
  *  - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
  *    stream) and never synchronises the device, except bz_batch_plan_create.
  *  - Every entry point returns a bz_status.  Arguments are validated before
@@ -179,13 +178,13 @@ int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, int du, int
  *                        length ncp+4; may be NULL if there is no NURBS
  *   n_t                  parameters per object
  * The plan reads the descriptor (synchronously), sorts objects into
- * uniform classes, extracts the rational Bezier segments of every NURBS on the
- * GPU and keeps its own copies of all of that, so kind_degree, cp_offset,
- * knot_offset and knots may be freed afterwards.  ctrl and w are referenced,
- * not copied: they must stay allocated while the plan is used (values of
- * Bezier objects may change between evaluations; NURBS changes need a new
- * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the
- * knot range) and out[dim][n_obj*n_t] are passed per evaluation.  method:
+ * uniform classes (kind, degree), copies the control points and weights of
+ * the Bezier objects into class-sorted contiguous order, extracts the
+ * rational Bezier segments of every NURBS on the GPU and keeps all of that in
+ * its own device memory: none of the descriptor arrays, ctrl or w is used
+ * after bz_batch_plan_create returns (changed control points need a new
+ * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the knot
+ * range) and out[dim][n_obj*n_t] are passed per evaluation.  method:
  * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects are evaluated in FP32
  * (no FP64 recomputation: use bz_eval_rational for signed weights).
  * n_obj*n_t must stay below 2^32.
@@ -197,9 +196,11 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
 int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
 /*
  * Autotuner: times the persistent launch on (t, out) for 3 tile sizes (1, 2
- * or 4 x 256 queries per tile) x 3 grid sizes (0.5, 1, 2 x CUs x occupancy)
- * and keeps the fastest in the plan.  Synchronises the stream.  best4
- * (nullable, host): workgroups, tile multiple, microseconds per launch, tiles.
+ * or 4 x 256 queries per tile) x 2 schedules (atomic tile counter, static
+ * round robin) x 3 grid sizes (0.5, 1, 2 x CUs x occupancy) and keeps the
+ * fastest in the plan.  Synchronises the stream.  best4 (nullable, host):
+ * workgroups, tile multiple, microseconds per launch, schedule (1 dynamic,
+ * 0 static).
  */
 int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best4);
 /* Plan statistics: n_classes, n_tiles, n_segments (NURBS), workgroups. */

@@ -246,7 +246,8 @@ class BatchPlan:
     def autotune(self, t, out):
         buf = (ctypes.c_int64 * 4)()
         check(lib().bz_batch_plan_autotune(self._h, _ptr(t), _ptr(out), _stream(), ctypes.cast(buf, _P)))
-        return {"workgroups": buf[0], "tile_multiple": buf[1], "us_per_launch": buf[2], "n_tiles": buf[3]}
+        return {"workgroups": buf[0], "tile_multiple": buf[1], "us_per_launch": buf[2],
+                "schedule": "dynamic" if buf[3] else "static"}
 
     def __call__(self, t, out=None):
         assert t.shape == (self.n_obj, self.n_t)

@@ -29,28 +29,29 @@ namespace {
 constexpr int kNurbsP = 3;
 
 struct ClassInfo {
-    int32_t kind;     // 0 Bezier, 1 rational, 2 NURBS
-    int32_t degree;   // 1..15 (3 for NURBS)
-    int32_t first;    // first slot of the class in perm
-    int32_t count;    // objects in the class
+    int32_t kind;       // 0 Bezier, 1 rational, 2 NURBS
+    int32_t degree;     // 1..15 (3 for NURBS)
+    int32_t first;      // first slot of the class in perm
+    int32_t count;      // objects in the class
+    int64_t ctrl_base;  // first element of the class in the sorted control points
+    int64_t w_base;     // first element of the class in the sorted weights (rational)
 };
 
+// A tile carries its class record, so a workgroup needs one scalar load per tile.
 struct Tile {
-    int32_t cls;
+    ClassInfo ci;
     uint32_t q0;  // first query of the tile within its class
+    uint32_t pad;
 };
 
 struct BatchArgs {
-    const void *ctrl;
-    const void *w;
-    const int64_t *cp_offset;
-    const int32_t *perm;
-    const ClassInfo *classes;
+    const void *ctrl_s;        // control points in class-sorted order (plan copy)
+    const void *w_s;           // weights of rational objects, class-sorted (plan copy)
+    const int32_t *perm;       // sorted slot -> object
     const Tile *tiles;
     uint32_t n_tiles;
-    uint32_t qpt;          // sub-tiles of kBlock queries per tile
-    const int32_t *nurbs_rank;
-    const int32_t *seg_first;  // [n_nurbs+1]
+    uint32_t qpt;              // sub-tiles of kBlock queries per tile
+    const int32_t *seg_first;  // [n_nurbs+1], NURBS ranked in sorted order
     const float *brk;          // breakpoints, nseg+1 per NURBS, at seg_first[r] + r
     const float *seg;          // [n_segs][4][dim+1] homogeneous
     const float *t;
@@ -60,6 +61,7 @@ struct BatchArgs {
     FastDiv div_nt;
     int dim;
     unsigned int *counters;    // [0] next tile, [1] finished workgroups
+    int dynamic;               // 1: atomic tile counter, 0: static round robin
 };
 
 // Load n contiguous storage elements as FP32.
@@ -158,75 +160,116 @@ __device__ __forceinline__ void eval_nurbs_query(const float *__restrict__ brk, 
         if (k < dim) st_stream(out + k * plane + q, H[k] / H[dim]);
 }
 
-template <int D, bool RAT, int F, typename T>
-__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const ClassInfo &ci, uint32_t q0) {
-    const uint32_t nq = static_cast<uint32_t>(ci.count) * a.n_t;
-    for (uint32_t s = 0; s < a.qpt; ++s) {
-        const uint32_t qi = q0 + s * kBlock + threadIdx.x;
-        if (qi >= nq) return;
-        const uint32_t slot = fdiv(qi, a.div_nt);
-        const uint32_t j = qi - slot * a.n_t;
-        const int64_t o = a.perm[ci.first + slot];
-        const int64_t q = o * a.n_t + j;
-        const float t = a.t[q];
-        const int64_t cp = a.cp_offset[o];
-        const T *P = static_cast<const T *>(a.ctrl) + cp * a.dim;
-        const T *W = RAT ? static_cast<const T *>(a.w) + cp : nullptr;
-        eval_curve_query<D, RAT, F, T>(P, W, a.dim, t, a.out, a.plane, q);
+constexpr int kMaxQpt = 4;
+
+// Index, permutation and parameter loads of every sub-tile are issued before
+// any evaluation, so their latencies overlap instead of adding up.  Tail lanes
+// re-read the last query of the tile and store nothing.
+struct SubTileQueries {
+    uint32_t slot[kMaxQpt], j[kMaxQpt];
+    int64_t q[kMaxQpt];
+    float t[kMaxQpt];
+    bool ok[kMaxQpt];
+};
+
+__device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile &tl, SubTileQueries &sq) {
+    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
+        sq.ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
+        const uint32_t qc = min(qi, nq - 1);
+        sq.slot[s] = fdiv(qc, a.div_nt);
+        sq.j[s] = qc - sq.slot[s] * a.n_t;
+    }
+    int64_t o[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) o[s] = a.perm[tl.ci.first + sq.slot[s]];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        sq.q[s] = o[s] * a.n_t + sq.j[s];
+        sq.t[s] = a.t[sq.q[s]];
     }
 }
 
-__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const ClassInfo &ci, uint32_t q0) {
-    const uint32_t nq = static_cast<uint32_t>(ci.count) * a.n_t;
-    for (uint32_t s = 0; s < a.qpt; ++s) {
-        const uint32_t qi = q0 + s * kBlock + threadIdx.x;
-        if (qi >= nq) return;
-        const uint32_t slot = fdiv(qi, a.div_nt);
-        const uint32_t j = qi - slot * a.n_t;
-        const int64_t o = a.perm[ci.first + slot];
-        const int64_t q = o * a.n_t + j;
-        const int r = a.nurbs_rank[o];
+template <int D, bool RAT, int F, typename T>
+__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &tl) {
+    SubTileQueries sq;
+    prefetch_queries(a, tl, sq);
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!sq.ok[s]) continue;
+        // the control points' address needs no index load: classes are contiguous
+        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(sq.slot[s]) * (D + 1) * a.dim;
+        const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1)
+                         : nullptr;
+        eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], a.out, a.plane, sq.q[s]);
+    }
+}
+
+__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl) {
+    SubTileQueries sq;
+    prefetch_queries(a, tl, sq);
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!sq.ok[s]) continue;
+        const uint32_t r = sq.slot[s];  // NURBS rank = slot in the class
         const int s0 = a.seg_first[r], nseg = a.seg_first[r + 1] - s0;
-        eval_nurbs_query(a.brk + s0 + r, a.seg + static_cast<size_t>(s0) * 4 * (a.dim + 1), nseg, a.dim, a.t[q], a.out,
-                         a.plane, q);
+        eval_nurbs_query(a.brk + s0 + r, a.seg + static_cast<size_t>(s0) * 4 * (a.dim + 1), nseg, a.dim, sq.t[s],
+                         a.out, a.plane, sq.q[s]);
     }
 }
 
 template <bool RAT, int F, typename T>
-__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const ClassInfo &ci, uint32_t q0) {
-    switch (ci.degree) {
-        case 1: run_curve_tile<1, RAT, F, T>(a, ci, q0); break;
-        case 2: run_curve_tile<2, RAT, F, T>(a, ci, q0); break;
-        case 3: run_curve_tile<3, RAT, F, T>(a, ci, q0); break;
-        case 4: run_curve_tile<4, RAT, F, T>(a, ci, q0); break;
-        case 5: run_curve_tile<5, RAT, F, T>(a, ci, q0); break;
-        case 6: run_curve_tile<6, RAT, F, T>(a, ci, q0); break;
-        case 7: run_curve_tile<7, RAT, F, T>(a, ci, q0); break;
-        case 8: run_curve_tile<8, RAT, F, T>(a, ci, q0); break;
-        case 9: run_curve_tile<9, RAT, F, T>(a, ci, q0); break;
-        case 10: run_curve_tile<10, RAT, F, T>(a, ci, q0); break;
-        case 11: run_curve_tile<11, RAT, F, T>(a, ci, q0); break;
-        case 12: run_curve_tile<12, RAT, F, T>(a, ci, q0); break;
-        case 13: run_curve_tile<13, RAT, F, T>(a, ci, q0); break;
-        case 14: run_curve_tile<14, RAT, F, T>(a, ci, q0); break;
-        default: run_curve_tile<15, RAT, F, T>(a, ci, q0); break;
+__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &tl) {
+    switch (tl.ci.degree) {
+        case 1: run_curve_tile<1, RAT, F, T>(a, tl); break;
+        case 2: run_curve_tile<2, RAT, F, T>(a, tl); break;
+        case 3: run_curve_tile<3, RAT, F, T>(a, tl); break;
+        case 4: run_curve_tile<4, RAT, F, T>(a, tl); break;
+        case 5: run_curve_tile<5, RAT, F, T>(a, tl); break;
+        case 6: run_curve_tile<6, RAT, F, T>(a, tl); break;
+        case 7: run_curve_tile<7, RAT, F, T>(a, tl); break;
+        case 8: run_curve_tile<8, RAT, F, T>(a, tl); break;
+        case 9: run_curve_tile<9, RAT, F, T>(a, tl); break;
+        case 10: run_curve_tile<10, RAT, F, T>(a, tl); break;
+        case 11: run_curve_tile<11, RAT, F, T>(a, tl); break;
+        case 12: run_curve_tile<12, RAT, F, T>(a, tl); break;
+        case 13: run_curve_tile<13, RAT, F, T>(a, tl); break;
+        case 14: run_curve_tile<14, RAT, F, T>(a, tl); break;
+        default: run_curve_tile<15, RAT, F, T>(a, tl); break;
     }
 }
 
 template <int F, typename T>
+__device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) {
+    const Tile tl = a.tiles[tile];
+    if (tl.ci.kind == 0) dispatch_degree<false, F, T>(a, tl);
+    else if (tl.ci.kind == 1) dispatch_degree<true, F, T>(a, tl);
+    else run_nurbs_tile(a, tl);
+}
+
+// Dynamic schedule: workgroups pull tiles from an atomic counter (the next
+// index is fetched while the current tile is evaluated).  Static schedule:
+// workgroup g takes tiles g, g+G, g+2G, ... -- balanced because tiles are
+// ordered by cost and every tile of a class costs the same.
+template <int F, typename T>
 __global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
+    if (!a.dynamic) {
+        for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T>(a, tile);
+        return;
+    }
     __shared__ unsigned int s_tile;
-    for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
+    __syncthreads();
+    unsigned int tile = s_tile;
+    __syncthreads();
+    while (tile < a.n_tiles) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
+        run_tile<F, T>(a, tile);
         __syncthreads();
-        const unsigned int tile = s_tile;
+        tile = s_tile;
         __syncthreads();
-        if (tile >= a.n_tiles) break;
-        const Tile tl = a.tiles[tile];
-        const ClassInfo ci = a.classes[tl.cls];
-        if (ci.kind == 0) dispatch_degree<false, F, T>(a, ci, tl.q0);
-        else if (ci.kind == 1) dispatch_degree<true, F, T>(a, ci, tl.q0);
-        else run_nurbs_tile(a, ci, tl.q0);
     }
     // every workgroup has seen the end of the tile list; the last one to get
     // here resets both counters for the next launch
@@ -237,6 +280,30 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
             atomicExch(&a.counters[1], 0u);
         }
     }
+}
+
+// Plan-time gather of control points (and weights of rational objects) into
+// class-sorted, contiguous order: sorted object i of class c lands at
+// ctrl_base(c) + slot*(d+1)*dim.  One thread per sorted object.
+template <typename U>
+__global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n_sorted, const int32_t *__restrict__ perm,
+                                                          const int64_t *__restrict__ cp_offset,
+                                                          const ClassInfo *__restrict__ classes, int n_classes, int dim,
+                                                          const U *__restrict__ ctrl, const U *__restrict__ w,
+                                                          U *__restrict__ ctrl_s, U *__restrict__ w_s) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n_sorted) return;
+    int c = 0;
+    while (c + 1 < n_classes && classes[c + 1].first <= i) ++c;
+    const ClassInfo ci = classes[c];
+    if (ci.kind == 2) return;
+    const int64_t slot = i - ci.first, o = perm[i];
+    const int n = (ci.degree + 1) * dim;
+    const U *src = ctrl + cp_offset[o] * dim;
+    U *dst = ctrl_s + ci.ctrl_base + slot * n;
+    for (int e = 0; e < n; ++e) dst[e] = src[e];
+    if (ci.kind == 1)
+        for (int e = 0; e <= ci.degree; ++e) w_s[ci.w_base + slot * (ci.degree + 1) + e] = w[cp_offset[o] + e];
 }
 
 // Bezier extraction of one clamped cubic NURBS by knot insertion: every
@@ -321,27 +388,25 @@ using namespace bzi;
 struct bz_plan_s {
     int64_t n_obj = 0, n_t = 0;
     int dim = 0, dtype = 0, method = 0;
-    const void *ctrl = nullptr, *w = nullptr;  // caller-owned storage (must outlive the plan)
-    // device copies owned by the plan
-    int64_t *cp_offset = nullptr;
+    // device buffers owned by the plan
+    void *ctrl_s = nullptr, *w_s = nullptr;
     int32_t *perm = nullptr;
-    ClassInfo *classes = nullptr;
     Tile *tiles = nullptr;
-    int32_t *nurbs_rank = nullptr, *seg_first = nullptr;
+    int32_t *seg_first = nullptr;
     float *brk = nullptr, *seg = nullptr;
     unsigned int *counters = nullptr;
-    int n_classes = 0;
+    std::vector<ClassInfo> classes;
     uint32_t n_tiles = 0, qpt = 1;
     int64_t n_segs = 0;
     uint32_t workgroups = 0;
+    int dynamic = 1;
 };
 
 namespace {
 
 void plan_free(bz_plan_s *p) {
     if (!p) return;
-    void *bufs[] = {p->cp_offset, p->perm, p->classes, p->tiles, p->nurbs_rank, p->seg_first, p->brk, p->seg,
-                    p->counters};
+    void *bufs[] = {p->ctrl_s, p->w_s, p->perm, p->tiles, p->seg_first, p->brk, p->seg, p->counters};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -357,17 +422,16 @@ int dev_upload(X **dst, const std::vector<X> &src, hipStream_t s) {
     return BZ_OK;
 }
 
-int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups, uint32_t qpt) {
+int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups, uint32_t qpt,
+                 int dynamic) {
     BatchArgs a;
-    a.ctrl = p->ctrl;
-    a.w = p->w;
-    a.cp_offset = p->cp_offset;
+    a.dynamic = dynamic;
+    a.ctrl_s = p->ctrl_s;
+    a.w_s = p->w_s;
     a.perm = p->perm;
-    a.classes = p->classes;
     a.tiles = p->tiles;
     a.n_tiles = p->n_tiles;
     a.qpt = qpt;
-    a.nurbs_rank = p->nurbs_rank;
     a.seg_first = p->seg_first;
     a.brk = p->brk;
     a.seg = p->seg;
@@ -395,7 +459,8 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
 }
 
 // Rebuild the tile list for `qpt` sub-tiles per tile (heaviest class first).
-int build_tiles(bz_plan_s *p, const std::vector<ClassInfo> &cls, uint32_t qpt, hipStream_t s) {
+int build_tiles(bz_plan_s *p, uint32_t qpt, hipStream_t s) {
+    const std::vector<ClassInfo> &cls = p->classes;
     std::vector<int> order(cls.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -406,8 +471,9 @@ int build_tiles(bz_plan_s *p, const std::vector<ClassInfo> &cls, uint32_t qpt, h
     const uint64_t span = static_cast<uint64_t>(kBlock) * qpt;
     for (int c : order) {
         const uint64_t nq = static_cast<uint64_t>(cls[c].count) * p->n_t;
-        for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{c, static_cast<uint32_t>(q0)});
+        for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), 0});
     }
+    if (p->tiles) BZ_CHECK_HIP(hipStreamSynchronize(s));
     if (p->tiles) BZ_CHECK_HIP(hipFree(p->tiles));
     p->tiles = nullptr;
     int rc = dev_upload(&p->tiles, tiles, s);
@@ -465,9 +531,36 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         if (need_w && !w) return fail(BZ_ERR_NULL, "%s: weights are required (rational or NURBS objects)", fn);
         if (!aligned(ctrl, dtype_size(dtype)) || !aligned(w, dtype_size(dtype)))
             return fail(BZ_ERR_ALIGN, "%s: misaligned ctrl or w", fn);
-        // NURBS knot vectors: read, validate (clamped, non-decreasing), count segments
+        // class list and permutation (stable counting sort by kind, degree)
+        std::vector<ClassInfo> cls;
+        std::vector<int32_t> cls_of_key(32, -1);
+        int32_t first = 0;
+        int64_t ctrl_elems = 0, w_elems = 0;
+        for (int key = 0; key < 31; ++key) {
+            if (count[key] == 0) continue;
+            ClassInfo ci;
+            ci.kind = key == 30 ? 2 : key / 15;
+            ci.degree = key == 30 ? kNurbsP : key % 15 + 1;
+            ci.first = first;
+            ci.count = static_cast<int32_t>(count[key]);
+            ci.ctrl_base = ctrl_elems;
+            ci.w_base = w_elems;
+            if (ci.kind != 2) ctrl_elems += count[key] * (ci.degree + 1) * dim;
+            if (ci.kind == 1) w_elems += count[key] * (ci.degree + 1);
+            cls_of_key[key] = static_cast<int32_t>(cls.size());
+            cls.push_back(ci);
+            first += ci.count;
+        }
+        std::vector<int32_t> perm(n_obj), fill(cls.size(), 0);
+        for (int64_t o = 0; o < n_obj; ++o) {
+            const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
+            const int c = cls_of_key[kind == 2 ? 30 : kind * 15 + deg - 1];
+            perm[cls[c].first + fill[c]++] = static_cast<int32_t>(o);
+        }
+        // NURBS (in sorted order, so a NURBS's rank is its slot in the class):
+        // read and validate the knot vectors, count segments, keep breakpoints
         std::vector<int64_t> nurbs_obj;
-        std::vector<int32_t> seg_first(1, 0), rank(n_obj, -1);
+        std::vector<int32_t> seg_first(1, 0);
         std::vector<float> brk;
         if (any_nurbs) {
             if (!knot_offset || !knots) return fail(BZ_ERR_NULL, "%s: knot_offset and knots are required for NURBS", fn);
@@ -475,11 +568,13 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             BZ_CHECK_HIP(hipMemcpyAsync(ko.data(), knot_offset, (n_obj + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
             BZ_CHECK_HIP(hipStreamSynchronize(s));
             const int64_t nk_total = ko[n_obj];
+            if (nk_total < 0 || nk_total > (int64_t(1) << 34)) return fail(BZ_ERR_SHAPE, "%s: knot_offset", fn);
             std::vector<float> U(nk_total);
             BZ_CHECK_HIP(hipMemcpyAsync(U.data(), knots, nk_total * sizeof(float), hipMemcpyDeviceToHost, s));
             BZ_CHECK_HIP(hipStreamSynchronize(s));
-            for (int64_t o = 0; o < n_obj; ++o) {
-                if ((kd[o] >> 8) != 2) continue;
+            const ClassInfo &nc = cls.back();
+            for (int32_t r = 0; r < nc.count; ++r) {
+                const int64_t o = perm[nc.first + r];
                 const int64_t ncp = cpo[o + 1] - cpo[o];
                 const int64_t nk = ko[o + 1] - ko[o];
                 if (nk != ncp + kNurbsP + 1 || ko[o] < 0 || ko[o + 1] > nk_total)
@@ -490,7 +585,6 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                 if (u[0] != u[kNurbsP] || u[nk - 1] != u[nk - 1 - kNurbsP] || !(u[kNurbsP] < u[kNurbsP + 1]) ||
                     !(u[nk - 2 - kNurbsP] < u[nk - 1 - kNurbsP]))
                     return fail(BZ_ERR_SHAPE, "%s: NURBS object %lld knot vector is not clamped with end multiplicity 4", fn, (long long)o);
-                rank[o] = static_cast<int32_t>(nurbs_obj.size());
                 nurbs_obj.push_back(o);
                 int32_t ns = 0;
                 brk.push_back(u[kNurbsP]);
@@ -502,27 +596,6 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                 seg_first.push_back(seg_first.back() + ns);
             }
         }
-        // class list and permutation (stable counting sort)
-        std::vector<ClassInfo> cls;
-        std::vector<int32_t> cls_of_key(32, -1);
-        int32_t first = 0;
-        for (int key = 0; key < 31; ++key) {
-            if (count[key] == 0) continue;
-            ClassInfo ci;
-            ci.kind = key == 30 ? 2 : key / 15;
-            ci.degree = key == 30 ? kNurbsP : key % 15 + 1;
-            ci.first = first;
-            ci.count = static_cast<int32_t>(count[key]);
-            cls_of_key[key] = static_cast<int32_t>(cls.size());
-            cls.push_back(ci);
-            first += ci.count;
-        }
-        std::vector<int32_t> perm(n_obj), fill(cls.size(), 0);
-        for (int64_t o = 0; o < n_obj; ++o) {
-            const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
-            const int c = cls_of_key[kind == 2 ? 30 : kind * 15 + deg - 1];
-            perm[cls[c].first + fill[c]++] = static_cast<int32_t>(o);
-        }
         bz_plan_s *p = new (std::nothrow) bz_plan_s();
         if (!p) return fail(BZ_ERR_NOMEM, "%s: host allocation", fn);
         p->n_obj = n_obj;
@@ -530,25 +603,48 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         p->dim = dim;
         p->dtype = dtype;
         p->method = method;
-        p->ctrl = ctrl;
-        p->w = w;
-        p->n_classes = static_cast<int>(cls.size());
+        p->classes = cls;
         p->n_segs = seg_first.back();
-        int rc = dev_upload(&p->cp_offset, cpo, s);
-        if (!rc) rc = dev_upload(&p->perm, perm, s);
-        if (!rc) rc = dev_upload(&p->classes, cls, s);
-        if (!rc) rc = dev_upload(&p->nurbs_rank, rank, s);
+        const int es = dtype_size(dtype);
+        auto dmalloc = [&](void **ptr, size_t bytes) -> int {
+            hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+            if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: device allocation of %zu bytes", fn, bytes);
+            return e == hipSuccess ? BZ_OK : hip_fail(e, "hipMalloc");
+        };
+        int rc = dev_upload(&p->perm, perm, s);
         if (!rc) rc = dev_upload(&p->seg_first, seg_first, s);
         if (!rc) rc = dev_upload(&p->brk, brk, s);
-        if (!rc) rc = build_tiles(p, cls, 1, s);
+        if (!rc) rc = build_tiles(p, 1, s);
+        if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);
+        if (!rc) rc = dmalloc(&p->w_s, w_elems * es);
+        if (!rc) rc = dmalloc(reinterpret_cast<void **>(&p->seg), std::max<int64_t>(p->n_segs, 1) * 4 * (dim + 1) * sizeof(float));
         if (!rc) {
-            hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->seg), std::max<int64_t>(p->n_segs, 1) * 4 * (dim + 1) * sizeof(float));
-            if (e != hipSuccess) rc = e == hipErrorOutOfMemory ? fail(BZ_ERR_NOMEM, "%s: segments", fn) : hip_fail(e, "hipMalloc");
+            rc = dmalloc(reinterpret_cast<void **>(&p->counters), 2 * sizeof(unsigned int));
+            if (!rc && hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned int), s) != hipSuccess) rc = fail(BZ_ERR_HIP, "%s: memset", fn);
         }
-        if (!rc) {
-            hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->counters), 2 * sizeof(unsigned int));
-            if (e == hipSuccess) e = hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned int), s);
-            if (e != hipSuccess) rc = hip_fail(e, "counters");
+        if (!rc && n_obj > 0) {  // class-sorted copies of control points and weights
+            ClassInfo *cls_d = nullptr;
+            rc = dev_upload(&cls_d, cls, s);
+            if (!rc) {
+                const int64_t n_sorted = cls.back().kind == 2 ? cls.back().first : n_obj;
+                const uint32_t blocks = static_cast<uint32_t>((n_sorted + kBlock - 1) / kBlock);
+                if (n_sorted > 0) {
+                    if (es == 4)
+                        hipLaunchKernelGGL((k_gather_sorted<uint32_t>), dim3(blocks), dim3(kBlock), 0, s, n_sorted, p->perm,
+                                           cp_offset, cls_d, static_cast<int>(cls.size()), dim,
+                                           static_cast<const uint32_t *>(ctrl), static_cast<const uint32_t *>(w),
+                                           static_cast<uint32_t *>(p->ctrl_s), static_cast<uint32_t *>(p->w_s));
+                    else
+                        hipLaunchKernelGGL((k_gather_sorted<uint16_t>), dim3(blocks), dim3(kBlock), 0, s, n_sorted, p->perm,
+                                           cp_offset, cls_d, static_cast<int>(cls.size()), dim,
+                                           static_cast<const uint16_t *>(ctrl), static_cast<const uint16_t *>(w),
+                                           static_cast<uint16_t *>(p->ctrl_s), static_cast<uint16_t *>(p->w_s));
+                }
+                hipError_t e = hipGetLastError();
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                (void)hipFree(cls_d);
+                if (e != hipSuccess) rc = hip_fail(e, "k_gather_sorted");
+            }
         }
         if (!rc && !nurbs_obj.empty()) {
             int64_t *nobj_d = nullptr;
@@ -557,16 +653,16 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                 const int nn = static_cast<int>(nurbs_obj.size());
                 const uint32_t blocks = (nn + kBlock - 1) / kBlock;
                 if (dtype == BZ_F32)
-                    hipLaunchKernelGGL((k_nurbs_extract<float>), dim3(blocks), dim3(kBlock), 0, s, nn, nobj_d, p->cp_offset,
+                    hipLaunchKernelGGL((k_nurbs_extract<float>), dim3(blocks), dim3(kBlock), 0, s, nn, nobj_d, cp_offset,
                                        knot_offset, static_cast<const float *>(ctrl), static_cast<const float *>(w), knots,
                                        p->seg_first, dim, p->seg);
                 else if (dtype == BZ_F16)
                     hipLaunchKernelGGL((k_nurbs_extract<_Float16>), dim3(blocks), dim3(kBlock), 0, s, nn, nobj_d,
-                                       p->cp_offset, knot_offset, static_cast<const _Float16 *>(ctrl),
+                                       cp_offset, knot_offset, static_cast<const _Float16 *>(ctrl),
                                        static_cast<const _Float16 *>(w), knots, p->seg_first, dim, p->seg);
                 else
                     hipLaunchKernelGGL((k_nurbs_extract<bf16_t>), dim3(blocks), dim3(kBlock), 0, s, nn, nobj_d,
-                                       p->cp_offset, knot_offset, static_cast<const bf16_t *>(ctrl),
+                                       cp_offset, knot_offset, static_cast<const bf16_t *>(ctrl),
                                        static_cast<const bf16_t *>(w), knots, p->seg_first, dim, p->seg);
                 hipError_t e = hipGetLastError();
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -599,7 +695,7 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream) {
         if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
         if (!t || !out) return fail(BZ_ERR_NULL, "bz_batch_eval: t and out are required");
         if (!aligned(t, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "bz_batch_eval: misaligned");
-        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->qpt);
+        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->qpt, plan->dynamic);
     });
 }
 
@@ -613,46 +709,48 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
         BZ_CHECK_HIP(hipEventCreate(&e0));
         BZ_CHECK_HIP(hipEventCreate(&e1));
         const uint32_t base = plan->workgroups;
-        std::vector<ClassInfo> cls(plan->n_classes);
-        BZ_CHECK_HIP(hipMemcpy(cls.data(), plan->classes, cls.size() * sizeof(ClassInfo), hipMemcpyDeviceToHost));
         float best = 1e30f;
         uint32_t best_wg = base, best_q = plan->qpt;
+        int best_dyn = plan->dynamic;
         const uint32_t qpts[] = {1, 2, 4};
         const double wgf[] = {0.5, 1.0, 2.0};
         for (uint32_t q : qpts) {
-            int rc = build_tiles(plan, cls, q, s);
+            int rc = build_tiles(plan, q, s);
             if (rc) return rc;
-            for (double f : wgf) {
-                const uint32_t wg = std::max<uint32_t>(1, static_cast<uint32_t>(base * f));
-                rc = launch_batch(plan, t, out, s, wg, q);  // warm-up
-                if (rc) return rc;
-                BZ_CHECK_HIP(hipEventRecord(e0, s));
-                for (int r = 0; r < 5; ++r) {
-                    rc = launch_batch(plan, t, out, s, wg, q);
+            for (int dyn = 1; dyn >= 0; --dyn)
+                for (double f : wgf) {
+                    const uint32_t wg = std::max<uint32_t>(1, static_cast<uint32_t>(base * f));
+                    rc = launch_batch(plan, t, out, s, wg, q, dyn);  // warm-up
                     if (rc) return rc;
+                    BZ_CHECK_HIP(hipEventRecord(e0, s));
+                    for (int r = 0; r < 5; ++r) {
+                        rc = launch_batch(plan, t, out, s, wg, q, dyn);
+                        if (rc) return rc;
+                    }
+                    BZ_CHECK_HIP(hipEventRecord(e1, s));
+                    BZ_CHECK_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    BZ_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) {
+                        best = ms;
+                        best_wg = wg;
+                        best_q = q;
+                        best_dyn = dyn;
+                    }
                 }
-                BZ_CHECK_HIP(hipEventRecord(e1, s));
-                BZ_CHECK_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                BZ_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) {
-                    best = ms;
-                    best_wg = wg;
-                    best_q = q;
-                }
-            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        int rc = build_tiles(plan, cls, best_q, s);
+        int rc = build_tiles(plan, best_q, s);
         if (rc) return rc;
         plan->workgroups = best_wg;
+        plan->dynamic = best_dyn;
         BZ_CHECK_HIP(hipStreamSynchronize(s));
         if (best4) {
             best4[0] = best_wg;
             best4[1] = best_q;
             best4[2] = static_cast<int64_t>(best * 1000.0f / 5.0f);  // microseconds per launch
-            best4[3] = plan->n_tiles;
+            best4[3] = best_dyn;
         }
         return BZ_OK;
     });
@@ -660,7 +758,7 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
 
 int bz_batch_plan_info(bz_plan plan, int64_t *info4) {
     if (!plan || !info4) return fail(BZ_ERR_NULL, "bz_batch_plan_info: plan and info are required");
-    info4[0] = plan->n_classes;
+    info4[0] = static_cast<int64_t>(plan->classes.size());
     info4[1] = plan->n_tiles;
     info4[2] = plan->n_segs;
     info4[3] = plan->workgroups;

@@ -165,11 +165,15 @@ struct CurveArgs {
     uint32_t *n_fixed;     // nullable device counter
 };
 
-template <int D, int DIM, int F, bool RAT, typename T>
+// UNI: n_t is a multiple of 64, so each wavefront evaluates one curve; its
+// index is made wave-uniform and the control points come in through scalar
+// loads instead of 64 identical vector loads.
+template <int D, int DIM, int F, bool RAT, typename T, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_curves(CurveArgs a) {
     const uint32_t ql = blockIdx.x * kBlock + threadIdx.x;
     if (ql >= a.nq) return;
-    const uint32_t cl = fdiv(ql, a.div_nt);
+    uint32_t cl = fdiv(ql, a.div_nt);
+    if constexpr (UNI) cl = __builtin_amdgcn_readfirstlane(cl);
     const uint32_t j = ql - cl * a.div_nt.d;
     const int64_t qg = a.q0 + ql;
     const float t = a.per_object ? a.t[qg] : a.t[j];
@@ -240,18 +244,24 @@ __global__ __launch_bounds__(kBlock) void k_to_seiler(const T *__restrict__ ctrl
 }
 
 // ---------------------------------------------------------------- host
-template <int F, bool RAT, typename T, int D>
-int launch_curves_d(int dim, const CurveArgs &a, hipStream_t s) {
+template <int F, bool RAT, typename T, int D, bool UNI>
+int launch_curves_du(int dim, const CurveArgs &a, hipStream_t s) {
     const uint32_t blocks = (a.nq + kBlock - 1) / kBlock;
     switch (dim) {
-        case 1: hipLaunchKernelGGL((k_curves<D, 1, F, RAT, T>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_curves<D, 2, F, RAT, T>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_curves<D, 3, F, RAT, T>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_curves<D, 4, F, RAT, T>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_curves<D, 1, F, RAT, T, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_curves<D, 2, F, RAT, T, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_curves<D, 3, F, RAT, T, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_curves<D, 4, F, RAT, T, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
         default: return fail(BZ_ERR_SHAPE, "dim %d out of range", dim);
     }
     BZ_CHECK_LAUNCH("k_curves");
     return BZ_OK;
+}
+
+template <int F, bool RAT, typename T, int D>
+int launch_curves_d(int dim, const CurveArgs &a, hipStream_t s) {
+    if (a.div_nt.d % 64 == 0) return launch_curves_du<F, RAT, T, D, true>(dim, a, s);
+    return launch_curves_du<F, RAT, T, D, false>(dim, a, s);
 }
 
 // Launch one chunk of curve queries for form F (rational when RAT) with
