@@ -54,26 +54,30 @@ __device__ __forceinline__ float dot_basis(const float (&B)[D + 1], const float 
 
 // Seiler difference terms by peeling (Sec. 3.1): Q - L(Q_0,Q_n,t) = st Q'
 // with Q'_{i-1} = (Q_i - ((n-i)/n)Q_0 - (i/n)Q_n) * n(n-1)/(i(n-i)).
-// Output order [b0, bd, d1, d_{d-1}, d2, d_{d-2}, ...].  Computed in FP64
-// (the terms grow like C(d, d/2) and peeling cancels) and rounded once; FP64
-// FMAs issue at the same vector rate as unpacked FP32 ones on gfx950.
-template <int D>
+// Output order [b0, bd, d1, d_{d-1}, d2, d_{d-2}, ...].  The terms grow like
+// C(d, d/2) and peeling cancels, so the stand-alone conversion works in FP64
+// (Acc = double) and rounds once; evaluations that derive the terms on the
+// fly use FP32 up to degree 7, where its error stays far below the tolerance.
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <int D, typename Acc = double>
 __device__ __forceinline__ void seiler_terms(const float (&b)[D + 1], float (&sc)[D + 1]) {
-    double Q[D + 1];
+    Acc Q[D + 1];
 #pragma unroll
-    for (int i = 0; i <= D; ++i) Q[i] = static_cast<double>(b[i]);
+    for (int i = 0; i <= D; ++i) Q[i] = static_cast<Acc>(b[i]);
     sc[0] = b[0];
     sc[1] = b[D];
     int pos = 2;
 #pragma unroll
     for (int n = D; n >= 2; n -= 2) {
-        double R[D + 1];
+        Acc R[D + 1];
 #pragma unroll
         for (int i = 1; i <= n - 1; ++i) {
-            const double a0 = static_cast<double>(n - i) / static_cast<double>(n);
-            const double a1 = static_cast<double>(i) / static_cast<double>(n);
-            const double sc_f = static_cast<double>(n * (n - 1)) / static_cast<double>(i * (n - i));
-            const double r = Q[i] - __builtin_fma(a0, Q[0], a1 * Q[n]);
+            const Acc a0 = static_cast<Acc>(n - i) / static_cast<Acc>(n);
+            const Acc a1 = static_cast<Acc>(i) / static_cast<Acc>(n);
+            const Acc sc_f = static_cast<Acc>(n * (n - 1)) / static_cast<Acc>(i * (n - i));
+            const Acc r = Q[i] - fma_acc(a0, Q[0], a1 * Q[n]);
             R[i - 1] = r * sc_f;
         }
 #pragma unroll
@@ -111,7 +115,8 @@ __device__ __forceinline__ void eval_channels(const float (&b)[CH][D + 1], float
         for (int k = 0; k < CH; ++k) {
             if constexpr (F == FORM_SEILER) {
                 float sc[D + 1];
-                seiler_terms<D>(b[k], sc);
+                if constexpr (D <= 7) seiler_terms<D, float>(b[k], sc);
+                else seiler_terms<D, double>(b[k], sc);
                 r[k] = eval_seiler<D>(sc, t, st);
             } else {
                 r[k] = eval_seiler<D>(b[k], t, st);

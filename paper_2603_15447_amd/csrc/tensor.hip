@@ -6,8 +6,8 @@
 //                  column b, contracts the control net with the v basis once
 //                  (isoline control points R_i(v_b)) and then needs only the
 //                  u basis and du+1 FMAs per coordinate for each of its points.
-//  k_tensor_points one object per workgroup, random (u,v[,w]) per query,
-//                  separable contraction w -> v -> u.
+//  k_tensor_points one object per wavefront, random (u,v[,w]) per query,
+//                  4 queries per lane, separable contraction w -> v -> u.
 //  k_tensor_mfma   bicubic 32x32 grids as a dense contraction on the matrix
 //                  cores: D[(patch,coord)][grid pt] = P[(patch,coord)][16] x
 //                  K[16][grid pt] with K the Kronecker product of the u and v
@@ -78,39 +78,60 @@ __global__ __launch_bounds__(kBlock) void k_tensor_grid(const T *__restrict__ ct
 }
 
 // ------------------------------------------------------------------ VALU points
+// One wavefront per object, 4 queries per lane at a time: the object's
+// control points are wave-uniform (scalar loads into SGPRs) and each one
+// feeds the FMAs of 4 queries.  Separable contraction w -> v -> u.
+constexpr int kPtsQ = 4;
+
 template <int DU, int DV, int DW, int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_tensor_points(const T *__restrict__ ctrl, const float *__restrict__ uvw,
-                                                          int64_t n_per, float *__restrict__ out, int64_t plane,
-                                                          int64_t o0) {
+                                                          int64_t n_per, uint32_t n_obj, float *__restrict__ out,
+                                                          int64_t plane, int64_t o0) {
     constexpr int NCP = (DU + 1) * (DV + 1) * (DW + 1);
     constexpr int NPAR = DW > 0 ? 3 : 2;
-    const uint32_t o = blockIdx.x;
+    const uint32_t o = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    if (o >= n_obj) return;
+    const int lane = threadIdx.x & 63;
     const T *__restrict__ P = ctrl + static_cast<size_t>(o) * DIM * NCP;
-    for (int64_t j = threadIdx.x; j < n_per; j += kBlock) {
-        const int64_t q = (o0 + o) * n_per + j;
-        const float *__restrict__ p = uvw + q * NPAR;
-        float Bu[DU + 1], Bv[DV + 1], Bw[DW + 1];
-        basis_at<DU>(p[0], Bu);
-        basis_at<DV>(p[1], Bv);
-        if constexpr (DW > 0) basis_at<DW>(p[2], Bw);
-        else Bw[0] = 1.0f;
+    for (int64_t j0 = 0; j0 < n_per; j0 += 64 * kPtsQ) {
+        float Bu[kPtsQ][DU + 1], Bv[kPtsQ][DV + 1], Bw[kPtsQ][DW + 1];
+        int64_t q[kPtsQ];
+        bool ok[kPtsQ];
+#pragma unroll
+        for (int s = 0; s < kPtsQ; ++s) {
+            const int64_t j = j0 + s * 64 + lane;
+            ok[s] = j < n_per;
+            q[s] = (o0 + o) * n_per + (ok[s] ? j : n_per - 1);
+            const float *__restrict__ p = uvw + q[s] * NPAR;
+            basis_at<DU>(p[0], Bu[s]);
+            basis_at<DV>(p[1], Bv[s]);
+            if constexpr (DW > 0) basis_at<DW>(p[2], Bw[s]);
+            else Bw[s][0] = 1.0f;
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            float Ri[DU + 1];
+            float acc[kPtsQ] = {};
 #pragma unroll
             for (int i = 0; i <= DU; ++i) {
-                float Qj[DV + 1];
+                float Ri[kPtsQ] = {};
 #pragma unroll
                 for (int jj = 0; jj <= DV; ++jj) {
-                    const int base = c * NCP + (i * (DV + 1) + jj) * (DW + 1);
-                    float acc = Bw[0] * to_f32<T>(P[base]);
+                    float Qj[kPtsQ] = {};
 #pragma unroll
-                    for (int k = 1; k <= DW; ++k) acc = __builtin_fmaf(Bw[k], to_f32<T>(P[base + k]), acc);
-                    Qj[jj] = acc;
+                    for (int k = 0; k <= DW; ++k) {
+                        const float pv = to_f32<T>(P[c * NCP + (i * (DV + 1) + jj) * (DW + 1) + k]);
+#pragma unroll
+                        for (int s = 0; s < kPtsQ; ++s) Qj[s] = __builtin_fmaf(Bw[s][k], pv, Qj[s]);
+                    }
+#pragma unroll
+                    for (int s = 0; s < kPtsQ; ++s) Ri[s] = __builtin_fmaf(Bv[s][jj], Qj[s], Ri[s]);
                 }
-                Ri[i] = dot_basis<DV>(Bv, Qj);
+#pragma unroll
+                for (int s = 0; s < kPtsQ; ++s) acc[s] = __builtin_fmaf(Bu[s][i], Ri[s], acc[s]);
             }
-            st_stream(out + c * plane + q, dot_basis<DU>(Bu, Ri));
+#pragma unroll
+            for (int s = 0; s < kPtsQ; ++s)
+                if (ok[s]) st_stream(out + c * plane + q[s], acc[s]);
         }
     }
 }
@@ -246,13 +267,14 @@ int launch_grid(int du, int dv, int dim, const void *ctrl, int nu, int nv, float
 
 template <typename T, int DU, int DV, int DW>
 int launch_pts3(int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane, int64_t o0,
-                uint32_t blocks, hipStream_t s) {
+                uint32_t n_obj, hipStream_t s) {
     const T *p = static_cast<const T *>(ctrl);
+    const uint32_t blocks = (n_obj + kBlock / 64 - 1) / (kBlock / 64);
     switch (dim) {
-        case 1: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 1, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
-        case 2: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 2, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
-        case 3: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 3, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
-        default: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 4, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, out, plane, o0); break;
+        case 1: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 1, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
+        case 2: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 2, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
+        case 3: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 3, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
+        default: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 4, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
     }
     return BZ_OK;
 }
