@@ -13,10 +13,40 @@
 namespace bzi {
 namespace {
 
+// Sum over the 64 lanes: a DPP butterfly inside each 16-lane row (swap
+// neighbours, swap pairs, mirror the 8-lane halves, mirror the row) leaves
+// every lane holding its row's sum; the four row sums are then read lane by
+// lane.  The result is wave-uniform.  No LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);  // row_half_mirror
+    v += dpp_mov<0x140>(v);  // row_mirror
+    const int b = __builtin_bit_cast(int, v);
+    return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16))) +
+           (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48)));
+}
+
+// Sums over each 32-lane half of the wavefront (two curves per wave): the
+// same row butterfly, then rows 0+1 and rows 2+3.  Lanes get their half's sum.
+__device__ __forceinline__ float half_sum(float v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    const int b = __builtin_bit_cast(int, v);
+    const float lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 0)) +
+                     __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 16));
+    const float hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 32)) +
+                     __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 48));
+    return (threadIdx.x & 32) ? hi : lo;
 }
 
 struct AdjArgs {
@@ -79,7 +109,7 @@ __device__ __forceinline__ void curve_and_derivative(const float (&b)[DIM][D + 1
 template <int D, int DIM, bool RAT>
 __global__ __launch_bounds__(kBlock) void k_adjoint(AdjArgs a) {
     const int lane = threadIdx.x & 63;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t c = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
     if (c >= a.n_curves) return;
     float b[DIM][D + 1], wv[D + 1];
 #pragma unroll
@@ -154,60 +184,75 @@ __device__ __forceinline__ float adam(float p, float g, float *m, float *v, cons
 
 // Fused step: L = (1/M) sum |C(t) - y|^2, gradients, Adam on t (clamped to
 // [0,1]) and on the control points.  All gradients use the parameters as they
-// were at the start of the step.
+// were at the start of the step.  Two curves per wavefront: lanes 0-31 work
+// on curve 2w, lanes 32-63 on curve 2w+1, so one DPP butterfly reduces the
+// per-curve sums of both.
 template <int D, int DIM>
 __global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    if (c >= a.n_curves) return;
     constexpr int NP = DIM * (D + 1);
+    constexpr int CPW = NP <= 32 ? 2 : 1;  // curves per wavefront
+    constexpr int L = 64 / CPW;            // lanes per curve
+    const int lane = threadIdx.x & 63, sub = lane % L;
+    const int64_t c0 = CPW * static_cast<int64_t>(__builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    if (c0 >= a.n_curves) return;
+    const bool has1 = CPW == 2 && c0 + 1 < a.n_curves;
+    const int64_t c = (lane < L || !has1) ? c0 : c0 + 1;
+    const bool live = lane < L || has1;  // the upper half idles when the curve count is odd
+    // both curves' control points are wave-uniform: scalar loads, then a select
     float b[DIM][D + 1], wv[D + 1] = {};
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
-        for (int i = 0; i <= D; ++i) b[k][i] = a.ctrl[c * NP + k * (D + 1) + i];
+        for (int i = 0; i <= D; ++i) {
+            const float v0 = a.ctrl[c0 * NP + k * (D + 1) + i];
+            const float v1 = a.ctrl[(has1 ? c0 + 1 : c0) * NP + k * (D + 1) + i];
+            b[k][i] = lane < L ? v0 : v1;
+        }
+    const int64_t pidx = c * NP + (sub < NP ? sub : 0);
+    const float p_own = a.ctrl[pidx];
+    float m_own = a.m_c[pidx], v_own = a.v_c[pidx];
     float gb[DIM][D + 1] = {};
     float loss = 0.0f;
-    for (int64_t j = lane; j < a.n_t; j += 64) {
+    for (int64_t j = sub; live && j < a.n_t; j += L) {
         const int64_t q = c * a.n_t + j;
         const float t = a.t[q];
+        float mt = a.m_t[q], vt = a.v_t[q];
+        float yv[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) yv[k] = a.y[k * a.plane + q];
         float B[D + 1], W, C[DIM], dC[DIM];
         curve_and_derivative<D, DIM, false>(b, wv, t, B, W, C, dC);
         float dt = 0.0f;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const float r = C[k] - a.y[k * a.plane + q];
+            const float r = C[k] - yv[k];
             loss = __builtin_fmaf(r, r, loss);
             const float g = 2.0f * r * a.inv_m;
             dt = __builtin_fmaf(g, dC[k], dt);
 #pragma unroll
             for (int i = 0; i <= D; ++i) gb[k][i] = __builtin_fmaf(g, B[i], gb[k][i]);
         }
-        float mt = a.m_t[q], vt = a.v_t[q];
         float tn = adam(t, dt, &mt, &vt, a);
         tn = tn < 0.0f ? 0.0f : (tn > 1.0f ? 1.0f : tn);
         a.t[q] = tn;
         a.m_t[q] = mt;
         a.v_t[q] = vt;
     }
-    loss = wave_sum(loss);
-    if (a.loss_part && lane == 0) a.loss_part[c] = loss * a.inv_m;
-    // lane p updates control-point parameter p (NP <= 64)
+    loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
+    if (a.loss_part && sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
     float mine = 0.0f;
 #pragma unroll
     for (int k = 0; k < DIM; ++k)
 #pragma unroll
         for (int i = 0; i <= D; ++i) {
-            const float v = wave_sum(gb[k][i]);
-            if (lane == k * (D + 1) + i) mine = v;
+            const float v = CPW == 2 ? half_sum(gb[k][i]) : wave_sum(gb[k][i]);
+            if (sub == k * (D + 1) + i) mine = v;
         }
-    if (lane < NP) {
-        const int64_t idx = c * NP + lane;
-        float m = a.m_c[idx], v = a.v_c[idx];
-        const float pn = adam(a.ctrl[idx], mine, &m, &v, a);
-        a.ctrl[idx] = pn;
-        a.m_c[idx] = m;
-        a.v_c[idx] = v;
+    if (sub < NP && live) {
+        const float pn = adam(p_own, mine, &m_own, &v_own, a);
+        a.ctrl[pidx] = pn;
+        a.m_c[pidx] = m_own;
+        a.v_c[pidx] = v_own;
     }
 }
 
@@ -245,7 +290,9 @@ int launch_adj(int degree, int dim, const AdjArgs &a, hipStream_t s, uint32_t bl
 }
 
 template <int D>
-int launch_fit_d(int dim, const FitArgs &a, hipStream_t s, uint32_t blocks) {
+int launch_fit_d(int dim, const FitArgs &a, hipStream_t s) {
+    const int cpw = dim * (D + 1) <= 32 ? 2 : 1;
+    const uint32_t blocks = static_cast<uint32_t>((a.n_curves + 4 * cpw - 1) / (4 * cpw));
     switch (dim) {
         case 1: hipLaunchKernelGGL((k_fit_step<D, 1>), dim3(blocks), dim3(kBlock), 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_fit_step<D, 2>), dim3(blocks), dim3(kBlock), 0, s, a); break;
@@ -257,23 +304,22 @@ int launch_fit_d(int dim, const FitArgs &a, hipStream_t s, uint32_t blocks) {
 }
 
 int launch_fit(int degree, int dim, const FitArgs &a, hipStream_t s) {
-    const uint32_t blocks = static_cast<uint32_t>((a.n_curves + 3) / 4);
     switch (degree) {
-        case 1: return launch_fit_d<1>(dim, a, s, blocks);
-        case 2: return launch_fit_d<2>(dim, a, s, blocks);
-        case 3: return launch_fit_d<3>(dim, a, s, blocks);
-        case 4: return launch_fit_d<4>(dim, a, s, blocks);
-        case 5: return launch_fit_d<5>(dim, a, s, blocks);
-        case 6: return launch_fit_d<6>(dim, a, s, blocks);
-        case 7: return launch_fit_d<7>(dim, a, s, blocks);
-        case 8: return launch_fit_d<8>(dim, a, s, blocks);
-        case 9: return launch_fit_d<9>(dim, a, s, blocks);
-        case 10: return launch_fit_d<10>(dim, a, s, blocks);
-        case 11: return launch_fit_d<11>(dim, a, s, blocks);
-        case 12: return launch_fit_d<12>(dim, a, s, blocks);
-        case 13: return launch_fit_d<13>(dim, a, s, blocks);
-        case 14: return launch_fit_d<14>(dim, a, s, blocks);
-        default: return launch_fit_d<15>(dim, a, s, blocks);
+        case 1: return launch_fit_d<1>(dim, a, s);
+        case 2: return launch_fit_d<2>(dim, a, s);
+        case 3: return launch_fit_d<3>(dim, a, s);
+        case 4: return launch_fit_d<4>(dim, a, s);
+        case 5: return launch_fit_d<5>(dim, a, s);
+        case 6: return launch_fit_d<6>(dim, a, s);
+        case 7: return launch_fit_d<7>(dim, a, s);
+        case 8: return launch_fit_d<8>(dim, a, s);
+        case 9: return launch_fit_d<9>(dim, a, s);
+        case 10: return launch_fit_d<10>(dim, a, s);
+        case 11: return launch_fit_d<11>(dim, a, s);
+        case 12: return launch_fit_d<12>(dim, a, s);
+        case 13: return launch_fit_d<13>(dim, a, s);
+        case 14: return launch_fit_d<14>(dim, a, s);
+        default: return launch_fit_d<15>(dim, a, s);
     }
 }
 
