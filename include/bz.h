@@ -235,8 +235,13 @@ int bz_fit_adam_step(float *ctrl, float *t, const float *y, int64_t n_curves, in
                      float beta2, float eps, float *loss_part, bz_stream stream);
 
 /*
- * n_steps consecutive fitting steps (steps first_step .. first_step+n_steps-1)
- * captured once into a HIP graph and replayed as one launch on `stream`.
+ * n_steps consecutive fitting steps (steps first_step .. first_step+n_steps-1),
+ * with exactly the results of n_steps calls of bz_fit_adam_step.  Curves are
+ * optimised independently, so when n_t <= 128 (<= 256 if dim*(degree+1) > 32)
+ * all steps run in one launch with each curve's samples, parameters and Adam
+ * moments held in registers; otherwise the single steps are captured once into
+ * a HIP graph and replayed.  loss_part receives the last step's loss.
+ * Synchronises the stream.
  */
 int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
                     float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int first_step, int n_steps, float lr,

@@ -7,6 +7,7 @@
 // deterministic and needs no atomics.  dL/dt is per query and is written by
 // the lane that owns the query.
 #include <cmath>
+#include <vector>
 
 #include "curves_impl.h"
 
@@ -173,13 +174,20 @@ struct FitArgs {
     float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
 };
 
-__device__ __forceinline__ float adam(float p, float g, float *m, float *v, const FitArgs &a) {
+// Adam update (bias corrections c1 = 1 - b1^step, c2 = 1 - b2^step); every
+// rounding step is written out so that all kernels produce identical bits.
+__device__ __forceinline__ float adam_c(float p, float g, float *m, float *v, const FitArgs &a, float c1, float c2) {
     const float mm = __builtin_fmaf(a.b1, *m, (1.0f - a.b1) * g);
-    const float vv = __builtin_fmaf(a.b2, *v, (1.0f - a.b2) * g * g);
+    const float vv = __builtin_fmaf(a.b2, *v, ((1.0f - a.b2) * g) * g);
     *m = mm;
     *v = vv;
-    const float mh = mm / a.c1, vh = vv / a.c2;
-    return p - a.lr * mh / (__builtin_sqrtf(vh) + a.eps);
+    const float mh = mm / c1, vh = vv / c2;
+    const float upd = mh / (__builtin_sqrtf(vh) + a.eps);
+    return __builtin_fmaf(-a.lr, upd, p);
+}
+
+__device__ __forceinline__ float adam(float p, float g, float *m, float *v, const FitArgs &a) {
+    return adam_c(p, g, m, v, a, a.c1, a.c2);
 }
 
 // Fused step: L = (1/M) sum |C(t) - y|^2, gradients, Adam on t (clamped to
@@ -253,6 +261,143 @@ __global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
         a.ctrl[pidx] = pn;
         a.m_c[pidx] = m_own;
         a.v_c[pidx] = v_own;
+    }
+}
+
+// Many fitting steps in one launch.  Curves are optimised independently, so
+// a wavefront can keep its curves' samples, parameters and Adam moments in
+// registers across all steps: HBM is read once and written once.  Each step
+// performs exactly the arithmetic of k_fit_step, in the same order.  SPL:
+// samples per lane (n_t <= SPL * lanes per curve).  bias[step] = (c1, c2).
+template <int D, int DIM, int SPL>
+__global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__restrict__ bias, int n_steps) {
+    constexpr int NP = DIM * (D + 1);
+    constexpr int CPW = NP <= 32 ? 2 : 1;
+    constexpr int L = 64 / CPW;
+    const int lane = threadIdx.x & 63, sub = lane % L;
+    const int64_t c0 = CPW * static_cast<int64_t>(__builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    if (c0 >= a.n_curves) return;
+    const bool has1 = CPW == 2 && c0 + 1 < a.n_curves;
+    const int64_t c = (lane < L || !has1) ? c0 : c0 + 1;
+    const bool live = lane < L || has1;
+    const int base = lane < L ? 0 : L;  // first lane of this lane's curve
+    const int64_t pidx = c * NP + (sub < NP ? sub : 0);
+    float p_own = a.ctrl[pidx], m_own = a.m_c[pidx], v_own = a.v_c[pidx];
+    float ts[SPL], mts[SPL], vts[SPL], ys[SPL][DIM];
+    int64_t qs[SPL];
+    bool ok[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+        const int64_t j = sub + static_cast<int64_t>(s) * L;
+        ok[s] = live && j < a.n_t;
+        qs[s] = c * a.n_t + (ok[s] ? j : 0);
+        ts[s] = a.t[qs[s]];
+        mts[s] = a.m_t[qs[s]];
+        vts[s] = a.v_t[qs[s]];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ys[s][k] = a.y[k * a.plane + qs[s]];
+    }
+    float b[DIM][D + 1], wv[D + 1] = {};
+    float loss = 0.0f;
+    for (int step = 0; step < n_steps; ++step) {
+        // current control points of this lane's curve, from the owning lanes
+        const int pb = __builtin_bit_cast(int, p_own);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                const float lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, k * (D + 1) + i));
+                const float hi = CPW == 2 ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, L + k * (D + 1) + i)) : lo;
+                b[k][i] = base == 0 ? lo : hi;
+            }
+        const float2 bc = bias[step];
+        float gb[DIM][D + 1] = {};
+        loss = 0.0f;
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) {
+            if (!ok[s]) continue;
+            float B[D + 1], W, C[DIM], dC[DIM];
+            curve_and_derivative<D, DIM, false>(b, wv, ts[s], B, W, C, dC);
+            float dt = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const float r = C[k] - ys[s][k];
+                loss = __builtin_fmaf(r, r, loss);
+                const float g = 2.0f * r * a.inv_m;
+                dt = __builtin_fmaf(g, dC[k], dt);
+#pragma unroll
+                for (int i = 0; i <= D; ++i) gb[k][i] = __builtin_fmaf(g, B[i], gb[k][i]);
+            }
+            float tn = adam_c(ts[s], dt, &mts[s], &vts[s], a, bc.x, bc.y);
+            ts[s] = tn < 0.0f ? 0.0f : (tn > 1.0f ? 1.0f : tn);
+        }
+        loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
+        float mine = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                const float v = CPW == 2 ? half_sum(gb[k][i]) : wave_sum(gb[k][i]);
+                if (sub == k * (D + 1) + i) mine = v;
+            }
+        if (sub < NP && live) p_own = adam_c(p_own, mine, &m_own, &v_own, a, bc.x, bc.y);
+    }
+    if (a.loss_part && sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
+    if (sub < NP && live) {
+        a.ctrl[pidx] = p_own;
+        a.m_c[pidx] = m_own;
+        a.v_c[pidx] = v_own;
+    }
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+        if (ok[s]) {
+            a.t[qs[s]] = ts[s];
+            a.m_t[qs[s]] = mts[s];
+            a.v_t[qs[s]] = vts[s];
+        }
+}
+
+template <int D, int DIM>
+int launch_fit_run_dd(const FitArgs &a, const float2 *bias, int n_steps, hipStream_t s) {
+    constexpr int NP = DIM * (D + 1);
+    constexpr int L = NP <= 32 ? 32 : 64;
+    constexpr int CPW = 64 / L;
+    const uint32_t blocks = static_cast<uint32_t>((a.n_curves + 4 * CPW - 1) / (4 * CPW));
+    const int64_t spl = (a.n_t + L - 1) / L;
+    if (spl <= 1) hipLaunchKernelGGL((k_fit_run<D, DIM, 1>), dim3(blocks), dim3(kBlock), 0, s, a, bias, n_steps);
+    else if (spl <= 2) hipLaunchKernelGGL((k_fit_run<D, DIM, 2>), dim3(blocks), dim3(kBlock), 0, s, a, bias, n_steps);
+    else hipLaunchKernelGGL((k_fit_run<D, DIM, 4>), dim3(blocks), dim3(kBlock), 0, s, a, bias, n_steps);
+    BZ_CHECK_LAUNCH("k_fit_run");
+    return BZ_OK;
+}
+
+template <int D>
+int launch_fit_run_d(int dim, const FitArgs &a, const float2 *bias, int n_steps, hipStream_t s) {
+    switch (dim) {
+        case 1: return launch_fit_run_dd<D, 1>(a, bias, n_steps, s);
+        case 2: return launch_fit_run_dd<D, 2>(a, bias, n_steps, s);
+        case 3: return launch_fit_run_dd<D, 3>(a, bias, n_steps, s);
+        default: return launch_fit_run_dd<D, 4>(a, bias, n_steps, s);
+    }
+}
+
+int launch_fit_run(int degree, int dim, const FitArgs &a, const float2 *bias, int n_steps, hipStream_t s) {
+    switch (degree) {
+        case 1: return launch_fit_run_d<1>(dim, a, bias, n_steps, s);
+        case 2: return launch_fit_run_d<2>(dim, a, bias, n_steps, s);
+        case 3: return launch_fit_run_d<3>(dim, a, bias, n_steps, s);
+        case 4: return launch_fit_run_d<4>(dim, a, bias, n_steps, s);
+        case 5: return launch_fit_run_d<5>(dim, a, bias, n_steps, s);
+        case 6: return launch_fit_run_d<6>(dim, a, bias, n_steps, s);
+        case 7: return launch_fit_run_d<7>(dim, a, bias, n_steps, s);
+        case 8: return launch_fit_run_d<8>(dim, a, bias, n_steps, s);
+        case 9: return launch_fit_run_d<9>(dim, a, bias, n_steps, s);
+        case 10: return launch_fit_run_d<10>(dim, a, bias, n_steps, s);
+        case 11: return launch_fit_run_d<11>(dim, a, bias, n_steps, s);
+        case 12: return launch_fit_run_d<12>(dim, a, bias, n_steps, s);
+        case 13: return launch_fit_run_d<13>(dim, a, bias, n_steps, s);
+        case 14: return launch_fit_run_d<14>(dim, a, bias, n_steps, s);
+        default: return launch_fit_run_d<15>(dim, a, bias, n_steps, s);
     }
 }
 
@@ -413,7 +558,32 @@ int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int
         if (rc || n_curves == 0 || n_t == 0 || n_steps == 0) return rc;
         if (first_step < 1 || n_steps < 0) return fail(BZ_ERR_SHAPE, "%s: steps count from 1", fn);
         const hipStream_t s = as_stream(stream);
-        // capture the steps on a private stream that follows `stream`
+        const int64_t lanes_per_curve = dim * (degree + 1) <= 32 ? 32 : 64;
+        if (n_t <= 4 * lanes_per_curve) {
+            // all steps in one launch, per-curve state in registers
+            std::vector<float> tab(2 * static_cast<size_t>(n_steps));
+            for (int i = 0; i < n_steps; ++i) {
+                const FitArgs ai = make_fit_args(ctrl, t, y, n_curves, n_t, m_ctrl, v_ctrl, m_t, v_t, first_step + i,
+                                                 lr, beta1, beta2, eps, loss_part);
+                tab[2 * i] = ai.c1;
+                tab[2 * i + 1] = ai.c2;
+            }
+            float2 *bias = nullptr;
+            hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&bias), tab.size() * sizeof(float), s);
+            if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: bias table", fn);
+            BZ_CHECK_HIP(e);
+            e = hipMemcpyAsync(bias, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, s);
+            const FitArgs a = make_fit_args(ctrl, t, y, n_curves, n_t, m_ctrl, v_ctrl, m_t, v_t, first_step, lr, beta1,
+                                            beta2, eps, loss_part);
+            if (e == hipSuccess) rc = launch_fit_run(degree, dim, a, bias, n_steps, s);
+            else rc = hip_fail(e, "bias table copy");
+            const hipError_t e2 = hipFreeAsync(bias, s);
+            const hipError_t e3 = hipStreamSynchronize(s);
+            if (rc == BZ_OK && e2 != hipSuccess) rc = hip_fail(e2, "hipFreeAsync");
+            if (rc == BZ_OK && e3 != hipSuccess) rc = hip_fail(e3, "hipStreamSynchronize");
+            return rc;
+        }
+        // otherwise: capture the single steps on a private stream and replay the graph
         hipStream_t cap;
         BZ_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
