@@ -81,6 +81,20 @@ def chain_walk(n_seg=1 << 20, dim=3, n_q=1 << 24, step=0.1, seed=SEEDS["chain"])
     return chain, T
 
 
+def cubic_chain_walk(n_seg=1 << 20, dim=3, n_q=1 << 24, step=0.1, seed=SEEDS["chain"] + 100):
+    """C0 cubic chain: 3*n_seg+1 points of a random walk started at 0 with
+    i.i.d. U[-step,step]^dim steps (points 3k are the shared endpoints), and
+    n_q global parameters T = f32(U[0,1) * n_seg)."""
+    rng = np.random.default_rng(seed)
+    steps = rng.uniform(-step, step, size=(3 * n_seg, dim))
+    walk = np.zeros((3 * n_seg + 1, dim), dtype=np.float64)
+    np.cumsum(steps, axis=0, out=walk[1:])
+    chain = _f32(walk)
+    del walk, steps
+    T = _f32(rng.uniform(0.0, 1.0, size=n_q) * n_seg)
+    return chain, T
+
+
 # ---------------------------------------------------------------- batched
 @dataclass
 class Batch:

@@ -126,6 +126,34 @@ def chain_eval(chain, T):
     return out
 
 
+def cubic_chain_encode(chain):
+    """Cubic chain[3N+1][dim] -> two stacked zig-zag layers grid[N+1][2][2][dim]."""
+    chain = _d(chain)
+    m, dim = chain.shape
+    nseg = (m - 1) // 3
+    grid = np.empty((nseg + 1, 2, 2, dim))
+    lib().bzo_cubic_chain_encode(_ptr(chain), _I64(nseg), ctypes.c_int(dim), _ptr(grid))
+    return grid
+
+
+def cubic_chain_grid_eval(grid, T):
+    grid = _d(grid)
+    nseg, dim = grid.shape[0] - 1, grid.shape[3]
+    T = _d(T)
+    out = np.empty((dim, T.shape[0]))
+    lib().bzo_cubic_chain_grid_eval(_ptr(grid), _I64(nseg), ctypes.c_int(dim), _ptr(T), _I64(T.shape[0]), _ptr(out))
+    return out
+
+
+def cubic_chain_eval(chain, T):
+    chain = _d(chain)
+    nseg, dim = (chain.shape[0] - 1) // 3, chain.shape[1]
+    T = _d(T)
+    out = np.empty((dim, T.shape[0]))
+    lib().bzo_cubic_chain_eval(_ptr(chain), _I64(nseg), ctypes.c_int(dim), _ptr(T), _I64(T.shape[0]), _ptr(out))
+    return out
+
+
 def rational_eval(ctrl, w, t, per_object=False):
     ctrl = _d(ctrl)
     w = _d(w)

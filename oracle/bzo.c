@@ -512,3 +512,75 @@ void bzo_adam(double *p, double *m, double *v, const double *g, int64_t n, int s
         if (lo <= hi) p[i] = p[i] < lo ? lo : (p[i] > hi ? hi : p[i]);
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* C0 piecewise cubic chain from two stacked zig-zag layers (Sec. 2.1, last
+ * paragraph: two C0 quadratic textures front to back, the depth read
+ * interpolating between them).  chain[3N+1][dim]: segment k is the cubic
+ * Bezier (P_3k, P_3k+1, P_3k+2, P_3k+3).  Reading: both layers share the
+ * on-path texels A_k = P_3k; their middle points are
+ *   E0_k = (3 P_3k+1 - P_3k) / 2   and   E1_k = (3 P_3k+2 - P_3k+3) / 2,
+ * because (1-t) Q0(t) + t Q1(t) with Q_l = A s^2 + 2 E_l s t + A' t^2 has
+ * Bernstein coefficients (A, (A + 2 E0)/3, (A' + 2 E1)/3, A').
+ * grid[N+1][2 layers][2 rows][dim]; each layer is zig-zag encoded as above.  */
+void bzo_cubic_chain_encode(const double *chain, int64_t nseg, int dim, double *grid)
+{
+    double *q = (double *)malloc(sizeof(double) * (size_t)((2 * nseg + 1) * dim));
+    double *g = (double *)malloc(sizeof(double) * (size_t)((nseg + 1) * 2 * dim));
+    for (int layer = 0; layer < 2; ++layer) {
+        for (int64_t k = 0; k <= nseg; ++k)
+            for (int c = 0; c < dim; ++c) q[(2 * k) * dim + c] = chain[(3 * k) * dim + c];
+        for (int64_t k = 0; k < nseg; ++k)
+            for (int c = 0; c < dim; ++c) {
+                const double A = chain[(3 * k) * dim + c], A1 = chain[(3 * k + 3) * dim + c];
+                const double B = chain[(3 * k + 1) * dim + c], C = chain[(3 * k + 2) * dim + c];
+                q[(2 * k + 1) * dim + c] = layer == 0 ? (3.0 * B - A) / 2.0 : (3.0 * C - A1) / 2.0;
+            }
+        bzo_piecewise_encode(q, nseg, dim, g);
+        for (int64_t k = 0; k <= nseg; ++k)
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < dim; ++c) grid[((k * 2 + layer) * 2 + r) * dim + c] = g[(k * 2 + r) * dim + c];
+    }
+    free(q);
+    free(g);
+}
+
+/* Trilinear read of the two layers along the zig-zag path: the bilinear
+ * value of each layer (Eq. 1), then a lerp between layers with the same t. */
+void bzo_cubic_chain_grid_eval(const double *grid, int64_t nseg, int dim, const double *T, int64_t nq, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        double t;
+        const int64_t k = chain_decode(T[q], nseg, &t);
+        const int r = (int)(k & 1);
+        const double s = 1.0 - t;
+        for (int c = 0; c < dim; ++c) {
+            double v[2];
+            for (int layer = 0; layer < 2; ++layer) {
+                const double A = grid[((k * 2 + layer) * 2 + r) * dim + c];
+                const double xk = grid[((k * 2 + layer) * 2 + 1 - r) * dim + c];
+                const double xk1 = grid[(((k + 1) * 2 + layer) * 2 + r) * dim + c];
+                const double D = grid[(((k + 1) * 2 + layer) * 2 + 1 - r) * dim + c];
+                v[layer] = A * s * s + (xk + xk1) * s * t + D * t * t;
+            }
+            out[c * nq + q] = lerp(v[0], v[1], t);
+        }
+    }
+}
+
+/* The chain's plain definition: segment k is the cubic Bezier
+ * (P_3k .. P_3k+3) at local parameter t (de Casteljau).                    */
+void bzo_cubic_chain_eval(const double *chain, int64_t nseg, int dim, const double *T, int64_t nq, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        double t;
+        const int64_t k = chain_decode(T[q], nseg, &t);
+        for (int c = 0; c < dim; ++c) {
+            double b[4];
+            for (int i = 0; i < 4; ++i) b[i] = chain[(3 * k + i) * dim + c];
+            out[c * nq + q] = decasteljau(b, 1, 3, t);
+        }
+    }
+}

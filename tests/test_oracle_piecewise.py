@@ -117,3 +117,70 @@ def test_tensor_diagonal_is_shared_diagonal(orc):
     quad = np.stack([P[:, :, 0], (P[:, :, 1] + P[:, :, 2]) / 2, P[:, :, 3]], axis=2)
     curve = orc.bezier_decasteljau(quad, t)
     np.testing.assert_allclose(surf, curve, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------ stacked zig-zag cubic chain
+def _cubic_chain(n_seg, dim=3, seed=11):
+    chain, _ = bz_synth.cubic_chain_walk(n_seg=n_seg, dim=dim, n_q=1, seed=seed)
+    return chain
+
+
+def test_stacked_layers_identity_exact():
+    """(1-t)(A s^2 + 2 E0 s t + A' t^2) + t(A s^2 + 2 E1 s t + A' t^2) is the
+    cubic Bezier (A, B, C, A') when E0 = (3B - A)/2 and E1 = (3C - A')/2
+    (exact rational arithmetic); any other E0 changes the curve."""
+    rng = np.random.default_rng(12)
+    for _ in range(10):
+        A, B, C, A1 = (ex.F(x) for x in rng.uniform(-3, 3, 4))
+        E0, E1 = (3 * B - A) / 2, (3 * C - A1) / 2
+        for t in (Fraction(0), Fraction(1), Fraction(2, 7), Fraction(1, 2)):
+            s = 1 - t
+            q0 = A * s * s + 2 * E0 * s * t + A1 * t * t
+            q1 = A * s * s + 2 * E1 * s * t + A1 * t * t
+            assert (1 - t) * q0 + t * q1 == ex.bezier([A, B, C, A1], t)
+            if 0 < t < 1:
+                q0b = A * s * s + 2 * (E0 + 1) * s * t + A1 * t * t
+                assert (1 - t) * q0b + t * q1 != ex.bezier([A, B, C, A1], t)
+
+
+def test_cubic_chain_encoding_layout(orc):
+    """Two layers, each a zig-zag quadratic chain over the shared endpoints:
+    4(N+1) texels in all (a 2x2x2 block per segment would need 8N)."""
+    n = 40
+    chain = _cubic_chain(n)
+    grid = orc.cubic_chain_encode(chain)
+    assert grid.shape == (n + 1, 2, 2, 3)
+    for k in range(n + 1):
+        for layer in (0, 1):
+            np.testing.assert_array_equal(grid[k, layer, k & 1], chain[3 * k])
+    c64 = chain.astype(np.float64)
+    for layer, pick in ((0, lambda k: (3 * c64[3 * k + 1] - c64[3 * k]) / 2),
+                        (1, lambda k: (3 * c64[3 * k + 2] - c64[3 * k + 3]) / 2)):
+        x = np.array([grid[k, layer, 1 - (k & 1)] for k in range(n + 1)])
+        mid = np.array([pick(k) for k in range(n)], np.float64)
+        np.testing.assert_allclose((x[:-1] + x[1:]) / 2, mid, rtol=0, atol=1e-12)
+
+
+def test_cubic_chain_grid_equals_definition(orc):
+    chain = _cubic_chain(300)
+    rng = np.random.default_rng(13)
+    T = np.concatenate([rng.uniform(0, 300, 4000), np.arange(301.0), [-1.0, 305.0, np.nan]]).astype(np.float32)
+    a = orc.cubic_chain_grid_eval(orc.cubic_chain_encode(chain), T)
+    b = orc.cubic_chain_eval(chain, T)
+    ok = ~np.isnan(T)
+    np.testing.assert_allclose(a[:, ok], b[:, ok], rtol=0, atol=1e-11)
+    assert np.isnan(a[:, ~ok]).all() and np.isnan(b[:, ~ok]).all()
+    # C0: integer T gives the shared endpoint exactly (definition side)
+    np.testing.assert_array_equal(orc.cubic_chain_eval(chain, np.arange(301.0)).T, chain[0::3])
+
+
+def test_cubic_chain_brute_force_exact(orc):
+    chain = _cubic_chain(6, dim=2, seed=14)
+    T = np.array([0.0, 0.3, 1.0, 2.5, 5.875, 6.0], np.float32)
+    out = orc.cubic_chain_grid_eval(orc.cubic_chain_encode(chain), T)
+    for q, Tq in enumerate(T):
+        k = min(int(np.floor(Tq)), 5)
+        t = ex.F(Tq) - k
+        for c in range(2):
+            b = [ex.F(chain[3 * k + i, c]) for i in range(4)]
+            assert abs(Fraction(out[c, q]) - ex.bezier(b, t)) < Fraction(1, 2 ** 40)
