@@ -10,10 +10,11 @@ texel gather, bilinear diagonal read, store), inputs resident in HBM.
 `suite` adds the other workloads, each with its own kernel time, roofline and
 a CPU-baseline leg (the FP64 oracle timed on a bounded sample, whose outputs
 also give the GPU's max error on that sample): plain cubic curves (three
-forms), the mixed batch in one persistent launch (FP32 vs FP16 storage),
-bicubic patch tessellation (VALU vs FP32/BF16/FP16 MFMA), tricubic volumes at
-random points, and the fitting loop (fused loss + adjoint + Adam, 200 steps
-replayed from one HIP graph).
+forms), the C0 cubic chain stored as two stacked zig-zag layers, the mixed
+batch in one persistent launch (FP32 vs FP16 storage), bicubic patch
+tessellation (VALU vs FP32/BF16/FP16 MFMA), tricubic volumes at random
+points, and the fitting loop (fused loss + adjoint + Adam, 200 steps in one
+register-resident launch).
 
 Prints one JSON line.
 """
@@ -274,6 +275,31 @@ def suite_volumes(torch, bz, bz_synth, cpu):
     return {"workload": "2^16 tricubic 3D volumes at 2^24 random (u,v,w)", "unit": "G points/s", **res}
 
 
+def suite_cubic_chain(torch, bz, bz_synth, cpu):
+    log("suite: cubic chain (generating 2^20 segments)")
+    chain, T = bz_synth.cubic_chain_walk()
+    n_seg, n_q, dim = (chain.shape[0] - 1) // 3, T.shape[0], chain.shape[1]
+    c_d, T_d = torch.from_numpy(chain).cuda(), torch.from_numpy(T).cuda()
+    grid = bz.encode_piecewise_cubic(c_d)
+    torch.cuda.synchronize()
+    enc_ms = event_time_ms(lambda: bz.encode_piecewise_cubic(c_d, out=grid), 5, torch)
+    out = torch.empty((dim, n_q), device="cuda")
+    ms = timed(lambda: bz.eval_piecewise_cubic(grid, T_d, out=out), torch)
+    nbytes = grid.numel() * 4 + n_q * 4 + n_q * dim * 4
+    res = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms),
+           "algorithmic_bytes": nbytes, "encode_ms": enc_ms}
+    if cpu:
+        import oracle
+        m = 1 << 22
+        ref, sec, reps = oracle_timed(lambda: oracle.cubic_chain_eval(chain, T[:m]), 5.0)
+        res["cpu_baseline"] = {"value": m / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "%d x %d random T (FP64 chain definition)" % (reps, m)}
+        ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+        res["max_err_bbox"] = float(np.abs(out[:, :m].cpu().numpy().astype(np.float64) - ref).max() / ext)
+    return {"workload": "C0 piecewise cubic chain as two stacked zig-zag layers, 2^20 segments, 2^24 uniform "
+                        "random global T, 3D, FP32", "unit": "G evals/s", **res}
+
+
 def suite_fit(torch, bz, bz_synth, cpu):
     log("suite: fit")
     gt_ctrl, tau, eps = bz_synth.fit_problem()
@@ -332,7 +358,7 @@ def main():
     ap.add_argument("--n-q", type=int, default=1 << 24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
-    ap.add_argument("--suite-only", choices=["plain", "batched", "patches", "volumes", "fit"], default=None,
+    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "batched", "patches", "volumes", "fit"], default=None,
                     help="run one suite workload only (no headline) and print its record")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
                     help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
@@ -359,7 +385,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
         return
-    suites = {"plain": suite_plain, "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
+    suites = {"plain": suite_plain, "cubic_chain": suite_cubic_chain, "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
               "fit": suite_fit}
     if args.suite_only:
         print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}), flush=True)

@@ -133,6 +133,22 @@ int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T,
                       bz_stream stream);
 
 /*
+ * C0 piecewise cubic chain as two zig-zag layers stacked front to back (Sec.
+ * 2.1: two C0 quadratic textures, interpolated in depth).  chain:
+ * [3*n_seg+1][dim], segment k the cubic Bezier (P_3k, P_3k+1, P_3k+2,
+ * P_3k+3).  grid: [n_seg+1][2 layers][2 rows][dim], 4(n_seg+1) texels.  Both
+ * layers hold the shared endpoints A_k = P_3k in row k mod 2; their free
+ * texels are the zig-zag encodings of the middle points E0_k = (3 P_3k+1 -
+ * P_3k)/2 (layer 0) and E1_k = (3 P_3k+2 - P_3k+3)/2 (layer 1), formed in
+ * FP64.  Evaluation: T is decoded as in bz_eval_piecewise; the point is the
+ * lerp with weight t of the two layers' bilinear diagonal reads, which is the
+ * cubic segment.  grid needs 16-byte alignment.  out: [dim][n_q].
+ */
+int bz_encode_piecewise_cubic(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream);
+int bz_eval_piecewise_cubic(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                            bz_stream stream);
+
+/*
  * Cache-line-tiled placement of the same zig-zag texels: 128-byte tiles of
  * C = 128/(8*dim) consecutive grid columns (16, 8, 5, 4 for dim 1..4),
  * consecutive tiles overlapping by one column, so tile j holds segments

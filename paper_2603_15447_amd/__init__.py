@@ -50,6 +50,8 @@ _SIGS = {
     "bz_eval_rational": (_I, [_P, _P, _I, _I64, _I, _I, _P, _I64, _I, _I, _F, _P, _P, _P]),
     "bz_encode_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_encode_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
+    "bz_eval_piecewise_cubic": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -188,6 +190,25 @@ def eval_piecewise(grid, T, out=None):
     nq = T.shape[0]
     out = _f32_out((dim, nq), grid.device, out)
     check(lib().bz_eval_piecewise(_ptr(grid), nseg, dim, _ptr(T), nq, _ptr(out), _stream()))
+    return out
+
+
+def encode_piecewise_cubic(chain, out=None):
+    """Cubic chain[3N+1, dim] -> two stacked zig-zag layers grid[N+1, 2, 2, dim]."""
+    m, dim = chain.shape
+    nseg = (m - 1) // 3
+    assert m == 3 * nseg + 1
+    out = _f32_out((nseg + 1, 2, 2, dim), chain.device, out)
+    check(lib().bz_encode_piecewise_cubic(_ptr(chain), nseg, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_cubic(grid, T, out=None):
+    """grid[N+1, 2, 2, dim], T[n_q] -> out[dim, n_q]."""
+    nseg, dim = grid.shape[0] - 1, grid.shape[3]
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), grid.device, out)
+    check(lib().bz_eval_piecewise_cubic(_ptr(grid), nseg, dim, _ptr(T), nq, _ptr(out), _stream()))
     return out
 
 

@@ -1,5 +1,6 @@
 // C0 piecewise quadratic chains in the shared-diagonal ("zig-zag") encoding
-// (Sec. 2.1, Eq. 1-2, Fig. 2): encoder and random-access evaluator.
+// (Sec. 2.1, Eq. 1-2, Fig. 2): random-access evaluators of the grid and of
+// its cache-line-tiled placement.  The encoder is in chain_encode.hip.
 //
 // Grid layout in HBM: grid[n_seg+1][2][dim] FP32, one 2*dim*4-byte column per
 // chain vertex, so segment k reads one contiguous 16*dim-byte window (columns
@@ -14,91 +15,6 @@
 
 namespace bzi {
 namespace {
-
-constexpr int kEncPerThread = 8;
-constexpr int kEncPerBlock = kBlock * kEncPerThread;
-
-// Element e_k = (-1)^(k+1) * 2 M_k of the alternating sum: the free texels are
-// x_k = (-1)^k y_k with y_k = M_0 + sum_{j<k} e_j, which is x_{k+1} = 2M_k - x_k.
-__device__ __forceinline__ double enc_elem(const float *__restrict__ chain, int dim, int c, int64_t k, int64_t n_seg) {
-    if (k >= n_seg) return 0.0;
-    const double m = static_cast<double>(chain[(2 * k + 1) * dim + c]);
-    return (k & 1) ? 2.0 * m : -2.0 * m;
-}
-
-// Inclusive scan of one double per thread over the block (four waves).
-__device__ double block_scan_incl(double v, double *lds) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-    }
-    if (lane == 63) lds[wave] = v;
-    __syncthreads();
-    double pre = 0.0;
-    for (int w = 0; w < wave; ++w) pre += lds[w];
-    __syncthreads();
-    return v + pre;
-}
-
-__global__ __launch_bounds__(kBlock) void k_enc_partials(const float *__restrict__ chain, int64_t n_seg, int dim,
-                                                         double *__restrict__ partial) {
-    __shared__ double lds[kBlock / 64];
-    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kEncPerBlock + threadIdx.x * kEncPerThread;
-    for (int c = 0; c < dim; ++c) {
-        double s = 0.0;
-        for (int i = 0; i < kEncPerThread; ++i) s += enc_elem(chain, dim, c, k0 + i, n_seg);
-        const double tot = block_scan_incl(s, lds);
-        if (threadIdx.x == kBlock - 1) partial[static_cast<int64_t>(blockIdx.x) * dim + c] = tot;
-    }
-}
-
-// Exclusive scan of the block partials (one block, serial over chunks),
-// seeded with y_0 = M_0.
-__global__ __launch_bounds__(kBlock) void k_enc_offsets(const float *__restrict__ chain, int64_t nb, int dim,
-                                                        double *__restrict__ partial) {
-    __shared__ double lds[kBlock / 64];
-    __shared__ double total;
-    for (int c = 0; c < dim; ++c) {
-        double carry = static_cast<double>(chain[1 * dim + c]);
-        for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
-            const int64_t b = b0 + threadIdx.x;
-            const double v = b < nb ? partial[b * dim + c] : 0.0;
-            const double incl = block_scan_incl(v, lds);
-            if (b < nb) partial[b * dim + c] = carry + (incl - v);
-            if (threadIdx.x == kBlock - 1) total = incl;
-            __syncthreads();
-            carry += total;
-            __syncthreads();
-        }
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_enc_write(const float *__restrict__ chain, int64_t n_seg, int dim,
-                                                      const double *__restrict__ offsets, float *__restrict__ grid) {
-    __shared__ double lds[kBlock / 64];
-    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kEncPerBlock + threadIdx.x * kEncPerThread;
-    for (int c = 0; c < dim; ++c) {
-        double e[kEncPerThread];
-        double s = 0.0;
-        for (int i = 0; i < kEncPerThread; ++i) {
-            e[i] = enc_elem(chain, dim, c, k0 + i, n_seg);
-            s += e[i];
-        }
-        const double incl = block_scan_incl(s, lds);
-        double y = offsets[static_cast<int64_t>(blockIdx.x) * dim + c] + (incl - s);
-        for (int i = 0; i < kEncPerThread; ++i) {
-            const int64_t k = k0 + i;
-            if (k > n_seg) break;
-            const int r = static_cast<int>(k & 1);
-            const double x = r ? -y : y;
-            grid[(k * 2 + r) * dim + c] = chain[(2 * k) * dim + c];
-            grid[(k * 2 + 1 - r) * dim + c] = static_cast<float>(x);
-            y += e[i];
-        }
-    }
-}
 
 template <int DIM, int QPT>
 __global__ __launch_bounds__(kBlock) void k_piecewise_eval(const float *__restrict__ grid, uint32_t n_seg,
@@ -289,29 +205,6 @@ int launch_eval(const float *grid, uint32_t n_seg, const float *T, uint32_t nq, 
 using namespace bzi;
 
 extern "C" {
-
-int bz_encode_piecewise(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream) {
-    return guarded("bz_encode_piecewise", [&]() -> int {
-        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "bz_encode_piecewise: dim %d", dim);
-        if (n_seg < 0 || n_seg > (int64_t(1) << 40)) return fail(BZ_ERR_SHAPE, "bz_encode_piecewise: n_seg %lld", (long long)n_seg);
-        if (n_seg == 0) return BZ_OK;
-        if (!chain || !grid) return fail(BZ_ERR_NULL, "bz_encode_piecewise: chain and grid are required");
-        if (!aligned(chain, 4) || !aligned(grid, 4)) return fail(BZ_ERR_ALIGN, "bz_encode_piecewise: misaligned");
-        const hipStream_t s = as_stream(stream);
-        const int64_t nb = (n_seg + 1 + kEncPerBlock - 1) / kEncPerBlock;
-        double *partial = nullptr;
-        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * nb * dim, s);
-        if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "bz_encode_piecewise: workspace");
-        BZ_CHECK_HIP(e);
-        hipLaunchKernelGGL(k_enc_partials, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, chain, n_seg, dim, partial);
-        hipLaunchKernelGGL(k_enc_offsets, dim3(1), dim3(kBlock), 0, s, chain, nb, dim, partial);
-        hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, chain, n_seg, dim, partial, grid);
-        const hipError_t le = hipGetLastError();
-        BZ_CHECK_HIP(hipFreeAsync(partial, s));
-        if (le != hipSuccess) return hip_fail(le, "bz_encode_piecewise kernels");
-        return BZ_OK;
-    });
-}
 
 int bz_eval_piecewise(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
                       bz_stream stream) {
