@@ -112,6 +112,17 @@ def extents(ctrl):
     return np.maximum(np.maximum(side, np.abs(c).max(axis=(1, 2))), 1e-30)
 
 
+def copy_probe(torch, mib=1024, iters=10):
+    """Measured HBM ceiling: a plain device-to-device copy of `mib` MiB
+    (read + write counted), timed with HIP events on the current stream."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), torch, iters=iters)
+    del src, dst
+    return {"bytes_per_copy": 2 * 4 * n, "ms": ms, "GB/s": 2 * 4 * n / (ms * 1e-3) / 1e9}
+
+
 # ---------------------------------------------------------------- headline
 def cpu_baseline_chain(chain, T, out_dev, budget_s=10.0):
     """CPU-baseline leg: the oracle's chain definition on the first 4M queries,
@@ -238,7 +249,7 @@ def suite_patches(torch, bz, bz_synth, cpu):
         ref, sec, _ = oracle_timed(lambda: oracle.tensor_grid(P[pick], 3, 3, 32, 32), 3.0)
         res["cpu_baseline"] = {"value": len(pick) * 1024 / sec / 1e9, "unit": "G points/s",
                                "cores": oracle.max_threads(), "kind": "oracle", "sample": "1024 patches x 32x32"}
-    for eng in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16"):
+    for eng in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16", "mfma_f16x3"):
         ms = timed(lambda: bz.eval_tensor_patch(Pd, 3, 3, nu=32, nv=32, engine=eng, out=out), torch, iters=10)
         e = {"kernel_ms": ms, "value": n * 1024 / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms)}
         if ref is not None:
@@ -446,6 +457,9 @@ def main():
         "other_layout": {"layout": other, "kernel_ms": other_ms, "value": args.n_q / (other_ms * 1e-3) / 1e9},
         "encode_ms": enc_ms,
     }
+    probe = copy_probe(torch)
+    probe["headline_frac_of_copy"] = roof["achieved"] / probe["GB/s"]
+    rec["hbm_copy_probe"] = probe
     if not args.no_cpu:
         log("headline: CPU baseline")
         rec["cpu_baseline"], rec["max_err_bbox"] = cpu_baseline_chain(chain, T, out)

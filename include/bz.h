@@ -60,7 +60,8 @@ typedef enum {
     BZ_TP_VALU = 0,      /* separable FP32 vector evaluation */
     BZ_TP_MFMA_F32 = 1,  /* basis-matrix contraction on FP32 matrix cores */
     BZ_TP_MFMA_BF16 = 2, /* BF16 operands, FP32 accumulation */
-    BZ_TP_MFMA_F16 = 3   /* FP16 operands, FP32 accumulation */
+    BZ_TP_MFMA_F16 = 3,  /* FP16 operands, FP32 accumulation */
+    BZ_TP_MFMA_F16X3 = 4 /* FP16 high/low operand split, three products, FP32 accumulation */
 } bz_tp_engine;
 
 int bz_version(void);
@@ -170,7 +171,11 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
  * Grid mode (uvw == NULL, surfaces only): nu x nv inclusive uniform grid,
  *   u_a = a/(nu-1), v_b = b/(nv-1); out[dim][n_obj*nu*nv], point o*nu*nv +
  *   a*nv + b.  engine selects VALU or an MFMA contraction (the MFMA engines
- *   require du = dv = 3, nu = nv = 32 and FP32 storage).
+ *   require du = dv = 3, nu = nv = 32 and FP32 storage).  BF16 and FP16 round
+ *   both operands once (error up to a few 2^-9 resp. 2^-11 of max|P|);
+ *   FP16x3 scales each control-point row by a power of two, splits both
+ *   operands into FP16 high + low parts and drops only the low*low product
+ *   (error of order 2^-21 of the row's max|P|).
  * Points mode (uvw != NULL): uvw[n_obj][n_per][2 or 3], out[dim][n_obj*n_per];
  *   engine must be BZ_TP_VALU.
  */

@@ -22,10 +22,11 @@ OK, ERR_NULL, ERR_SHAPE, ERR_DTYPE, ERR_UNSUPPORTED, ERR_ALIGN, ERR_HIP, ERR_NOM
 F32, F16, BF16 = 0, 1, 2
 DECASTELJAU, BERNSTEIN, SEILER = 0, 1, 2
 T_SHARED, T_PER_OBJECT = 0, 1
-TP_VALU, TP_MFMA_F32, TP_MFMA_BF16, TP_MFMA_F16 = 0, 1, 2, 3
+TP_VALU, TP_MFMA_F32, TP_MFMA_BF16, TP_MFMA_F16, TP_MFMA_F16X3 = 0, 1, 2, 3, 4
 
 METHODS = {"decasteljau": DECASTELJAU, "bernstein": BERNSTEIN, "seiler": SEILER}
-ENGINES = {"valu": TP_VALU, "mfma_f32": TP_MFMA_F32, "mfma_bf16": TP_MFMA_BF16, "mfma_f16": TP_MFMA_F16}
+ENGINES = {"valu": TP_VALU, "mfma_f32": TP_MFMA_F32, "mfma_bf16": TP_MFMA_BF16, "mfma_f16": TP_MFMA_F16,
+           "mfma_f16x3": TP_MFMA_F16X3}
 _DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 _lib = None

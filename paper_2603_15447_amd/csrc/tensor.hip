@@ -12,6 +12,11 @@
 //                  cores: D[(patch,coord)][grid pt] = P[(patch,coord)][16] x
 //                  K[16][grid pt] with K the Kronecker product of the u and v
 //                  Bernstein bases, one 32x32 output tile per MFMA group.
+//                  FP16x3 splits both operands into FP16 high and low parts
+//                  (each control-point row first scaled by a power of two so
+//                  that its largest entry lies in [0.5, 1)) and sums the
+//                  products hi*hi + hi*lo + lo*hi in the FP32 accumulator,
+//                  which recovers FP32-class accuracy from FP16 MFMAs.
 #include "curves_impl.h"
 
 namespace bzi {
@@ -141,7 +146,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
-enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2 };
+enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2, MF_F16X3 = 3 };
 
 // Bicubic patches on a 32 x 32 grid.  Rows of the contraction are the
 // (patch, coordinate) pairs, i.e. the control-point array read as
@@ -182,13 +187,31 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
         obase[r] = c * plane + (o0 + o) * 1024 + col;
     }
     v8bf Ab;
-    v8h Ah;
+    v8h Ah, Al;
+    float unscale[16];
     if constexpr (ENG == MF_BF16) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) Ab[e] = static_cast<__bf16>(A[8 * kh + e]);
     } else if constexpr (ENG == MF_F16) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) Ah[e] = static_cast<_Float16>(A[8 * kh + e]);
+    } else if constexpr (ENG == MF_F16X3) {
+        float m = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) m = __builtin_fmaxf(m, __builtin_fabsf(A[e]));
+        int ex = 0;
+        (void)__builtin_frexpf(m, &ex);  // m = f * 2^ex, f in [0.5, 1); m = 0 gives ex = 0
+        const float sc = __builtin_ldexpf(1.0f, -ex);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float a = A[8 * kh + e] * sc;  // exact: power-of-two scale
+            Ah[e] = static_cast<_Float16>(a);
+            Al[e] = static_cast<_Float16>(a - static_cast<float>(Ah[e]));
+        }
+        // The scale of accumulator row j belongs to A row j, held by lane j.
+        const float inv = __builtin_ldexpf(1.0f, ex);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) unscale[r] = __shfl(inv, 8 * (r / 4) + 4 * kh + (r % 4));
     }
     for (int a = 0; a < 32; ++a) {
         float Bu[4];
@@ -208,6 +231,21 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
                 Bb[e] = static_cast<__bf16>(Bu[k >> 2] * Bv[k & 3]);
             }
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ab, Bb, acc, 0, 0, 0);
+        } else if constexpr (ENG == MF_F16X3) {
+            v8h Bh, Bl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * kh + e;
+                const float b = Bu[k >> 2] * Bv[k & 3];
+                Bh[e] = static_cast<_Float16>(b);
+                Bl[e] = static_cast<_Float16>(b - static_cast<float>(Bh[e]));
+            }
+            // small terms first, so the high product is added last
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, Bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, Bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, Bh, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] *= unscale[r];
         } else {
             v8h Bh;
 #pragma unroll
@@ -329,7 +367,7 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
         if (n_obj < 0) return fail(BZ_ERR_SHAPE, "%s: n_obj %lld", fn, (long long)n_obj);
         const int es = dtype_size(dtype);
         if (es == 0) return fail(BZ_ERR_DTYPE, "%s: dtype %d", fn, dtype);
-        if (engine < BZ_TP_VALU || engine > BZ_TP_MFMA_F16) return fail(BZ_ERR_UNSUPPORTED, "%s: engine %d", fn, engine);
+        if (engine < BZ_TP_VALU || engine > BZ_TP_MFMA_F16X3) return fail(BZ_ERR_UNSUPPORTED, "%s: engine %d", fn, engine);
         const int ncp = (du + 1) * (dv + 1) * (dw + 1);
         const hipStream_t s = as_stream(stream);
         if (uvw == nullptr) {  // grid mode
@@ -367,8 +405,10 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                         hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
                     else if (engine == BZ_TP_MFMA_BF16)
                         hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
-                    else
+                    else if (engine == BZ_TP_MFMA_F16)
                         hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                    else
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16X3>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
                     BZ_CHECK_LAUNCH("k_tensor_mfma");
                 }
             }

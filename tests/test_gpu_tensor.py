@@ -41,10 +41,11 @@ def test_grid_low_precision_storage(orc, dtype):
 # bound for basis-matrix contraction with both operands rounded to a format of
 # unit roundoff u: |sum (P+dP)(K+dK) - sum P K| <= 2u max|P| (sum K = 1),
 # plus FP32 accumulation of 16 terms.
-MFMA_BOUNDS = {"mfma_f32": None, "mfma_bf16": 2 * 2.0 ** -9, "mfma_f16": 2 * 2.0 ** -11}
+# FP16x3 keeps hi*hi + hi*lo + lo*hi: it is held to the FP32 tolerance.
+MFMA_BOUNDS = {"mfma_f32": None, "mfma_bf16": 2 * 2.0 ** -9, "mfma_f16": 2 * 2.0 ** -11, "mfma_f16x3": None}
 
 
-@pytest.mark.parametrize("engine", ["mfma_f32", "mfma_bf16", "mfma_f16"])
+@pytest.mark.parametrize("engine", ["mfma_f32", "mfma_bf16", "mfma_f16", "mfma_f16x3"])
 @pytest.mark.parametrize("n_obj,dim", [(1, 3), (11, 3), (43, 3), (64, 2), (9, 1), (17, 4)])
 def test_grid_mfma(orc, engine, n_obj, dim):
     P = bz_synth.patches(n_obj=n_obj, dim=dim, seed=n_obj + 100 * dim)
@@ -57,9 +58,25 @@ def test_grid_mfma(orc, engine, n_obj, dim):
         assert np.abs(got - ref).max() <= u * np.abs(P).max() + 1e-5
 
 
+@pytest.mark.parametrize("scale", [1e6, 1e-6, 3e30])
+def test_grid_mfma_f16x3_row_scaling(orc, scale):
+    """Control points far outside FP16's range (or deep in its subnormals):
+    the per-row power-of-two scaling keeps the FP16x3 engine at FP32-class
+    accuracy; each (patch, coordinate) row gets its own magnitude."""
+    n, dim = 37, 3
+    P = bz_synth.patches(n_obj=n, dim=dim, seed=77).astype(np.float64)
+    rng = np.random.default_rng(78)
+    P *= scale * np.exp2(rng.integers(-6, 7, size=(n, dim, 1)))
+    P = P.astype(np.float32)
+    got = host(bz.eval_tensor_patch(to_dev(P), 3, 3, nu=32, nv=32, engine="mfma_f16x3"))
+    ref = orc.tensor_grid(P, 3, 3, 32, 32)
+    assert np.isfinite(got).all()
+    assert bbox_err(got, ref, extents(P), 1024) <= TOL_F32
+
+
 def test_grid_config_full_size_sampled(orc):
-    """2^18 bicubic patches on 32x32 grids (2^28 points): VALU, FP32 MFMA and
-    BF16 MFMA outputs checked on 2048 sampled patches (every grid point)."""
+    """2^18 bicubic patches on 32x32 grids (2^28 points): VALU, FP32, BF16 and
+    FP16x3 MFMA outputs checked on 2048 sampled patches (every grid point)."""
     n = 1 << 18
     P = bz_synth.patches(n_obj=n)
     Pd = to_dev(P)
@@ -67,7 +84,7 @@ def test_grid_config_full_size_sampled(orc):
     pick = np.sort(rng.choice(n, size=2048, replace=False))
     ref = orc.tensor_grid(P[pick], 3, 3, 32, 32).reshape(3, 2048, 1024)
     out = torch.empty((3, n * 1024), dtype=torch.float32, device=Pd.device)
-    for engine in ("valu", "mfma_f32", "mfma_bf16"):
+    for engine in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16x3"):
         bz.eval_tensor_patch(Pd, 3, 3, nu=32, nv=32, engine=engine, out=out)
         got = out.view(3, n, 1024)[:, torch.from_numpy(pick).to(Pd.device)].cpu().numpy().astype(np.float64)
         if engine == "mfma_bf16":
