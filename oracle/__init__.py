@@ -290,3 +290,63 @@ def fit_reference(gt_ctrl, tau, eps, steps, lr=1e-2):
     y, ctrl, t = fit_init(gt_ctrl, tau, eps)
     losses = fit_steps(y, ctrl, t, steps, lr)
     return ctrl, t, losses
+
+
+# ------------------------------------------------ texture-filter emulation
+TEX_DC, TEX_HYBRID, TEX_SEILER = 0, 1, 2
+TEX_MODES = {"decasteljau": TEX_DC, "hybrid": TEX_HYBRID, "seiler": TEX_SEILER}
+ROUNDINGS = {"nearest": 0, "truncate": 1}
+
+
+def _f(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def tex_texels(deg, mode):
+    return lib().bzo_tex_texels(ctypes.c_int(deg), ctypes.c_int(TEX_MODES[mode]))
+
+
+def tex_axis_weights(p, frac_bits=8, rounding="nearest"):
+    """Filter weights of a 2-texel axis sampled at FP32 parameters p."""
+    p = _f(p).ravel()
+    w = np.empty(p.shape[0])
+    lib().bzo_tex_axis_weights(_ptr(p), _I64(p.shape[0]), ctypes.c_int(frac_bits),
+                               ctypes.c_int(ROUNDINGS[rounding]), _ptr(w))
+    return w
+
+
+def tex_build(ctrl, mode):
+    """Curve textures tex[n][dim][texels] (float64) of ctrl[n][dim][d+1]."""
+    ctrl = _d(ctrl)
+    n, dim, dp1 = ctrl.shape
+    ntx = tex_texels(dp1 - 1, mode)
+    tex = np.empty((n, dim, ntx))
+    lib().bzo_tex_build(_ptr(ctrl), _I64(n), ctypes.c_int(dp1 - 1), ctypes.c_int(dim),
+                        ctypes.c_int(TEX_MODES[mode]), _ptr(tex))
+    return tex
+
+
+def tex_eval(tex, deg, mode, t, per_object=False, frac_bits=8, rounding="nearest"):
+    """Emulated texture sampling of float32 textures tex[n][dim][texels] at
+    FP32 parameters t -> out[dim][n*n_t] (float64)."""
+    tex = _f(tex)
+    n, dim, _ = tex.shape
+    t = _f(t)
+    nt = t.shape[-1]
+    out = np.empty((dim, n * nt))
+    lib().bzo_tex_eval(_ptr(tex), _I64(n), ctypes.c_int(deg), ctypes.c_int(dim), ctypes.c_int(TEX_MODES[mode]),
+                       _ptr(t), _I64(nt), ctypes.c_int(int(per_object)), ctypes.c_int(frac_bits),
+                       ctypes.c_int(ROUNDINGS[rounding]), _ptr(out))
+    return out
+
+
+def chain_texemu_eval(grid, T, frac_bits=8, rounding="nearest"):
+    """Zig-zag grid[N+1][2][dim] (float32) read by the emulated bilinear
+    filter at FP32 global parameters T -> out[dim][n_q]."""
+    grid = _f(grid)
+    nseg, dim = grid.shape[0] - 1, grid.shape[2]
+    T = _f(T)
+    out = np.empty((dim, T.shape[0]))
+    lib().bzo_chain_texemu_eval(_ptr(grid), _I64(nseg), ctypes.c_int(dim), _ptr(T), _I64(T.shape[0]),
+                                ctypes.c_int(frac_bits), ctypes.c_int(ROUNDINGS[rounding]), _ptr(out))
+    return out

@@ -584,3 +584,198 @@ void bzo_cubic_chain_eval(const double *chain, int64_t nseg, int dim, const doub
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Texture-filter emulation (Sec. 2: texel values sit at texel centres and
+ * 2x2 / 2x2x2 textures hold de Casteljau levels; Sec. 2.1: the zig-zag
+ * chain texture; Sec. 2.3: fixed-point filter weights with 8 fractional
+ * bits; Sec. 3 with Table 1: Seiler textures read at (t, st[, st]);
+ * Fig. 3: the trilinear, hybrid and Seiler modes of a cubic).
+ *
+ * Per axis a linear filter blends the two texels around the sample with
+ * the sample's fractional position between their centres.  Readings (the
+ * paper names the 8 fractional bits but no rounding rule):
+ *   - that fraction is rounded to F fractional bits, to nearest with halves
+ *     up (rounding = 0) or by truncation (rounding = 1); F = 0 leaves it
+ *     unrounded;
+ *   - coordinates and the weight decision are FP32 (shader arithmetic), each
+ *     operation rounded as written; the blends here are FP64;
+ *   - every axis of a curve texture has two texels and a parameter p in
+ *     [0,1] is placed by the texel-centre remap x = 1/4 + p/2 (normalised),
+ *     which the filter turns back into the texel-space position 2x - 1/2;
+ *   - clamp-to-edge addressing: the curve parameter is clamped to [0,1] (the
+ *     shader lerps use the clamped value too), the chain's T to [0,N].     */
+#define BZO_TEX_DC 0
+#define BZO_TEX_HYBRID 1
+#define BZO_TEX_SEILER 2
+
+/* Fraction f in [0,1] held with F fractional bits. */
+static double tex_round_fraction(float f, int frac_bits, int rounding)
+{
+    if (frac_bits == 0) return (double)f;
+    const float scaled = ldexpf(f, frac_bits); /* exact: power-of-two scale */
+    const float q = rounding == 0 ? floorf(scaled + 0.5f) : floorf(scaled);
+    return ldexp((double)q, -frac_bits);
+}
+
+/* Filter weight of a 2-texel axis sampled at parameter p in [0,1]. */
+double bzo_tex_axis_weight(float p, int frac_bits, int rounding)
+{
+    const float x = 0.25f + 0.5f * p; /* normalised coordinate */
+    const float xb = 2.0f * x - 0.5f; /* texel-space position, centres at 0 and 1 */
+    if (isnan(xb)) return NAN;
+    if (xb <= 0.0f) return 0.0;
+    if (xb >= 1.0f) return 1.0;
+    return tex_round_fraction(xb, frac_bits, rounding);
+}
+
+void bzo_tex_axis_weights(const float *p, int64_t n, int frac_bits, int rounding, double *w)
+{
+    for (int64_t i = 0; i < n; ++i) w[i] = bzo_tex_axis_weight(p[i], frac_bits, rounding);
+}
+
+/* Bilinear filter of a 2x2 layer L[row*2 + col]: x blends along a row
+ * (column 0 -> 1), y across rows (row 0 -> 1).                             */
+static double tex_bilinear(const double *L, double wx, double wy)
+{
+    return (1.0 - wy) * ((1.0 - wx) * L[0] + wx * L[1]) + wy * ((1.0 - wx) * L[2] + wx * L[3]);
+}
+
+static double tex_trilinear(const double *L0, const double *L1, double wx, double wy, double wz)
+{
+    return (1.0 - wz) * tex_bilinear(L0, wx, wy) + wz * tex_bilinear(L1, wx, wy);
+}
+
+/* Texels per curve and coordinate. */
+int bzo_tex_texels(int deg, int mode)
+{
+    if (mode == BZO_TEX_SEILER) return deg <= 3 ? 4 : 8;
+    return 4 * (deg - 1);
+}
+
+/* Curve textures, tex[n][dim][texels].
+ * De Casteljau / hybrid (degree >= 2): deg-1 layers, layer i the quadratic
+ * (b_i, b_i+1, b_i+2) as [[b_i, b_i+1], [b_i+1, b_i+2]]: its bilinear read
+ * at (t,t) is that quadratic's point, and the trilinear read of layers i
+ * and i+1 at (t,t,t) is the point of the cubic (b_i .. b_i+3).
+ * Seiler (degree 2..5, Table 1), with d_j the difference terms:
+ *   2: [[b0, b2], [b0+d1, b2+d1]]      3: [[b0, b3], [b0+d1, b3+d2]]
+ *   4: [[b0, b4], [b0, b4]] then [[b0+d1, b4+d3], [b0+d1+d2, b4+d3+d2]]
+ *   5: [[b0, b5], [b0, b5]] then [[b0+d1, b5+d4], [b0+d1+d2, b5+d4+d3]]  */
+void bzo_tex_build(const double *ctrl, int64_t n, int deg, int dim, int mode, double *tex)
+{
+    const int nt = bzo_tex_texels(deg, mode);
+    for (int64_t c = 0; c < n; ++c)
+        for (int k = 0; k < dim; ++k) {
+            const double *b = ctrl + (c * dim + k) * (deg + 1);
+            double *T = tex + (c * dim + k) * nt;
+            if (mode != BZO_TEX_SEILER) {
+                for (int i = 0; i < deg - 1; ++i) {
+                    T[4 * i + 0] = b[i];
+                    T[4 * i + 1] = b[i + 1];
+                    T[4 * i + 2] = b[i + 1];
+                    T[4 * i + 3] = b[i + 2];
+                }
+                continue;
+            }
+            double sc[BZO_MAXDEG + 1];
+            seiler_coeffs(b, deg, sc);
+            /* sc = [b0, bd, d1, d_{d-1}, d2, d_{d-2}, ...] */
+            const double b0 = sc[0], bd = sc[1];
+            if (deg == 2) {
+                const double d1 = sc[2];
+                T[0] = b0, T[1] = bd, T[2] = b0 + d1, T[3] = bd + d1;
+            } else if (deg == 3) {
+                const double d1 = sc[2], d2 = sc[3];
+                T[0] = b0, T[1] = bd, T[2] = b0 + d1, T[3] = bd + d2;
+            } else {
+                /* deg 4: d1, d3, d2 = sc[2], sc[3], sc[4];
+                 * deg 5: d1, d4, d2, d3 = sc[2], sc[3], sc[4], sc[5]         */
+                const double d1 = sc[2], dl = sc[3], d2 = sc[4];
+                const double dm = deg == 4 ? d2 : sc[5];
+                T[0] = b0, T[1] = bd, T[2] = b0, T[3] = bd;
+                T[4] = b0 + d1, T[5] = bd + dl;
+                T[6] = b0 + d1 + d2, T[7] = bd + dl + dm;
+            }
+        }
+}
+
+/* Sampling of the curve textures (float texels, as stored for the GPU). */
+void bzo_tex_eval(const float *tex, int64_t n, int deg, int dim, int mode, const float *t, int64_t nt,
+                  int per_object, int frac_bits, int rounding, double *out)
+{
+    const int ntx = bzo_tex_texels(deg, mode);
+    const int64_t nq = n * nt;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t j = 0; j < nt; ++j) {
+            float p = per_object ? t[c * nt + j] : t[j];
+            if (p < 0.0f) p = 0.0f;
+            if (p > 1.0f) p = 1.0f;
+            const double w = bzo_tex_axis_weight(p, frac_bits, rounding);
+            const float st = (1.0f - p) * p;
+            const double wst = bzo_tex_axis_weight(st, frac_bits, rounding);
+            for (int k = 0; k < dim; ++k) {
+                const float *T = tex + (c * dim + k) * ntx;
+                double L[8 * BZO_MAXDEG];
+                for (int i = 0; i < ntx; ++i) L[i] = (double)T[i];
+                double v;
+                if (isnan(p)) {
+                    v = NAN;
+                } else if (mode == BZO_TEX_SEILER) {
+                    v = deg <= 3 ? tex_bilinear(L, w, wst) : tex_trilinear(L, L + 4, w, wst, wst);
+                } else {
+                    /* texture reads: level-3 points (trilinear, de Casteljau
+                     * mode from degree 3) or level-2 points (bilinear) */
+                    double lv[BZO_MAXDEG + 1];
+                    int m;
+                    if (mode == BZO_TEX_DC && deg >= 3) {
+                        m = deg - 2;
+                        for (int i = 0; i < m; ++i) lv[i] = tex_trilinear(L + 4 * i, L + 4 * i + 4, w, w, w);
+                    } else {
+                        m = deg - 1;
+                        for (int i = 0; i < m; ++i) lv[i] = tex_bilinear(L + 4 * i, w, w);
+                    }
+                    /* remaining de Casteljau levels in the shader, exact t */
+                    v = decasteljau(lv, 1, m - 1, (double)p);
+                }
+                out[k * nq + c * nt + j] = v;
+            }
+        }
+}
+
+/* Zig-zag chain (grid[N+1][2][dim], as bzo_piecewise_encode writes it) read
+ * by the emulated bilinear filter: texel (column, row) has its centre at
+ * (column + 1/2, row + 1/2) in texel space; segment k's sample runs from the
+ * centre of (k, k mod 2) to that of (k+1, 1 - k mod 2).                    */
+void bzo_chain_texemu_eval(const float *grid, int64_t nseg, int dim, const float *T, int64_t nq, int frac_bits,
+                           int rounding, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+        float Tc = T[q];
+        if (isnan(Tc)) {
+            for (int c = 0; c < dim; ++c) out[c * nq + q] = NAN;
+            continue;
+        }
+        if (Tc < 0.0f) Tc = 0.0f;
+        if (Tc > (float)nseg) Tc = (float)nseg;
+        const float x = Tc + 0.5f;
+        const float xb = x - 0.5f;
+        int64_t k = (int64_t)floorf(xb);
+        if (k > nseg - 1) k = nseg - 1;
+        const float fx = xb - (float)k;
+        const double wx = tex_round_fraction(fx, frac_bits, rounding);
+        const int r = (int)(k & 1);
+        const float y = r == 0 ? fx + 0.5f : 1.5f - fx;
+        float yb = y - 0.5f;
+        if (yb < 0.0f) yb = 0.0f;
+        if (yb > 1.0f) yb = 1.0f;
+        const double wy = tex_round_fraction(yb, frac_bits, rounding);
+        for (int c = 0; c < dim; ++c) {
+            const double L[4] = {grid[(k * 2 + 0) * dim + c], grid[((k + 1) * 2 + 0) * dim + c],
+                                 grid[(k * 2 + 1) * dim + c], grid[((k + 1) * 2 + 1) * dim + c]};
+            out[c * nq + q] = tex_bilinear(L, wx, wy);
+        }
+    }
+}
