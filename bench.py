@@ -10,11 +10,13 @@ texel gather, bilinear diagonal read, store), inputs resident in HBM.
 `suite` adds the other workloads, each with its own kernel time, roofline and
 a CPU-baseline leg (the FP64 oracle timed on a bounded sample, whose outputs
 also give the GPU's max error on that sample): plain cubic curves (three
-forms), the C0 cubic chain stored as two stacked zig-zag layers, the mixed
-batch in one persistent launch (FP32 vs FP16 storage), bicubic patch
-tessellation (VALU vs FP32/BF16/FP16 MFMA), tricubic volumes at random
-points, and the fitting loop (fused loss + adjoint + Adam, 200 steps in one
-register-resident launch).
+forms), the C0 cubic chain stored as two stacked zig-zag layers, the
+texture-filter emulation (Fig. 3's three read modes and the chain through an
+emulated bilinear filter, 8-bit weights), the mixed batch in one persistent
+launch (FP32 vs FP16 storage), bicubic patch tessellation (VALU vs
+FP32/BF16/FP16/FP16x3 MFMA), tricubic volumes at random points, and the
+fitting loop (fused loss + adjoint + Adam, 200 steps in one register-resident
+launch).
 
 Prints one JSON line.
 """
@@ -311,6 +313,69 @@ def suite_cubic_chain(torch, bz, bz_synth, cpu):
                         "random global T, 3D, FP32", "unit": "G evals/s", **res}
 
 
+def suite_texemu(torch, bz, bz_synth, cpu):
+    """Texture-filter emulation: Fig. 3's three read modes of a cubic and the
+    zig-zag chain through the emulated bilinear filter, 8-bit weights.  The
+    quantisation errors come from the CPU-baseline leg (the oracle's exact
+    curves and emulated filter on a sample)."""
+    log("suite: texture-filter emulation")
+    ctrl, t = bz_synth.plain_curves(n_curves=1 << 16)
+    n, nt = ctrl.shape[0], t.shape[0]
+    c_d, t_d = torch.from_numpy(ctrl).cuda(), torch.from_numpy(t).cuda()
+    out = torch.empty((3, n * nt), device="cuda")
+    sub = 1024  # error sample: the first 1024 curves, every t
+    res = {}
+    exact = ext = None
+    if cpu:
+        import oracle
+        exact = oracle.bezier_decasteljau(ctrl[:sub], t)
+        ext = extents(ctrl[:sub])
+    for mode in ("decasteljau", "hybrid", "seiler"):
+        tex = bz.build_texture(c_d, mode)
+        torch.cuda.synchronize()
+        build_ms = event_time_ms(lambda: bz.build_texture(c_d, mode, out=tex), 5, torch)
+        e = {"texels_per_coord": tex.shape[2], "build_ms": build_ms}
+        for rounding in ("nearest", "truncate"):
+            ms = timed(lambda: bz.eval_texture(tex, 3, mode, t_d, 8, rounding, out=out), torch)
+            nbytes = tex.numel() * 4 + t.nbytes + out.numel() * 4
+            r = {"kernel_ms": ms, "value": n * nt / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms)}
+            if cpu:
+                got = out[:, :sub * nt].cpu().numpy()
+                ref = oracle.tex_eval(tex[:sub].cpu().numpy(), 3, mode, t, False, 8, rounding)
+                r["quantisation_err_bbox"] = max_err_bbox(got, exact, ext, nt)
+                r["max_err_bbox_vs_oracle_emulation"] = max_err_bbox(got, ref, ext, nt)
+            e[rounding] = r
+        res[mode] = e
+    del out
+    chain, T = bz_synth.chain_walk()
+    nseg, nq = (chain.shape[0] - 1) // 2, T.shape[0]
+    grid = bz.encode_piecewise(torch.from_numpy(chain).cuda())
+    T_d = torch.from_numpy(T).cuda()
+    out = torch.empty((3, nq), device="cuda")
+    m = 1 << 22
+    cext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+    chain_exact = oracle.chain_eval(chain, T[:m]) if cpu else None
+    ch = {}
+    for rounding in ("nearest", "truncate"):
+        ms = timed(lambda: bz.eval_piecewise_texemu(grid, T_d, 8, rounding, out=out), torch)
+        r = {"kernel_ms": ms, "value": nq / (ms * 1e-3) / 1e9, "roofline": hbm_roof(chain_bytes(nseg, 3, nq), ms)}
+        if cpu:
+            got = out[:, :m].cpu().numpy().astype(np.float64)
+            ref = oracle.chain_texemu_eval(grid.cpu().numpy(), T[:m], 8, rounding)
+            r["quantisation_err_bbox"] = float(np.abs(got - chain_exact).max() / cext)
+            r["max_err_bbox_vs_oracle_emulation"] = float(np.abs(got - ref).max() / cext)
+        ch[rounding] = r
+    res["chain"] = ch
+    if cpu:
+        tex = oracle.tex_build(ctrl[:sub], "decasteljau").astype(np.float32)
+        _, sec, _ = oracle_timed(lambda: oracle.tex_eval(tex, 3, "decasteljau", t), 2.0)
+        res["cpu_baseline"] = {"value": sub * nt / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "1024 curves x 256 t, trilinear mode"}
+    return {"workload": "texture-filter emulation, 8 fractional weight bits: 65536 cubic 3D curves x 256 shared t "
+                        "in the trilinear / hybrid / Seiler modes (quantisation error on the first 1024 curves), "
+                        "and the 2^20-segment chain at 2^24 random T", "unit": "G evals/s", **res}
+
+
 def suite_fit(torch, bz, bz_synth, cpu):
     log("suite: fit")
     gt_ctrl, tau, eps = bz_synth.fit_problem()
@@ -369,7 +434,7 @@ def main():
     ap.add_argument("--n-q", type=int, default=1 << 24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
-    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "batched", "patches", "volumes", "fit"], default=None,
+    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit"], default=None,
                     help="run one suite workload only (no headline) and print its record")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
                     help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
@@ -396,7 +461,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
         return
-    suites = {"plain": suite_plain, "cubic_chain": suite_cubic_chain, "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
+    suites = {"plain": suite_plain, "cubic_chain": suite_cubic_chain, "texemu": suite_texemu,
+              "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
               "fit": suite_fit}
     if args.suite_only:
         print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}), flush=True)

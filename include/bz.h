@@ -56,6 +56,10 @@ typedef enum { BZ_DECASTELJAU = 0, BZ_BERNSTEIN = 1, BZ_SEILER = 2 } bz_method;
 
 typedef enum { BZ_T_SHARED = 0, BZ_T_PER_OBJECT = 1 } bz_tmode;
 
+typedef enum { BZ_TEX_DECASTELJAU = 0, BZ_TEX_HYBRID = 1, BZ_TEX_SEILER = 2 } bz_tex_mode;
+
+typedef enum { BZ_TEXW_NEAREST = 0, BZ_TEXW_TRUNCATE = 1 } bz_tex_rounding;
+
 typedef enum {
     BZ_TP_VALU = 0,      /* separable FP32 vector evaluation */
     BZ_TP_MFMA_F32 = 1,  /* basis-matrix contraction on FP32 matrix cores */
@@ -163,6 +167,54 @@ int64_t bz_piecewise_tiled_floats(int64_t n_seg, int dim);
 int bz_tile_piecewise(const float *grid, int64_t n_seg, int dim, float *tiles, bz_stream stream);
 int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
                             bz_stream stream);
+
+/*
+ * Texture-filter emulation (Sec. 2: texel values at texel centres, 2x2 and
+ * 2x2x2 textures holding de Casteljau levels; Sec. 2.3: filter weights in
+ * fixed point with 8 fractional bits; Sec. 3 with Table 1: Seiler textures;
+ * Fig. 3: the three ways of reading a cubic).  No texture unit is used: the
+ * filter runs on the vector ALUs.
+ *
+ * Weight rule (per axis, decided in FP32 with every operation rounded as
+ * written): a curve parameter p is clamped to [0,1] (clamp-to-edge), placed
+ * on a two-texel axis at x = 1/4 + p/2, turned back into the texel-space
+ * position xb = 2x - 1/2, and the fraction xb in [0,1] is held with
+ * frac_bits fractional bits: BZ_TEXW_NEAREST rounds to nearest with halves
+ * up, BZ_TEXW_TRUNCATE truncates; frac_bits = 0 leaves it unrounded
+ * (0..20).  Blends are FP32 lerps.
+ *
+ * bz_texture_texels: texels per curve and coordinate for (degree, mode), 0
+ * if unsupported.  De Casteljau and hybrid: 4(degree-1), degree 2..8;
+ * Seiler: 4 (degree 2, 3) or 8 (degree 4, 5).
+ * bz_build_texture: ctrl[n][dim][degree+1] FP32 -> tex[n][dim][texels],
+ * 2x2 layers stored [layer][row][column] (tex 16-byte aligned).
+ *   de Casteljau / hybrid: layer i = [[b_i, b_i+1], [b_i+1, b_i+2]];
+ *   Seiler (Table 1, d_j the difference terms, sums formed in FP64):
+ *     2: [[b0, b2], [b0+d1, b2+d1]]   3: [[b0, b3], [b0+d1, b3+d2]]
+ *     4: [[b0, b4], [b0, b4]], [[b0+d1, b4+d3], [b0+d1+d2, b4+d3+d2]]
+ *     5: [[b0, b5], [b0, b5]], [[b0+d1, b5+d4], [b0+d1+d2, b5+d4+d3]]
+ * bz_eval_texture: tex as built, t / t_mode / out as bz_eval_bezier.
+ *   BZ_TEX_DECASTELJAU: degree 2 one bilinear read at (t,t); degree >= 3 a
+ *     trilinear read of layers i, i+1 at (t,t,t) per cubic sub-curve, then
+ *     the remaining degree-3 de Casteljau levels as FP32 lerps with t.
+ *   BZ_TEX_HYBRID: a bilinear read of every layer, then degree-2 FP32 levels.
+ *   BZ_TEX_SEILER: one bilinear read at (t, st) (degree 2, 3) or trilinear at
+ *     (t, st, st) (degree 4, 5), st = (1-t)t formed in FP32 before the remap.
+ * bz_eval_piecewise_texemu: the zig-zag grid of bz_encode_piecewise read by
+ *   the emulated bilinear filter in texel space: T is clamped to [0,N] and
+ *   placed at x = T + 1/2 (texel centres at column + 1/2), k = min(floor(x -
+ *   1/2), N-1), the column weight is the rounded fraction x - 1/2 - k, the
+ *   row coordinate runs from the centre of row k mod 2 to the other row.
+ *   n_seg 1..2^24 (FP32 texel-space coordinates); grid 8-byte aligned.
+ * Errors: BZ_ERR_UNSUPPORTED for a (degree, mode) pair outside the above,
+ * BZ_ERR_SHAPE for counts, dim, frac_bits or rounding out of range.
+ */
+int bz_texture_texels(int degree, int mode);
+int bz_build_texture(const float *ctrl, int64_t n_curves, int degree, int dim, int mode, float *tex, bz_stream stream);
+int bz_eval_texture(const float *tex, int64_t n_curves, int degree, int dim, int mode, const float *t, int64_t n_t,
+                    int t_mode, int frac_bits, int rounding, float *out, bz_stream stream);
+int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, int frac_bits,
+                             int rounding, float *out, bz_stream stream);
 
 /*
  * Tensor-product surfaces and volumes (Sec. 2.2: per-axis order split).

@@ -27,6 +27,8 @@ TP_VALU, TP_MFMA_F32, TP_MFMA_BF16, TP_MFMA_F16, TP_MFMA_F16X3 = 0, 1, 2, 3, 4
 METHODS = {"decasteljau": DECASTELJAU, "bernstein": BERNSTEIN, "seiler": SEILER}
 ENGINES = {"valu": TP_VALU, "mfma_f32": TP_MFMA_F32, "mfma_bf16": TP_MFMA_BF16, "mfma_f16": TP_MFMA_F16,
            "mfma_f16x3": TP_MFMA_F16X3}
+TEX_MODES = {"decasteljau": 0, "hybrid": 1, "seiler": 2}
+TEX_ROUNDING = {"nearest": 0, "truncate": 1}
 _DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
 
 _lib = None
@@ -53,6 +55,10 @@ _SIGS = {
     "bz_eval_piecewise": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
     "bz_encode_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_cubic": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_texture_texels": (_I, [_I, _I]),
+    "bz_build_texture": (_I, [_P, _I64, _I, _I, _I, _P, _P]),
+    "bz_eval_texture": (_I, [_P, _I64, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
+    "bz_eval_piecewise_texemu": (_I, [_P, _I64, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -210,6 +216,42 @@ def eval_piecewise_cubic(grid, T, out=None):
     nq = T.shape[0]
     out = _f32_out((dim, nq), grid.device, out)
     check(lib().bz_eval_piecewise_cubic(_ptr(grid), nseg, dim, _ptr(T), nq, _ptr(out), _stream()))
+    return out
+
+
+def texture_texels(degree, mode):
+    return lib().bz_texture_texels(degree, TEX_MODES[mode])
+
+
+def build_texture(ctrl, mode, out=None):
+    """FP32 ctrl[n, dim, d+1] -> emulated curve textures tex[n, dim, texels]."""
+    n, dim, dp1 = ctrl.shape
+    ntx = texture_texels(dp1 - 1, mode)
+    out = _f32_out((n, dim, max(ntx, 1)), ctrl.device, out)
+    check(lib().bz_build_texture(_ptr(ctrl), n, dp1 - 1, dim, TEX_MODES[mode], _ptr(out), _stream()))
+    return out
+
+
+def eval_texture(tex, degree, mode, t, frac_bits=8, rounding="nearest", out=None):
+    """Sample emulated curve textures tex[n, dim, texels] at t ([n_t] shared
+    or [n, n_t]) through the emulated linear filter -> out[dim, n*n_t]."""
+    n, dim, _ = tex.shape
+    per_object = t.dim() == 2
+    nt = t.shape[-1]
+    out = _f32_out((dim, n * nt), tex.device, out)
+    check(lib().bz_eval_texture(_ptr(tex), n, degree, dim, TEX_MODES[mode], _ptr(t), nt,
+                                T_PER_OBJECT if per_object else T_SHARED, frac_bits, TEX_ROUNDING[rounding],
+                                _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_texemu(grid, T, frac_bits=8, rounding="nearest", out=None):
+    """Zig-zag grid[N+1, 2, dim] read by the emulated bilinear filter at T -> out[dim, n_q]."""
+    nseg, dim = grid.shape[0] - 1, grid.shape[2]
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), grid.device, out)
+    check(lib().bz_eval_piecewise_texemu(_ptr(grid), nseg, dim, _ptr(T), nq, frac_bits, TEX_ROUNDING[rounding],
+                                         _ptr(out), _stream()))
     return out
 
 

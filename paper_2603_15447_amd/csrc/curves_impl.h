@@ -61,8 +61,8 @@ __device__ __forceinline__ float dot_basis(const float (&B)[D + 1], const float 
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <int D, typename Acc = double>
-__device__ __forceinline__ void seiler_terms(const float (&b)[D + 1], float (&sc)[D + 1]) {
+template <int D, typename Acc = double, typename Out = float>
+__device__ __forceinline__ void seiler_terms(const float (&b)[D + 1], Out (&sc)[D + 1]) {
     Acc Q[D + 1];
 #pragma unroll
     for (int i = 0; i <= D; ++i) Q[i] = static_cast<Acc>(b[i]);
@@ -82,8 +82,8 @@ __device__ __forceinline__ void seiler_terms(const float (&b)[D + 1], float (&sc
         }
 #pragma unroll
         for (int i = 0; i <= n - 2; ++i) Q[i] = R[i];
-        sc[pos++] = static_cast<float>(Q[0]);
-        if (n - 2 > 0) sc[pos++] = static_cast<float>(Q[n - 2]);
+        sc[pos++] = static_cast<Out>(Q[0]);
+        if (n - 2 > 0) sc[pos++] = static_cast<Out>(Q[n - 2]);
     }
 }
 

@@ -1,0 +1,395 @@
+// Texture-filter emulation on the vector ALUs.  gfx950 exposes no texture
+// filtering to HIP, so the filter the paper relies on -- texel values at
+// texel centres (Sec. 2), weights held in fixed point with 8 fractional bits
+// (Sec. 2.3), bilinear / trilinear blends -- runs in registers:
+//
+//  k_tex_build       control points -> curve textures: de Casteljau layers
+//                    [[b_i, b_i+1], [b_i+1, b_i+2]] (Sec. 2) or the Seiler
+//                    layouts of Table 1 (Sec. 3), texels formed in FP64.
+//  k_texemu          one query per thread: clamp t, per-axis weight (remap
+//                    1/4 + t/2, texel-space 2x - 1/2, F-bit rounding), then
+//                    the mode's reads (Fig. 3): one trilinear read (de
+//                    Casteljau), bilinear reads + FP32 lerps (hybrid), or
+//                    the Seiler read at (t, st[, st]).
+//  k_piecewise_texemu  the zig-zag chain (Sec. 2.1) read through the same
+//                    emulated bilinear filter in texel space.
+//
+// The weight decisions are FP32 with every operation rounded as written (no
+// contraction), so they match any other FP32 evaluation of the same rule.
+#include "curves_impl.h"
+
+namespace bzi {
+namespace {
+
+enum { TX_DC = 0, TX_HYBRID = 1, TX_SEILER = 2 };
+constexpr int kTexMaxDegree = 8;
+
+template <int D, int MODE>
+constexpr int tex_texels() {
+    return MODE == TX_SEILER ? (D <= 3 ? 4 : 8) : 4 * (D - 1);
+}
+
+// Fraction f in [0,1] held with F fractional bits: nearest with halves up
+// (rnd 0) or truncation (rnd 1); F = 0 leaves it unrounded.
+__device__ __forceinline__ float tx_round(float f, int F, int rnd) {
+#pragma clang fp contract(off)
+    if (F == 0) return f;
+    const float sc = __builtin_ldexpf(f, F);
+    const float q = rnd == 0 ? __builtin_floorf(sc + 0.5f) : __builtin_floorf(sc);
+    return __builtin_ldexpf(q, -F);
+}
+
+// Weight of a two-texel axis sampled at parameter p in [0,1].
+__device__ __forceinline__ float tx_axis_weight(float p, int F, int rnd) {
+#pragma clang fp contract(off)
+    const float x = 0.25f + 0.5f * p;  // normalised coordinate
+    const float xb = 2.0f * x - 0.5f;  // texel-space position, centres at 0 and 1
+    if (xb != xb) return xb;
+    if (xb <= 0.0f) return 0.0f;
+    if (xb >= 1.0f) return 1.0f;
+    return tx_round(xb, F, rnd);
+}
+
+// Bilinear blend of a 2x2 layer L[row*2 + col]: x along a row, y across rows.
+__device__ __forceinline__ float tx_bilinear(const float *L, float wx, float wy) {
+    return lerp(lerp(L[0], L[1], wx), lerp(L[2], L[3], wx), wy);
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_tex_build(const float *__restrict__ ctrl, float *__restrict__ tex,
+                                                       uint32_t n_rows) {
+    constexpr int NT = tex_texels<D, MODE>();
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n_rows) return;
+    float b[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) b[i] = ctrl[static_cast<size_t>(r) * (D + 1) + i];
+    float T[NT];
+    if constexpr (MODE != TX_SEILER) {
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) {
+            T[4 * i] = b[i];
+            T[4 * i + 1] = b[i + 1];
+            T[4 * i + 2] = b[i + 1];
+            T[4 * i + 3] = b[i + 2];
+        }
+    } else {
+        double sc[D + 1];  // [b0, bd, d1, d_{d-1}, d2, ...]
+        seiler_terms<D, double, double>(b, sc);
+        const double b0 = sc[0], bd = sc[1];
+        if constexpr (D == 2) {
+            T[0] = b[0], T[1] = b[2];
+            T[2] = static_cast<float>(b0 + sc[2]), T[3] = static_cast<float>(bd + sc[2]);
+        } else if constexpr (D == 3) {
+            T[0] = b[0], T[1] = b[3];
+            T[2] = static_cast<float>(b0 + sc[2]), T[3] = static_cast<float>(bd + sc[3]);
+        } else {
+            // degree 4: d1, d3, d2; degree 5: d1, d4, d2, d3
+            const double d1 = sc[2], dl = sc[3], d2 = sc[4];
+            const double dm = D == 4 ? sc[4] : sc[5];
+            T[0] = b[0], T[1] = b[D], T[2] = b[0], T[3] = b[D];
+            T[4] = static_cast<float>(b0 + d1), T[5] = static_cast<float>(bd + dl);
+            T[6] = static_cast<float>(b0 + d1 + d2), T[7] = static_cast<float>(bd + dl + dm);
+        }
+    }
+    float4 *__restrict__ o = reinterpret_cast<float4 *>(tex + static_cast<size_t>(r) * NT);
+#pragma unroll
+    for (int e = 0; e < NT / 4; ++e) o[e] = make_float4(T[4 * e], T[4 * e + 1], T[4 * e + 2], T[4 * e + 3]);
+}
+
+struct TexArgs {
+    const float *tex;  // textures of curves [c0, c0+n)
+    const float *t;    // base of the full parameter array
+    float *out;        // base of the full output array
+    int64_t plane;     // total queries of the call
+    int64_t q0;        // first query of this launch
+    uint32_t nq;
+    FastDiv div_nt;
+    int per_object;
+    int frac_bits;
+    int rounding;
+};
+
+template <int D, int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
+    constexpr int NT = tex_texels<D, MODE>();
+    const uint32_t ql = blockIdx.x * kBlock + threadIdx.x;
+    if (ql >= a.nq) return;
+    const uint32_t cl = fdiv(ql, a.div_nt);
+    const uint32_t j = ql - cl * a.div_nt.d;
+    const int64_t qg = a.q0 + ql;
+    float p = a.per_object ? a.t[qg] : a.t[j];
+    p = p < 0.0f ? 0.0f : p;  // clamp-to-edge; NaN passes
+    p = p > 1.0f ? 1.0f : p;
+    const float w = tx_axis_weight(p, a.frac_bits, a.rounding);
+    float wst = 0.0f;
+    if constexpr (MODE == TX_SEILER) {
+#pragma clang fp contract(off)
+        const float st = (1.0f - p) * p;
+        wst = tx_axis_weight(st, a.frac_bits, a.rounding);
+    }
+    const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.tex + static_cast<size_t>(cl) * DIM * NT);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        float L[NT];
+#pragma unroll
+        for (int e = 0; e < NT / 4; ++e) {
+            const float4 v = src[k * (NT / 4) + e];
+            L[4 * e] = v.x, L[4 * e + 1] = v.y, L[4 * e + 2] = v.z, L[4 * e + 3] = v.w;
+        }
+        float v;
+        if constexpr (MODE == TX_SEILER) {
+            v = D <= 3 ? tx_bilinear(L, w, wst) : lerp(tx_bilinear(L, w, wst), tx_bilinear(L + 4, w, wst), wst);
+        } else {
+            // texture reads: level-3 points (trilinear) in de Casteljau mode
+            // from degree 3, level-2 points (bilinear) otherwise; the
+            // remaining de Casteljau levels run in FP32 with the exact t
+            constexpr int M = (MODE == TX_DC && D >= 3) ? D - 2 : D - 1;
+            float lv[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if constexpr (MODE == TX_DC && D >= 3)
+                    lv[i] = lerp(tx_bilinear(L + 4 * i, w, w), tx_bilinear(L + 4 * i + 4, w, w), w);
+                else
+                    lv[i] = tx_bilinear(L + 4 * i, w, w);
+            }
+#pragma unroll
+            for (int lvl = 1; lvl < M; ++lvl)
+#pragma unroll
+                for (int i = 0; i < M - lvl; ++i) lv[i] = lerp(lv[i], lv[i + 1], p);
+            v = lv[0];
+        }
+        st_stream(a.out + k * a.plane + qg, v);
+    }
+}
+
+template <int DIM, int QPT>
+__global__ __launch_bounds__(kBlock) void k_piecewise_texemu(const float *__restrict__ grid, uint32_t n_seg,
+                                                             const float *__restrict__ T, uint32_t nq,
+                                                             float *__restrict__ out, int64_t plane, int F,
+                                                             int rnd) {
+#pragma clang fp contract(off)
+    const uint32_t base = blockIdx.x * (kBlock * QPT) + threadIdx.x;
+    const float nf = static_cast<float>(n_seg);
+    const float nm1 = static_cast<float>(n_seg - 1);
+    float wx[QPT], wy[QPT];
+    uint32_t kk[QPT];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+        float Tc = ld_stream(T + q);
+        Tc = Tc < 0.0f ? 0.0f : Tc;
+        Tc = Tc > nf ? nf : Tc;
+        const float x = Tc + 0.5f;  // texel-space coordinate, centres at c + 1/2
+        const float xb = x - 0.5f;
+        const float kf = __builtin_fminf(__builtin_floorf(xb), nm1);  // NaN -> n_seg-1, in bounds
+        const uint32_t k = min(static_cast<uint32_t>(kf), n_seg - 1);
+        const float fx = xb - static_cast<float>(k);
+        const float y = (k & 1) ? 1.5f - fx : fx + 0.5f;
+        float yb = y - 0.5f;
+        yb = yb < 0.0f ? 0.0f : yb;
+        yb = yb > 1.0f ? 1.0f : yb;
+        kk[i] = k;
+        wx[i] = tx_round(fx, F, rnd);
+        wy[i] = tx_round(yb, F, rnd);
+    }
+    float2 g[QPT][2 * DIM];
+    const float2 *__restrict__ g2 = reinterpret_cast<const float2 *>(grid);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) g[i][e] = g2[static_cast<size_t>(kk[i]) * DIM + e];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        float f[4 * DIM];  // [column k, k+1][row 0, 1][dim]
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e) f[2 * e] = g[i][e].x, f[2 * e + 1] = g[i][e].y;
+        const uint32_t q = min(base + i * kBlock, nq - 1);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const float L[4] = {f[c], f[2 * DIM + c], f[DIM + c], f[3 * DIM + c]};
+            st_stream(out + c * plane + q, tx_bilinear(L, wx[i], wy[i]));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host
+template <int MODE>
+int launch_build_m(int degree, const float *ctrl, float *tex, uint32_t rows, hipStream_t s) {
+    const uint32_t blocks = (rows + kBlock - 1) / kBlock;
+#define BZI_TB(D)                                                                                   \
+    case D:                                                                                         \
+        if constexpr (MODE != TX_SEILER || D <= 5)                                                  \
+            hipLaunchKernelGGL((k_tex_build<D, MODE>), dim3(blocks), dim3(kBlock), 0, s, ctrl, tex, rows); \
+        break;
+    switch (degree) {
+        BZI_TB(2) BZI_TB(3) BZI_TB(4) BZI_TB(5) BZI_TB(6) BZI_TB(7) BZI_TB(8)
+        default: return fail(BZ_ERR_SHAPE, "degree %d", degree);
+    }
+#undef BZI_TB
+    BZ_CHECK_LAUNCH("k_tex_build");
+    return BZ_OK;
+}
+
+template <int D, int MODE>
+int launch_texemu_dm(int dim, const TexArgs &a, hipStream_t s) {
+    const uint32_t blocks = (a.nq + kBlock - 1) / kBlock;
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_texemu<D, 1, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_texemu<D, 2, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_texemu<D, 3, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_texemu<D, 4, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
+    BZ_CHECK_LAUNCH("k_texemu");
+    return BZ_OK;
+}
+
+template <int MODE>
+int launch_texemu_m(int degree, int dim, const TexArgs &a, hipStream_t s) {
+    switch (degree) {
+        case 2: return launch_texemu_dm<2, MODE>(dim, a, s);
+        case 3: return launch_texemu_dm<3, MODE>(dim, a, s);
+        case 4: return launch_texemu_dm<4, MODE>(dim, a, s);
+        case 5: return launch_texemu_dm<5, MODE>(dim, a, s);
+        default: break;
+    }
+    if constexpr (MODE != TX_SEILER) {
+        switch (degree) {
+            case 6: return launch_texemu_dm<6, MODE>(dim, a, s);
+            case 7: return launch_texemu_dm<7, MODE>(dim, a, s);
+            case 8: return launch_texemu_dm<8, MODE>(dim, a, s);
+            default: break;
+        }
+    }
+    return fail(BZ_ERR_SHAPE, "degree %d", degree);
+}
+
+int tex_texels_rt(int degree, int mode) {
+    if (mode == TX_SEILER) return degree >= 2 && degree <= 5 ? (degree <= 3 ? 4 : 8) : 0;
+    if (mode == TX_DC || mode == TX_HYBRID) return degree >= 2 && degree <= kTexMaxDegree ? 4 * (degree - 1) : 0;
+    return 0;
+}
+
+template <int DIM>
+int launch_chain_texemu(const float *grid, uint32_t n_seg, const float *T, uint32_t nq, float *out, int64_t plane,
+                        int F, int rnd, hipStream_t s) {
+    constexpr int Q = 4;
+    const uint32_t blocks = (nq + kBlock * Q - 1) / (kBlock * Q);
+    hipLaunchKernelGGL((k_piecewise_texemu<DIM, Q>), dim3(blocks), dim3(kBlock), 0, s, grid, n_seg, T, nq, out, plane,
+                       F, rnd);
+    BZ_CHECK_LAUNCH("k_piecewise_texemu");
+    return BZ_OK;
+}
+
+constexpr int kMaxFracBits = 20;
+
+}  // namespace
+}  // namespace bzi
+
+using namespace bzi;
+
+extern "C" {
+
+int bz_texture_texels(int degree, int mode) { return tex_texels_rt(degree, mode); }
+
+int bz_build_texture(const float *ctrl, int64_t n_curves, int degree, int dim, int mode, float *tex,
+                     bz_stream stream) {
+    return guarded("bz_build_texture", [&]() -> int {
+        const char *fn = "bz_build_texture";
+        if (tex_texels_rt(degree, mode) == 0)
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..5)", fn,
+                        mode, degree, kTexMaxDegree);
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_curves < 0 || n_curves * dim > (int64_t(1) << 31)) return fail(BZ_ERR_SHAPE, "%s: n_curves", fn);
+        if (n_curves == 0) return BZ_OK;
+        if (!ctrl || !tex) return fail(BZ_ERR_NULL, "%s: ctrl and tex are required", fn);
+        if (!aligned(ctrl, 4) || !aligned(tex, 16)) return fail(BZ_ERR_ALIGN, "%s: tex needs 16-byte alignment", fn);
+        const uint32_t rows = static_cast<uint32_t>(n_curves * dim);
+        const hipStream_t s = as_stream(stream);
+        if (mode == TX_SEILER) return launch_build_m<TX_SEILER>(degree, ctrl, tex, rows, s);
+        return launch_build_m<TX_DC>(degree, ctrl, tex, rows, s);  // hybrid shares the texels
+    });
+}
+
+int bz_eval_texture(const float *tex, int64_t n_curves, int degree, int dim, int mode, const float *t, int64_t n_t,
+                    int t_mode, int frac_bits, int rounding, float *out, bz_stream stream) {
+    return guarded("bz_eval_texture", [&]() -> int {
+        const char *fn = "bz_eval_texture";
+        const int ntx = tex_texels_rt(degree, mode);
+        if (ntx == 0)
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..5)", fn,
+                        mode, degree, kTexMaxDegree);
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_curves < 0 || n_t < 0 || n_t > (int64_t(1) << 30)) return fail(BZ_ERR_SHAPE, "%s: counts", fn);
+        if (n_curves > 0 && n_t > 0 && n_curves > (int64_t(1) << 62) / n_t)
+            return fail(BZ_ERR_SHAPE, "%s: n_curves*n_t overflows", fn);
+        if (t_mode != BZ_T_SHARED && t_mode != BZ_T_PER_OBJECT) return fail(BZ_ERR_SHAPE, "%s: t_mode %d", fn, t_mode);
+        if (frac_bits < 0 || frac_bits > kMaxFracBits)
+            return fail(BZ_ERR_SHAPE, "%s: frac_bits %d not in 0..%d", fn, frac_bits, kMaxFracBits);
+        if (rounding != BZ_TEXW_NEAREST && rounding != BZ_TEXW_TRUNCATE)
+            return fail(BZ_ERR_SHAPE, "%s: rounding %d", fn, rounding);
+        if (n_curves == 0 || n_t == 0) return BZ_OK;
+        if (!tex || !t || !out) return fail(BZ_ERR_NULL, "%s: tex, t and out are required", fn);
+        if (!aligned(tex, 16) || !aligned(t, 4) || !aligned(out, 4))
+            return fail(BZ_ERR_ALIGN, "%s: tex needs 16-byte alignment", fn);
+        const hipStream_t s = as_stream(stream);
+        const int64_t nq = n_curves * n_t;
+        const int64_t per = std::max<int64_t>(1, (int64_t(1) << 30) / n_t);
+        for (int64_t c0 = 0; c0 < n_curves; c0 += per) {
+            const int64_t nc = std::min(per, n_curves - c0);
+            TexArgs a;
+            a.tex = tex + c0 * dim * ntx;
+            a.t = t;
+            a.out = out;
+            a.plane = nq;
+            a.q0 = c0 * n_t;
+            a.nq = static_cast<uint32_t>(nc * n_t);
+            a.div_nt = make_fastdiv(static_cast<uint32_t>(n_t));
+            a.per_object = t_mode == BZ_T_PER_OBJECT;
+            a.frac_bits = frac_bits;
+            a.rounding = rounding;
+            int rc;
+            if (mode == TX_DC) rc = launch_texemu_m<TX_DC>(degree, dim, a, s);
+            else if (mode == TX_HYBRID) rc = launch_texemu_m<TX_HYBRID>(degree, dim, a, s);
+            else rc = launch_texemu_m<TX_SEILER>(degree, dim, a, s);
+            if (rc) return rc;
+        }
+        return BZ_OK;
+    });
+}
+
+int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, int frac_bits,
+                             int rounding, float *out, bz_stream stream) {
+    return guarded("bz_eval_piecewise_texemu", [&]() -> int {
+        const char *fn = "bz_eval_piecewise_texemu";
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_q < 0) return fail(BZ_ERR_SHAPE, "%s: n_q", fn);
+        if (n_seg < 1 || n_seg > (int64_t(1) << 24))
+            return fail(BZ_ERR_SHAPE, "%s: n_seg not in 1..2^24 (FP32 texel-space coordinates)", fn);
+        if (frac_bits < 0 || frac_bits > kMaxFracBits)
+            return fail(BZ_ERR_SHAPE, "%s: frac_bits %d not in 0..%d", fn, frac_bits, kMaxFracBits);
+        if (rounding != BZ_TEXW_NEAREST && rounding != BZ_TEXW_TRUNCATE)
+            return fail(BZ_ERR_SHAPE, "%s: rounding %d", fn, rounding);
+        if (n_q == 0) return BZ_OK;
+        if (!grid || !T || !out) return fail(BZ_ERR_NULL, "%s: grid, T and out are required", fn);
+        if (!aligned(grid, 8) || !aligned(T, 4) || !aligned(out, 4))
+            return fail(BZ_ERR_ALIGN, "%s: grid needs 8-byte alignment", fn);
+        const hipStream_t s = as_stream(stream);
+        const int64_t per = int64_t(1) << 30;
+        for (int64_t q0 = 0; q0 < n_q; q0 += per) {
+            const uint32_t nq = static_cast<uint32_t>(std::min(per, n_q - q0));
+            const uint32_t ns = static_cast<uint32_t>(n_seg);
+            int rc;
+            switch (dim) {
+                case 1: rc = launch_chain_texemu<1>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+                case 2: rc = launch_chain_texemu<2>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+                case 3: rc = launch_chain_texemu<3>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+                default: rc = launch_chain_texemu<4>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+            }
+            if (rc) return rc;
+        }
+        return BZ_OK;
+    });
+}
+
+}  // extern "C"

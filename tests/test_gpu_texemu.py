@@ -1,0 +1,147 @@
+"""GPU parity: texture-filter emulation (Sec. 2, Sec. 2.3, Sec. 3 with
+Table 1, Fig. 3) and the zig-zag chain read through the emulated bilinear
+filter (Sec. 2.1), against the FP64 oracle with the same FP32 weight rule."""
+import numpy as np
+import pytest
+import torch
+
+import bz_synth
+import paper_2603_15447_amd as bz
+from tests._gpu import TOL_F32, bbox_err, extents, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("decasteljau", d) for d in range(2, 9)] + [("hybrid", d) for d in range(2, 9)] + \
+        [("seiler", d) for d in range(2, 6)]
+
+
+def _curves(n, d, dim, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1, 1, size=(n, dim, d + 1)).astype(np.float32)
+
+
+@pytest.mark.parametrize("mode,d", CASES)
+def test_build_parity(orc, mode, d):
+    ctrl = _curves(257, d, 3, 500 + d)
+    got = host(bz.build_texture(to_dev(ctrl), mode))
+    ref = orc.tex_build(ctrl, mode)
+    assert got.shape == ref.shape == (257, 3, bz.texture_texels(d, mode))
+    if mode != "seiler":
+        np.testing.assert_array_equal(got, ref)
+    else:  # FP64 texels rounded once to FP32: within one FP32 spacing
+        assert (np.abs(got - ref) <= np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)).all()
+
+
+@pytest.mark.parametrize("mode,d", CASES)
+@pytest.mark.parametrize("frac_bits,rounding", [(8, "nearest"), (8, "truncate"), (0, "nearest"), (4, "nearest")])
+def test_eval_parity(orc, mode, d, frac_bits, rounding):
+    """Same FP32 textures on both sides; every weight decision must agree
+    (one flip would cost ~2^-8 of the curve's extent, far above the
+    tolerance)."""
+    n, nt = 67, 130  # ragged against the 256-thread blocks
+    rng = np.random.default_rng(510 + d + 20 * frac_bits)
+    for dim in (3, 1):
+        ctrl = _curves(n, d, dim, 520 + d + dim)
+        tex = orc.tex_build(ctrl, mode).astype(np.float32)
+        t = np.concatenate([[0.0, 1.0, 0.5], rng.random(nt - 3)]).astype(np.float32)
+        got = host(bz.eval_texture(to_dev(tex), d, mode, to_dev(t), frac_bits, rounding))
+        ref = orc.tex_eval(tex, d, mode, t, False, frac_bits, rounding)
+        assert bbox_err(got, ref, extents(ctrl), nt) <= TOL_F32, dim
+        tp = rng.random((n, 7)).astype(np.float32)  # per-object parameters
+        got = host(bz.eval_texture(to_dev(tex), d, mode, to_dev(tp), frac_bits, rounding))
+        ref = orc.tex_eval(tex, d, mode, tp, True, frac_bits, rounding)
+        assert bbox_err(got, ref, extents(ctrl), 7) <= TOL_F32, dim
+
+
+def test_eval_edges(orc):
+    """Clamp-to-edge outside [0,1], endpoints, ties of the weight rule, NaN."""
+    ctrl = _curves(9, 3, 2, 530)
+    t = np.array([-1.0, 0.0, 1.0, 2.0, np.inf, -np.inf, np.nan, 0.5 / 256, 128.5 / 256, 255.5 / 256],
+                 np.float32)
+    for mode in ("decasteljau", "hybrid", "seiler"):
+        tex = orc.tex_build(ctrl, mode).astype(np.float32)
+        for rounding in ("nearest", "truncate"):
+            got = host(bz.eval_texture(to_dev(tex), 3, mode, to_dev(t), 8, rounding))
+            ref = orc.tex_eval(tex, 3, mode, t, False, 8, rounding)
+            ok = ~np.isnan(ref)
+            assert np.isnan(got[~ok]).all()
+            assert np.abs(got[ok] - ref[ok]).max() <= 1e-6
+            g = got.reshape(2, 9, -1)
+            np.testing.assert_allclose(g[:, :, 0], g[:, :, 1], rtol=0, atol=1e-7)
+
+
+def test_eval_fig3_errors_match_oracle(orc):
+    """Fig. 3 workload shape: cubic curves, 8-bit nearest weights.  The GPU's
+    deviation from the exact curve, per mode, is the oracle's (same weights),
+    and the modes keep the oracle's order: hybrid < trilinear < Seiler."""
+    ctrl = _curves(2048, 3, 3, 540)
+    t = (np.arange(256) / 255).astype(np.float32)
+    exact = orc.bezier_decasteljau(ctrl, t)
+    ext = extents(ctrl)
+    errs = {}
+    for mode in ("decasteljau", "hybrid", "seiler"):
+        tex = bz.build_texture(to_dev(ctrl), mode)
+        got = host(bz.eval_texture(tex, 3, mode, to_dev(t), 8, "nearest"))
+        ref = orc.tex_eval(host(tex).astype(np.float32), 3, mode, t, False, 8, "nearest")
+        assert bbox_err(got, ref, ext, 256) <= TOL_F32
+        errs[mode] = bbox_err(got, exact, ext, 256)
+    assert errs["hybrid"] < errs["decasteljau"] < errs["seiler"]
+    assert errs["seiler"] < 2 ** -6
+
+
+def test_errors():
+    ctrl = to_dev(_curves(4, 3, 3, 550))
+    tex = bz.build_texture(ctrl, "decasteljau")
+    t = to_dev(np.zeros(8, np.float32))
+    assert bz.texture_texels(6, "seiler") == 0 and bz.texture_texels(9, "decasteljau") == 0
+    with pytest.raises(bz.BzError) as e:
+        bz.build_texture(to_dev(_curves(4, 6, 3, 551)), "seiler")
+    assert e.value.code == bz.ERR_UNSUPPORTED
+    with pytest.raises(bz.BzError) as e:
+        bz.eval_texture(tex, 3, "decasteljau", t, frac_bits=21)
+    assert e.value.code == bz.ERR_SHAPE
+    with pytest.raises(bz.BzError) as e:
+        bz.check(bz.lib().bz_eval_texture(tex.data_ptr() + 4, 4, 3, 3, 0, t.data_ptr(), 8, 0, 8, 0,
+                                          torch.empty(3 * 32, device=tex.device).data_ptr(), None))
+    assert e.value.code == bz.ERR_ALIGN
+    empty = bz.eval_texture(tex, 3, "decasteljau", to_dev(np.zeros(0, np.float32)))
+    assert empty.shape == (3, 0)
+
+
+# ------------------------------------------------------------ chain
+@pytest.mark.parametrize("n_seg,dim,n_q", [(1, 3, 100), (7, 1, 1000), (1000, 3, 5003), (2048, 2, 70001),
+                                           (777, 4, 4099)])
+@pytest.mark.parametrize("frac_bits,rounding", [(8, "nearest"), (8, "truncate"), (0, "nearest")])
+def test_chain_texemu_parity(orc, n_seg, dim, n_q, frac_bits, rounding):
+    chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=n_q, seed=7 * n_seg + dim)
+    grid = orc.piecewise_encode(chain).astype(np.float32)
+    got = host(bz.eval_piecewise_texemu(to_dev(grid), to_dev(T), frac_bits, rounding))
+    ref = orc.chain_texemu_eval(grid, T, frac_bits, rounding)
+    scale = max(float((chain.max(axis=0) - chain.min(axis=0)).max()), float(np.abs(grid).max()))
+    assert np.abs(got - ref).max() <= TOL_F32 * scale
+
+
+def test_chain_texemu_edges(orc):
+    n_seg = 64
+    chain, _ = bz_synth.chain_walk(n_seg=n_seg, dim=3, n_q=1, seed=560)
+    grid = bz.encode_piecewise(to_dev(chain))
+    T = np.array([-5.0, 0.0, 64.0, 70.0, np.inf, -np.inf, np.nan, 1 + 0.5 / 256, 3 + 100.5 / 256] +
+                 list(range(65)), np.float32)
+    got = host(bz.eval_piecewise_texemu(grid, to_dev(T)))
+    ref = orc.chain_texemu_eval(host(grid).astype(np.float32), T)
+    assert np.isnan(got[:, 6]).all()
+    ok = np.arange(T.size) != 6
+    assert np.abs(got[:, ok] - ref[:, ok]).max() <= 1e-5
+    np.testing.assert_array_equal(got[:, 9:].T, chain[0::2])
+
+
+def test_chain_texemu_full_size(orc):
+    """2^20 segments, 2^24 random T, 8-bit nearest weights: every query
+    against the oracle's emulated filter."""
+    chain, T = bz_synth.chain_walk()
+    grid = bz.encode_piecewise(to_dev(chain))
+    got = host(bz.eval_piecewise_texemu(grid, to_dev(T)))
+    gh = host(grid).astype(np.float32)
+    ref = orc.chain_texemu_eval(gh, T)
+    scale = max(float((chain.max(axis=0) - chain.min(axis=0)).max()), float(np.abs(gh).max()))
+    assert np.abs(got - ref).max() / scale <= TOL_F32

@@ -271,3 +271,23 @@ def test_chain_error_bound(orc):
     odd = (np.floor(Td).astype(np.int64) & 1) == 1
     assert err[tie & ~odd].max() <= dmax * (2 ** -9 + 2 ** -23) + 1e-6
     assert err[tie & odd].max() > err[~tie].max()
+
+
+def test_hybrid_error_is_two_thirds_of_trilinear_error(orc):
+    """To first order in d = w - t the trilinear read errs by C'(t) d and the
+    hybrid read by ((1-t) Q0'(t) + t Q1'(t)) d = (2/3) C'(t) d (the Bernstein
+    derivative of the cubic is 3 sum B_i^2 (b_i+1 - b_i), that of the lerped
+    quadratics 2 sum B_i^2 (b_i+1 - b_i)); the rest is O(d^2) with
+    |C''| <= 6 max|b_i+2 - 2 b_i+1 + b_i|."""
+    rng = np.random.default_rng(390)
+    ctrl = _curves(300, 3, 1, 391)
+    t = rng.random(128).astype(np.float32)
+    ref = orc.bezier_decasteljau(ctrl, t)
+    e_dc = orc.tex_eval(orc.tex_build(ctrl, "decasteljau").astype(np.float32), 3, "decasteljau", t) - ref
+    e_hy = orc.tex_eval(orc.tex_build(ctrl, "hybrid").astype(np.float32), 3, "hybrid", t) - ref
+    c = ctrl[:, 0].astype(np.float64)
+    d2 = np.abs(c[:, 2:] - 2 * c[:, 1:-1] + c[:, :-2]).max(axis=1)
+    d = 2.0 ** -9 + 2.0 ** -24
+    slack = (6 * d2 * d * d)[:, None] + 1e-12
+    assert (np.abs(e_hy - 2.0 / 3.0 * e_dc).reshape(300, 128) <= slack).all()
+    assert np.abs(e_dc).max() > 1e-4
