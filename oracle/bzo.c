@@ -589,7 +589,7 @@ void bzo_cubic_chain_eval(const double *chain, int64_t nseg, int dim, const doub
 /* Texture-filter emulation (Sec. 2: texel values sit at texel centres and
  * 2x2 / 2x2x2 textures hold de Casteljau levels; Sec. 2.1: the zig-zag
  * chain texture; Sec. 2.3: fixed-point filter weights with 8 fractional
- * bits; Sec. 3 with Table 1: Seiler textures read at (t, st[, st]);
+ * bits; Sec. 3 with Table 1: Seiler textures read at (t, st[, st]), degrees 6 and 7 at (t, st, (st)^2);
  * Fig. 3: the trilinear, hybrid and Seiler modes of a cubic).
  *
  * Per axis a linear filter blends the two texels around the sample with
@@ -658,10 +658,18 @@ int bzo_tex_texels(int deg, int mode)
  * (b_i, b_i+1, b_i+2) as [[b_i, b_i+1], [b_i+1, b_i+2]]: its bilinear read
  * at (t,t) is that quadratic's point, and the trilinear read of layers i
  * and i+1 at (t,t,t) is the point of the cubic (b_i .. b_i+3).
- * Seiler (degree 2..5, Table 1), with d_j the difference terms:
+ * Seiler (degree 2..5 as Table 1, 6..7 below), with d_j the difference terms:
  *   2: [[b0, b2], [b0+d1, b2+d1]]      3: [[b0, b3], [b0+d1, b3+d2]]
  *   4: [[b0, b4], [b0, b4]] then [[b0+d1, b4+d3], [b0+d1+d2, b4+d3+d2]]
- *   5: [[b0, b5], [b0, b5]] then [[b0+d1, b5+d4], [b0+d1+d2, b5+d4+d3]]  */
+ *   5: [[b0, b5], [b0, b5]] then [[b0+d1, b5+d4], [b0+d1+d2, b5+d4+d3]]
+ * read at (t, st) or (t, st, st).  Degrees 6 and 7 (the 2x2x2 case the
+ * paper's conclusion expects to exist): a trilinear read at (x, y, z) spans
+ * {1, x, y, z, xy, xz, yz, xyz}; at (t, st, (st)^2) these have the distinct
+ * degrees 0..7 in t, so every degree-7 curve fits.  Matching
+ *   L(b0,bd,t) + st L(d1,d_{d-1},t) + (st)^2 L(d2,d_{d-2},t) + (st)^3 L(d3,d_{d-3},t)
+ * (d_{d-3} = d3 for d = 6) term by term gives
+ *   6/7: [[b0, bd], [b0+d1, bd+d_{d-1}]] then
+ *        [[b0+d2, bd+d_{d-2}], [b0+d1+d2+d3, bd+d_{d-1}+d_{d-2}+d_{d-3}]]      */
 void bzo_tex_build(const double *ctrl, int64_t n, int deg, int dim, int mode, double *tex)
 {
     const int nt = bzo_tex_texels(deg, mode);
@@ -688,6 +696,14 @@ void bzo_tex_build(const double *ctrl, int64_t n, int deg, int dim, int mode, do
             } else if (deg == 3) {
                 const double d1 = sc[2], d2 = sc[3];
                 T[0] = b0, T[1] = bd, T[2] = b0 + d1, T[3] = bd + d2;
+            } else if (deg >= 6) {
+                /* deg 6: d1, d5, d2, d4, d3 = sc[2..6];
+                 * deg 7: d1, d6, d2, d5, d3, d4 = sc[2..7]                   */
+                const double d1 = sc[2], dl1 = sc[3], d2 = sc[4], dl2 = sc[5], d3 = sc[6];
+                const double dl3 = deg == 6 ? sc[6] : sc[7];
+                T[0] = b0, T[1] = bd, T[2] = b0 + d1, T[3] = bd + dl1;
+                T[4] = b0 + d2, T[5] = bd + dl2;
+                T[6] = b0 + d1 + d2 + d3, T[7] = bd + dl1 + dl2 + dl3;
             } else {
                 /* deg 4: d1, d3, d2 = sc[2], sc[3], sc[4];
                  * deg 5: d1, d4, d2, d3 = sc[2], sc[3], sc[4], sc[5]         */
@@ -715,6 +731,7 @@ void bzo_tex_eval(const float *tex, int64_t n, int deg, int dim, int mode, const
             const double w = bzo_tex_axis_weight(p, frac_bits, rounding);
             const float st = (1.0f - p) * p;
             const double wst = bzo_tex_axis_weight(st, frac_bits, rounding);
+            const double wst2 = bzo_tex_axis_weight(st * st, frac_bits, rounding);
             for (int k = 0; k < dim; ++k) {
                 const float *T = tex + (c * dim + k) * ntx;
                 double L[8 * BZO_MAXDEG];
@@ -723,7 +740,8 @@ void bzo_tex_eval(const float *tex, int64_t n, int deg, int dim, int mode, const
                 if (isnan(p)) {
                     v = NAN;
                 } else if (mode == BZO_TEX_SEILER) {
-                    v = deg <= 3 ? tex_bilinear(L, w, wst) : tex_trilinear(L, L + 4, w, wst, wst);
+                    v = deg <= 3 ? tex_bilinear(L, w, wst)
+                                 : tex_trilinear(L, L + 4, w, wst, deg <= 5 ? wst : wst2);
                 } else {
                     /* texture reads: level-3 points (trilinear, de Casteljau
                      * mode from degree 3) or level-2 points (bilinear) */

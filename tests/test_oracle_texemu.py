@@ -67,7 +67,7 @@ def test_weight_bounds_clamp_and_monotone(orc):
 # ------------------------------------------------------------ curve textures
 def test_texel_counts(orc):
     assert [orc.tex_texels(d, "decasteljau") for d in (2, 3, 4, 7)] == [4, 8, 12, 24]
-    assert [orc.tex_texels(d, "seiler") for d in (2, 3, 4, 5)] == [4, 4, 8, 8]
+    assert [orc.tex_texels(d, "seiler") for d in (2, 3, 4, 5, 6, 7)] == [4, 4, 8, 8, 8, 8]
 
 
 def test_decasteljau_layers_are_the_quadratic_textures(orc):
@@ -99,7 +99,7 @@ def test_seiler_textures_match_table1(orc):
 
 
 @pytest.mark.parametrize("mode,degs", [("decasteljau", range(2, 9)), ("hybrid", range(2, 9)),
-                                       ("seiler", range(2, 6))])
+                                       ("seiler", range(2, 8))])
 def test_unrounded_weights_give_the_curve(orc, mode, degs):
     """F = 0: every mode reads the curve itself (texels rounded once to
     FP32; the remap moves p by at most 2^-24)."""
@@ -291,3 +291,52 @@ def test_hybrid_error_is_two_thirds_of_trilinear_error(orc):
     slack = (6 * d2 * d * d)[:, None] + 1e-12
     assert (np.abs(e_hy - 2.0 / 3.0 * e_dc).reshape(300, 128) <= slack).all()
     assert np.abs(e_dc).max() > 1e-4
+
+
+# ------------------------------------------------------------ degree 7 in 2x2x2
+def _poly_mul(a, b):
+    return np.convolve(a, b)
+
+
+def _trilinear_span_rank(y, z):
+    """Rank of {1, x, y, z, xy, xz, yz, xyz} with x = t as integer
+    polynomials in t (coefficient vectors, degree <= 9)."""
+    x = np.array([0, 1])
+    one = np.array([1])
+    prods = [one, x, y, z, _poly_mul(x, y), _poly_mul(x, z), _poly_mul(y, z), _poly_mul(_poly_mul(x, y), z)]
+    M = np.zeros((8, 10))
+    for r, p in enumerate(prods):
+        M[r, :len(p)] = p
+    return np.linalg.matrix_rank(M), max(len(p) for p in prods) - 1
+
+
+def test_conjecture_by_dimension_count():
+    """A 2x2x2 read at (t, st, st) (the layout of degrees 4 and 5) spans only
+    the polynomials of degree <= 5 -- two of its eight products coincide --
+    while (t, st, (st)^2) spans all polynomials of degree <= 7: eight texels
+    for eight control points, as the conclusion anticipates."""
+    st = np.array([0, 1, -1])  # t - t^2
+    st2 = _poly_mul(st, st)
+    assert _trilinear_span_rank(st, st) == (6, 5)
+    assert _trilinear_span_rank(st, st2) == (8, 7)
+
+
+@pytest.mark.parametrize("d", [6, 7])
+def test_degree_6_7_layout_exact(orc, d):
+    """The 2x2x2 Seiler layout read at (t, st, (st)^2) in exact rational
+    arithmetic equals the curve's Bernstein sum."""
+    from fractions import Fraction
+    from tests import _exact as ex
+    ctrl = _curves(3, d, 1, 395 + d)
+    tex = orc.tex_build(ctrl, "seiler")
+    for c in range(3):
+        T = [Fraction(v) for v in tex[c, 0]]
+        b = [ex.F(v) for v in ctrl[c, 0]]
+        for t in (Fraction(0), Fraction(1), Fraction(1, 3), Fraction(5, 7), Fraction(1, 2)):
+            y, z = (1 - t) * t, ((1 - t) * t) ** 2
+
+            def lx(a, bb):
+                return (1 - t) * a + t * bb
+            v = (1 - z) * ((1 - y) * lx(T[0], T[1]) + y * lx(T[2], T[3])) + \
+                z * ((1 - y) * lx(T[4], T[5]) + y * lx(T[6], T[7]))
+            assert abs(v - ex.bezier(b, t)) < Fraction(1, 2 ** 40)
