@@ -350,3 +350,37 @@ def chain_texemu_eval(grid, T, frac_bits=8, rounding="nearest"):
     lib().bzo_chain_texemu_eval(_ptr(grid), _I64(nseg), ctypes.c_int(dim), _ptr(T), _I64(T.shape[0]),
                                 ctypes.c_int(frac_bits), ctypes.c_int(ROUNDINGS[rounding]), _ptr(out))
     return out
+
+
+# ------------------------------------------------ Seiler surfaces and volumes
+def tensor_to_seiler(ctrl, du, dv, dw=0):
+    """Per-axis Seiler terms sc[n][dim][ncp] of tensor control points."""
+    ctrl = _d(ctrl)
+    n, dim, ncp = ctrl.shape
+    assert ncp == (du + 1) * (dv + 1) * (dw + 1)
+    sc = np.empty_like(ctrl)
+    lib().bzo_tensor_to_seiler(_ptr(ctrl), _I64(n), ctypes.c_int(du), ctypes.c_int(dv), ctypes.c_int(dw),
+                               ctypes.c_int(dim), _ptr(sc))
+    return sc
+
+
+def tensor_seiler_points(sc, du, dv, dw, uvw):
+    """Nested per-axis Seiler evaluation at uvw[n][n_per][2|3] -> out[dim][n*n_per]."""
+    sc = _d(sc)
+    n, dim, _ = sc.shape
+    uvw = _d(uvw)
+    n_per = uvw.shape[1]
+    out = np.empty((dim, n * n_per))
+    lib().bzo_tensor_seiler_points(_ptr(sc), _I64(n), ctypes.c_int(du), ctypes.c_int(dv), ctypes.c_int(dw),
+                                   ctypes.c_int(dim), _ptr(uvw), _I64(n_per), _ptr(out))
+    return out
+
+
+def tensor_seiler_grid(sc, du, dv, nu, nv):
+    """Nested per-axis Seiler evaluation of surfaces on the inclusive nu x nv
+    grid (u_a = a/(nu-1), v_b = b/(nv-1)) -> out[dim][n*nu*nv]."""
+    n = np.asarray(sc).shape[0]
+    u = np.arange(nu) / max(nu - 1, 1)
+    v = np.arange(nv) / max(nv - 1, 1)
+    uv = np.stack(np.meshgrid(u, v, indexing="ij"), axis=-1).reshape(1, nu * nv, 2)
+    return tensor_seiler_points(sc, du, dv, 0, np.repeat(uv, n, axis=0))

@@ -589,7 +589,7 @@ void bzo_cubic_chain_eval(const double *chain, int64_t nseg, int dim, const doub
 /* Texture-filter emulation (Sec. 2: texel values sit at texel centres and
  * 2x2 / 2x2x2 textures hold de Casteljau levels; Sec. 2.1: the zig-zag
  * chain texture; Sec. 2.3: fixed-point filter weights with 8 fractional
- * bits; Sec. 3 with Table 1: Seiler textures read at (t, st[, st]), degrees 6 and 7 at (t, st, (st)^2);
+ * bits; Sec. 4 with Table 1: Seiler textures read at (t, st[, st]), degrees 6 and 7 at (t, st, (st)^2);
  * Fig. 3: the trilinear, hybrid and Seiler modes of a cubic).
  *
  * Per axis a linear filter blends the two texels around the sample with
@@ -796,4 +796,69 @@ void bzo_chain_texemu_eval(const float *grid, int64_t nseg, int dim, const float
             out[c * nq + q] = tex_bilinear(L, wx, wy);
         }
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Seiler surfaces and volumes (Sec. 2.2 splits a tensor product over its
+ * axes; Sec. 3 gives the Seiler form of one axis; Sec. 6 leaves surfaces
+ * and volumes in Seiler form open).  Reading: per-axis Seiler terms -- the
+ * Seiler conversion of a curve applied to every fibre of the control net
+ * along w, then v, then u (it is linear, so the order is immaterial);
+ * storage sc[n][dim][(du+1)(dv+1)(dw+1)] indexed like the control points,
+ * each axis in the curve order [b0, bd, d1, d_{d-1}, ...].  Evaluation nests
+ * the Seiler recursion of each axis: w innermost, then v, then u.          */
+static void fibre_to_seiler(double *a, int64_t stride, int deg)
+{
+    double b[BZO_MAXDEG + 1] = {0}, sc[BZO_MAXDEG + 1];
+    if (deg < 1) return;
+    for (int i = 0; i <= deg; ++i) b[i] = a[i * stride];
+    seiler_coeffs(b, deg, sc);
+    for (int i = 0; i <= deg; ++i) a[i * stride] = sc[i];
+}
+
+void bzo_tensor_to_seiler(const double *ctrl, int64_t n, int du, int dv, int dw, int dim, double *sc)
+{
+    const int nv = dv + 1, nw = dw + 1, ncp = (du + 1) * nv * nw;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n * dim; ++r) {
+        double *a = sc + r * ncp;
+        for (int e = 0; e < ncp; ++e) a[e] = ctrl[r * ncp + e];
+        for (int i = 0; i <= du; ++i)
+            for (int j = 0; j <= dv; ++j) fibre_to_seiler(a + (i * nv + j) * nw, 1, dw);
+        for (int i = 0; i <= du; ++i)
+            for (int k = 0; k <= dw; ++k) fibre_to_seiler(a + i * nv * nw + k, nw, dv);
+        for (int j = 0; j <= dv; ++j)
+            for (int k = 0; k <= dw; ++k) fibre_to_seiler(a + j * nw + k, nv * nw, du);
+    }
+}
+
+static double seiler_fibre_point(const double *a, int64_t stride, int deg, double t)
+{
+    double sc[BZO_MAXDEG + 1];
+    for (int i = 0; i <= deg; ++i) sc[i] = a[i * stride];
+    return seiler_point(sc, deg, t);
+}
+
+void bzo_tensor_seiler_points(const double *sc, int64_t n, int du, int dv, int dw, int dim, const double *uvw,
+                              int64_t n_per, double *out)
+{
+    const int nv = dv + 1, nw = dw + 1, ncp = (du + 1) * nv * nw;
+    const int npar = dw > 0 ? 3 : 2;
+    const int64_t nq = n * n_per;
+#pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < n; ++o)
+        for (int64_t j = 0; j < n_per; ++j) {
+            const double *p = uvw + (o * n_per + j) * npar;
+            for (int c = 0; c < dim; ++c) {
+                const double *a = sc + (o * dim + c) * ncp;
+                double Ru[BZO_MAXDEG + 1];
+                for (int i = 0; i <= du; ++i) {
+                    double Rv[BZO_MAXDEG + 1];
+                    for (int jj = 0; jj <= dv; ++jj)
+                        Rv[jj] = dw > 0 ? seiler_fibre_point(a + (i * nv + jj) * nw, 1, dw, p[2]) : a[i * nv + jj];
+                    Ru[i] = seiler_point(Rv, dv, p[1]);
+                }
+                out[c * nq + o * n_per + j] = seiler_point(Ru, du, p[0]);
+            }
+        }
 }
