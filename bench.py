@@ -277,15 +277,28 @@ def suite_volumes(torch, bz, bz_synth, cpu):
     res = {"kernel_ms": ms, "value": n * per / (ms * 1e-3) / 1e9, "hbm": hbm_roof(nbytes, ms),
            "roofline": {"bound": "alu", "achieved": tf, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": tf / FP32_VALU_PEAK_TFLOPS}}
+    # the same volumes in per-axis Seiler form (terms converted once)
+    sc = bz.tensor_to_seiler(c_d, 3, 3, 3)
+    torch.cuda.synchronize()
+    conv_ms = event_time_ms(lambda: bz.tensor_to_seiler(c_d, 3, 3, 3, out=sc), 3, torch)
+    out_s = torch.empty_like(out)
+    ms_s = timed(lambda: bz.eval_tensor_seiler(sc, 3, 3, 3, uvw=u_d, out=out_s), torch)
+    tf_s = flop / (ms_s * 1e-3) / 1e12
+    res["seiler"] = {"kernel_ms": ms_s, "value": n * per / (ms_s * 1e-3) / 1e9, "convert_ms": conv_ms,
+                     "roofline": {"bound": "alu", "achieved": tf_s, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf_s / FP32_VALU_PEAK_TFLOPS}}
     if cpu:
         import oracle
         k = 512
         ref, sec, _ = oracle_timed(lambda: oracle.tensor_points(ctrl[:k], 3, 3, 3, uvw[:k]), 3.0)
+        gs = out_s.view(3, n, per)[:, :k].cpu().numpy().reshape(3, -1)
+        res["seiler"]["max_err_bbox"] = max_err_bbox(gs, ref, extents(ctrl[:k]), per)
         res["cpu_baseline"] = {"value": k * per / sec / 1e9, "unit": "G points/s", "cores": oracle.max_threads(),
                                "kind": "oracle", "sample": "first 512 volumes x 256 points"}
         got = out.view(3, n, per)[:, :k].cpu().numpy().reshape(3, -1)
         res["max_err_bbox"] = max_err_bbox(got, ref, extents(ctrl[:k]), per)
-    return {"workload": "2^16 tricubic 3D volumes at 2^24 random (u,v,w)", "unit": "G points/s", **res}
+    return {"workload": "2^16 tricubic 3D volumes at 2^24 random (u,v,w); Bernstein and per-axis Seiler forms",
+            "unit": "G points/s", **res}
 
 
 def suite_cubic_chain(torch, bz, bz_synth, cpu):
@@ -346,6 +359,21 @@ def suite_texemu(torch, bz, bz_synth, cpu):
                 r["max_err_bbox_vs_oracle_emulation"] = max_err_bbox(got, ref, ext, nt)
             e[rounding] = r
         res[mode] = e
+    # degree 7 in one 2x2x2 Seiler texture read at (t, st, (st)^2)
+    c7, _ = bz_synth.random_curves(1 << 14, 7, 3, nt, seed=1001 + 700, per_object=False)
+    c7_d = torch.from_numpy(c7).cuda()
+    tex7 = bz.build_texture(c7_d, "seiler")
+    o7 = torch.empty((3, c7.shape[0] * nt), device="cuda")
+    ms = timed(lambda: bz.eval_texture(tex7, 7, "seiler", t_d, 8, "nearest", out=o7), torch)
+    r = {"kernel_ms": ms, "value": c7.shape[0] * nt / (ms * 1e-3) / 1e9,
+         "roofline": hbm_roof(tex7.numel() * 4 + t.nbytes + o7.numel() * 4, ms)}
+    if cpu:
+        got = o7[:, :sub * nt].cpu().numpy()
+        e7 = extents(c7[:sub])
+        r["quantisation_err_bbox"] = max_err_bbox(got, oracle.bezier_decasteljau(c7[:sub], t), e7, nt)
+        ref = oracle.tex_eval(tex7[:sub].cpu().numpy(), 7, "seiler", t, False, 8, "nearest")
+        r["max_err_bbox_vs_oracle_emulation"] = max_err_bbox(got, ref, e7, nt)
+    res["seiler_degree7"] = r
     del out
     chain, T = bz_synth.chain_walk()
     nseg, nq = (chain.shape[0] - 1) // 2, T.shape[0]
@@ -372,7 +400,8 @@ def suite_texemu(torch, bz, bz_synth, cpu):
         res["cpu_baseline"] = {"value": sub * nt / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
                                "kind": "oracle", "sample": "1024 curves x 256 t, trilinear mode"}
     return {"workload": "texture-filter emulation, 8 fractional weight bits: 65536 cubic 3D curves x 256 shared t "
-                        "in the trilinear / hybrid / Seiler modes (quantisation error on the first 1024 curves), "
+                        "in the trilinear / hybrid / Seiler modes (quantisation error on the first 1024 curves), 16384 "
+                        "degree-7 curves in one 2x2x2 Seiler texture, "
                         "and the 2^20-segment chain at 2^24 random T", "unit": "G evals/s", **res}
 
 

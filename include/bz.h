@@ -171,7 +171,7 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
 /*
  * Texture-filter emulation (Sec. 2: texel values at texel centres, 2x2 and
  * 2x2x2 textures holding de Casteljau levels; Sec. 2.3: filter weights in
- * fixed point with 8 fractional bits; Sec. 3 with Table 1: Seiler textures;
+ * fixed point with 8 fractional bits; Sec. 4 with Table 1: Seiler textures;
  * Fig. 3: the three ways of reading a cubic).  No texture unit is used: the
  * filter runs on the vector ALUs.
  *
@@ -185,7 +185,7 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
  *
  * bz_texture_texels: texels per curve and coordinate for (degree, mode), 0
  * if unsupported.  De Casteljau and hybrid: 4(degree-1), degree 2..8;
- * Seiler: 4 (degree 2, 3) or 8 (degree 4, 5).
+ * Seiler: 4 (degree 2, 3) or 8 (degree 4..7).
  * bz_build_texture: ctrl[n][dim][degree+1] FP32 -> tex[n][dim][texels],
  * 2x2 layers stored [layer][row][column] (tex 16-byte aligned).
  *   de Casteljau / hybrid: layer i = [[b_i, b_i+1], [b_i+1, b_i+2]];
@@ -193,13 +193,16 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
  *     2: [[b0, b2], [b0+d1, b2+d1]]   3: [[b0, b3], [b0+d1, b3+d2]]
  *     4: [[b0, b4], [b0, b4]], [[b0+d1, b4+d3], [b0+d1+d2, b4+d3+d2]]
  *     5: [[b0, b5], [b0, b5]], [[b0+d1, b5+d4], [b0+d1+d2, b5+d4+d3]]
+ *     6, 7 (one 2x2x2 texture, the case Sec. 6 anticipates; e_j = d_{d-j}):
+ *       [[b0, bd], [b0+d1, bd+e1]], [[b0+d2, bd+e2], [b0+d1+d2+d3, bd+e1+e2+e3]]
  * bz_eval_texture: tex as built, t / t_mode / out as bz_eval_bezier.
  *   BZ_TEX_DECASTELJAU: degree 2 one bilinear read at (t,t); degree >= 3 a
  *     trilinear read of layers i, i+1 at (t,t,t) per cubic sub-curve, then
  *     the remaining degree-3 de Casteljau levels as FP32 lerps with t.
  *   BZ_TEX_HYBRID: a bilinear read of every layer, then degree-2 FP32 levels.
  *   BZ_TEX_SEILER: one bilinear read at (t, st) (degree 2, 3) or trilinear at
- *     (t, st, st) (degree 4, 5), st = (1-t)t formed in FP32 before the remap.
+ *     (t, st, st) (degree 4, 5) or (t, st, (st)^2) (degree 6, 7), st = (1-t)t
+ *     and (st)^2 formed in FP32 before the remap.
  * bz_eval_piecewise_texemu: the zig-zag grid of bz_encode_piecewise read by
  *   the emulated bilinear filter in texel space: T is clamped to [0,N] and
  *   placed at x = T + 1/2 (texel centres at column + 1/2), k = min(floor(x -
@@ -234,6 +237,24 @@ int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const fl
 int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, int du, int dv, int dw, int dim,
                          const float *uvw, int64_t n_per, int nu, int nv, int engine, float *out,
                          bz_stream stream);
+
+/*
+ * Seiler surfaces and volumes (Sec. 3's Seiler form applied per axis of the
+ * Sec. 2.2 tensor product; Sec. 6 leaves Seiler surfaces and volumes open).
+ * bz_tensor_to_seiler: FP32 ctrl[n_obj][dim][(du+1)(dv+1)(dw+1)] (u major)
+ *   -> sc of the same shape: every fibre of the net converted to Seiler terms
+ *   [b0, bd, d1, d_{d-1}, d2, ...] along w, then v, then u, in FP64, each
+ *   term rounded once.  Degrees 1..4 per axis (dw 0..4).
+ * bz_eval_tensor_seiler: sc as above; grid mode (uvw == NULL, surfaces) and
+ *   points mode exactly as bz_eval_tensor_patch; evaluates the nested
+ *   per-axis Seiler recursion L(b0,bd,t) + st (L(d1,d_{d-1},t) + st ...) as a
+ *   separable contraction with the per-axis Seiler basis (1-t, t, st(1-t),
+ *   st t, ..., (st)^(d/2) for even d).  FP32 throughout.
+ */
+int bz_tensor_to_seiler(const float *ctrl, int64_t n_obj, int du, int dv, int dw, int dim, float *sc,
+                        bz_stream stream);
+int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw, int dim, const float *uvw,
+                          int64_t n_per, int nu, int nv, float *out, bz_stream stream);
 
 /*
  * Mixed batches in one persistent launch: integral and rational Bezier

@@ -59,6 +59,8 @@ _SIGS = {
     "bz_build_texture": (_I, [_P, _I64, _I, _I, _I, _P, _P]),
     "bz_eval_texture": (_I, [_P, _I64, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
     "bz_eval_piecewise_texemu": (_I, [_P, _I64, _I, _P, _I64, _I, _I, _P, _P]),
+    "bz_tensor_to_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
+    "bz_eval_tensor_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -285,6 +287,27 @@ def eval_tensor_patch(ctrl, du, dv, dw=0, uvw=None, nu=0, nv=0, engine="valu", o
     out = _f32_out((dim, nq), ctrl.device, out)
     check(lib().bz_eval_tensor_patch(_ptr(ctrl), _dtype(ctrl), n, du, dv, dw, dim, _ptr(uvw), n_per, nu, nv,
                                      ENGINES[engine], _ptr(out), _stream()))
+    return out
+
+
+def tensor_to_seiler(ctrl, du, dv, dw=0, out=None):
+    """FP32 tensor control points [n, dim, ncp] -> per-axis Seiler terms (same shape)."""
+    n, dim, ncp = ctrl.shape
+    out = _f32_out((n, dim, ncp), ctrl.device, out)
+    check(lib().bz_tensor_to_seiler(_ptr(ctrl), n, du, dv, dw, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_tensor_seiler(sc, du, dv, dw=0, uvw=None, nu=0, nv=0, out=None):
+    """Per-axis Seiler terms [n, dim, ncp] -> points (grid or uvw mode, as eval_tensor_patch)."""
+    n, dim, _ = sc.shape
+    if uvw is None:
+        nq, n_per = n * nu * nv, 0
+    else:
+        n_per = uvw.shape[1]
+        nq = n * n_per
+    out = _f32_out((dim, nq), sc.device, out)
+    check(lib().bz_eval_tensor_seiler(_ptr(sc), n, du, dv, dw, dim, _ptr(uvw), n_per, nu, nv, _ptr(out), _stream()))
     return out
 
 

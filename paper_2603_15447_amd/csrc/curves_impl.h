@@ -61,13 +61,13 @@ __device__ __forceinline__ float dot_basis(const float (&B)[D + 1], const float 
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <int D, typename Acc = double, typename Out = float>
-__device__ __forceinline__ void seiler_terms(const float (&b)[D + 1], Out (&sc)[D + 1]) {
+template <int D, typename Acc = double, typename Out = float, typename In = float>
+__device__ __forceinline__ void seiler_terms(const In (&b)[D + 1], Out (&sc)[D + 1]) {
     Acc Q[D + 1];
 #pragma unroll
     for (int i = 0; i <= D; ++i) Q[i] = static_cast<Acc>(b[i]);
-    sc[0] = b[0];
-    sc[1] = b[D];
+    sc[0] = static_cast<Out>(b[0]);
+    sc[1] = static_cast<Out>(b[D]);
     int pos = 2;
 #pragma unroll
     for (int n = D; n >= 2; n -= 2) {

@@ -17,131 +17,11 @@
 //                  that its largest entry lies in [0.5, 1)) and sums the
 //                  products hi*hi + hi*lo + lo*hi in the FP32 accumulator,
 //                  which recovers FP32-class accuracy from FP16 MFMAs.
-#include "curves_impl.h"
+#include "tensor_impl.h"
 
 namespace bzi {
 namespace {
 
-template <int D>
-__device__ __forceinline__ void basis_at(float x, float (&B)[D + 1]) {
-    bernstein_basis<D>(x, B);
-}
-
-// ------------------------------------------------------------------ VALU grid
-template <int DU, int DV, int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_tensor_grid(const T *__restrict__ ctrl, int nu, int nv,
-                                                        float *__restrict__ out, int64_t plane, int64_t o0) {
-    constexpr int NCP = (DU + 1) * (DV + 1);
-    const uint32_t o = blockIdx.x;
-    const T *__restrict__ P = ctrl + static_cast<size_t>(o) * DIM * NCP;
-    const int npts = nu * nv;
-    float *__restrict__ ob = out + (o0 + o) * static_cast<int64_t>(npts);
-    const float du_den = nu > 1 ? static_cast<float>(nu - 1) : 1.0f;
-    const float dv_den = nv > 1 ? static_cast<float>(nv - 1) : 1.0f;
-    if (kBlock % nv == 0) {
-        const int b = threadIdx.x % nv;
-        const int astep = kBlock / nv;
-        float Bv[DV + 1];
-        basis_at<DV>(static_cast<float>(b) / dv_den, Bv);
-        float R[DIM][DU + 1];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-#pragma unroll
-            for (int i = 0; i <= DU; ++i) {
-                float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
-#pragma unroll
-                for (int j = 1; j <= DV; ++j) acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
-                R[c][i] = acc;
-            }
-        for (int a = threadIdx.x / nv; a < nu; a += astep) {
-            float Bu[DU + 1];
-            basis_at<DU>(static_cast<float>(a) / du_den, Bu);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) st_stream(ob + c * plane + a * nv + b, dot_basis<DU>(Bu, R[c]));
-        }
-    } else {
-        for (int p = threadIdx.x; p < npts; p += kBlock) {
-            const int a = p / nv, b = p - (p / nv) * nv;
-            float Bu[DU + 1], Bv[DV + 1];
-            basis_at<DU>(static_cast<float>(a) / du_den, Bu);
-            basis_at<DV>(static_cast<float>(b) / dv_den, Bv);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                float Ri[DU + 1];
-#pragma unroll
-                for (int i = 0; i <= DU; ++i) {
-                    float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
-#pragma unroll
-                    for (int j = 1; j <= DV; ++j)
-                        acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
-                    Ri[i] = acc;
-                }
-                st_stream(ob + c * plane + p, dot_basis<DU>(Bu, Ri));
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------------ VALU points
-// One wavefront per object, 4 queries per lane at a time: the object's
-// control points are wave-uniform (scalar loads into SGPRs) and each one
-// feeds the FMAs of 4 queries.  Separable contraction w -> v -> u.
-constexpr int kPtsQ = 4;
-
-template <int DU, int DV, int DW, int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_tensor_points(const T *__restrict__ ctrl, const float *__restrict__ uvw,
-                                                          int64_t n_per, uint32_t n_obj, float *__restrict__ out,
-                                                          int64_t plane, int64_t o0) {
-    constexpr int NCP = (DU + 1) * (DV + 1) * (DW + 1);
-    constexpr int NPAR = DW > 0 ? 3 : 2;
-    const uint32_t o = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
-    if (o >= n_obj) return;
-    const int lane = threadIdx.x & 63;
-    const T *__restrict__ P = ctrl + static_cast<size_t>(o) * DIM * NCP;
-    for (int64_t j0 = 0; j0 < n_per; j0 += 64 * kPtsQ) {
-        float Bu[kPtsQ][DU + 1], Bv[kPtsQ][DV + 1], Bw[kPtsQ][DW + 1];
-        int64_t q[kPtsQ];
-        bool ok[kPtsQ];
-#pragma unroll
-        for (int s = 0; s < kPtsQ; ++s) {
-            const int64_t j = j0 + s * 64 + lane;
-            ok[s] = j < n_per;
-            q[s] = (o0 + o) * n_per + (ok[s] ? j : n_per - 1);
-            const float *__restrict__ p = uvw + q[s] * NPAR;
-            basis_at<DU>(p[0], Bu[s]);
-            basis_at<DV>(p[1], Bv[s]);
-            if constexpr (DW > 0) basis_at<DW>(p[2], Bw[s]);
-            else Bw[s][0] = 1.0f;
-        }
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            float acc[kPtsQ] = {};
-#pragma unroll
-            for (int i = 0; i <= DU; ++i) {
-                float Ri[kPtsQ] = {};
-#pragma unroll
-                for (int jj = 0; jj <= DV; ++jj) {
-                    float Qj[kPtsQ] = {};
-#pragma unroll
-                    for (int k = 0; k <= DW; ++k) {
-                        const float pv = to_f32<T>(P[c * NCP + (i * (DV + 1) + jj) * (DW + 1) + k]);
-#pragma unroll
-                        for (int s = 0; s < kPtsQ; ++s) Qj[s] = __builtin_fmaf(Bw[s][k], pv, Qj[s]);
-                    }
-#pragma unroll
-                    for (int s = 0; s < kPtsQ; ++s) Ri[s] = __builtin_fmaf(Bv[s][jj], Qj[s], Ri[s]);
-                }
-#pragma unroll
-                for (int s = 0; s < kPtsQ; ++s) acc[s] = __builtin_fmaf(Bu[s][i], Ri[s], acc[s]);
-            }
-#pragma unroll
-            for (int s = 0; s < kPtsQ; ++s)
-                if (ok[s]) st_stream(out + c * plane + q[s], acc[s]);
-        }
-    }
-}
-
-// ------------------------------------------------------------------ MFMA grid
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
@@ -261,96 +141,6 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
     }
 }
 
-// ------------------------------------------------------------------ dispatch
-template <typename T, int DU, int DV, int DIM>
-void launch_grid3(const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0, uint32_t blocks,
-                  hipStream_t s) {
-    hipLaunchKernelGGL((k_tensor_grid<DU, DV, DIM, T>), dim3(blocks), dim3(kBlock), 0, s,
-                       static_cast<const T *>(ctrl), nu, nv, out, plane, o0);
-}
-
-template <typename T, int DU, int DV>
-int launch_grid2(int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0, uint32_t blocks,
-                 hipStream_t s) {
-    switch (dim) {
-        case 1: launch_grid3<T, DU, DV, 1>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
-        case 2: launch_grid3<T, DU, DV, 2>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
-        case 3: launch_grid3<T, DU, DV, 3>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
-        default: launch_grid3<T, DU, DV, 4>(ctrl, nu, nv, out, plane, o0, blocks, s); break;
-    }
-    return BZ_OK;
-}
-
-template <typename T, int DU>
-int launch_grid1(int dv, int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0,
-                 uint32_t blocks, hipStream_t s) {
-    switch (dv) {
-        case 1: return launch_grid2<T, DU, 1>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        case 2: return launch_grid2<T, DU, 2>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        case 3: return launch_grid2<T, DU, 3>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        default: return launch_grid2<T, DU, 4>(dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-    }
-}
-
-template <typename T>
-int launch_grid(int du, int dv, int dim, const void *ctrl, int nu, int nv, float *out, int64_t plane, int64_t o0,
-                uint32_t blocks, hipStream_t s) {
-    switch (du) {
-        case 1: return launch_grid1<T, 1>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        case 2: return launch_grid1<T, 2>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        case 3: return launch_grid1<T, 3>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-        default: return launch_grid1<T, 4>(dv, dim, ctrl, nu, nv, out, plane, o0, blocks, s);
-    }
-}
-
-template <typename T, int DU, int DV, int DW>
-int launch_pts3(int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane, int64_t o0,
-                uint32_t n_obj, hipStream_t s) {
-    const T *p = static_cast<const T *>(ctrl);
-    const uint32_t blocks = (n_obj + kBlock / 64 - 1) / (kBlock / 64);
-    switch (dim) {
-        case 1: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 1, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
-        case 2: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 2, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
-        case 3: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 3, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
-        default: hipLaunchKernelGGL((k_tensor_points<DU, DV, DW, 4, T>), dim3(blocks), dim3(kBlock), 0, s, p, uvw, n_per, n_obj, out, plane, o0); break;
-    }
-    return BZ_OK;
-}
-
-template <typename T, int DU, int DV>
-int launch_pts2(int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane,
-                int64_t o0, uint32_t blocks, hipStream_t s) {
-    switch (dw) {
-        case 0: return launch_pts3<T, DU, DV, 0>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 1: return launch_pts3<T, DU, DV, 1>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 2: return launch_pts3<T, DU, DV, 2>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 3: return launch_pts3<T, DU, DV, 3>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        default: return launch_pts3<T, DU, DV, 4>(dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-    }
-}
-
-template <typename T, int DU>
-int launch_pts1(int dv, int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out, int64_t plane,
-                int64_t o0, uint32_t blocks, hipStream_t s) {
-    switch (dv) {
-        case 1: return launch_pts2<T, DU, 1>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 2: return launch_pts2<T, DU, 2>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 3: return launch_pts2<T, DU, 3>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        default: return launch_pts2<T, DU, 4>(dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-    }
-}
-
-template <typename T>
-int launch_pts(int du, int dv, int dw, int dim, const void *ctrl, const float *uvw, int64_t n_per, float *out,
-               int64_t plane, int64_t o0, uint32_t blocks, hipStream_t s) {
-    switch (du) {
-        case 1: return launch_pts1<T, 1>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 2: return launch_pts1<T, 2>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        case 3: return launch_pts1<T, 3>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-        default: return launch_pts1<T, 4>(dv, dw, dim, ctrl, uvw, n_per, out, plane, o0, blocks, s);
-    }
-}
-
 }  // namespace
 }  // namespace bzi
 
@@ -387,9 +177,9 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                 for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
                     const uint32_t blocks = static_cast<uint32_t>(std::min(per, n_obj - o0));
                     const char *c0 = static_cast<const char *>(ctrl) + o0 * dim * ncp * es;
-                    if (dtype == BZ_F32) launch_grid<float>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
-                    else if (dtype == BZ_F16) launch_grid<_Float16>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
-                    else launch_grid<bf16_t>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    if (dtype == BZ_F32) launch_grid<float, kBasisBernstein>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    else if (dtype == BZ_F16) launch_grid<_Float16, kBasisBernstein>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
+                    else launch_grid<bf16_t, kBasisBernstein>(du, dv, dim, c0, nu, nv, out, plane, o0, blocks, s);
                     BZ_CHECK_LAUNCH("k_tensor_grid");
                 }
             } else {
@@ -425,9 +215,9 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
         for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
             const uint32_t blocks = static_cast<uint32_t>(std::min(per, n_obj - o0));
             const char *c0 = static_cast<const char *>(ctrl) + o0 * dim * ncp * es;
-            if (dtype == BZ_F32) launch_pts<float>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
-            else if (dtype == BZ_F16) launch_pts<_Float16>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
-            else launch_pts<bf16_t>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            if (dtype == BZ_F32) launch_pts<float, kBasisBernstein>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            else if (dtype == BZ_F16) launch_pts<_Float16, kBasisBernstein>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
+            else launch_pts<bf16_t, kBasisBernstein>(du, dv, dw, dim, c0, uvw, n_per, out, plane, o0, blocks, s);
             BZ_CHECK_LAUNCH("k_tensor_points");
         }
         return BZ_OK;

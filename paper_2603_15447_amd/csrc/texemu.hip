@@ -5,12 +5,15 @@
 //
 //  k_tex_build       control points -> curve textures: de Casteljau layers
 //                    [[b_i, b_i+1], [b_i+1, b_i+2]] (Sec. 2) or the Seiler
-//                    layouts of Table 1 (Sec. 3), texels formed in FP64.
+//                    layouts of Table 1 (Sec. 4), extended to degrees 6 and 7
+//                    in one 2x2x2 texture (the case Sec. 6 anticipates),
+//                    texels formed in FP64.
 //  k_texemu          one query per thread: clamp t, per-axis weight (remap
 //                    1/4 + t/2, texel-space 2x - 1/2, F-bit rounding), then
 //                    the mode's reads (Fig. 3): one trilinear read (de
 //                    Casteljau), bilinear reads + FP32 lerps (hybrid), or
-//                    the Seiler read at (t, st[, st]).
+//                    the Seiler read at (t, st), (t, st, st) or, for degrees
+//                    6 and 7, (t, st, (st)^2).
 //  k_piecewise_texemu  the zig-zag chain (Sec. 2.1) read through the same
 //                    emulated bilinear filter in texel space.
 //
@@ -83,6 +86,17 @@ __global__ __launch_bounds__(kBlock) void k_tex_build(const float *__restrict__ 
         } else if constexpr (D == 3) {
             T[0] = b[0], T[1] = b[3];
             T[2] = static_cast<float>(b0 + sc[2]), T[3] = static_cast<float>(bd + sc[3]);
+        } else if constexpr (D >= 6) {
+            // Read at (t, st, (st)^2), where the eight trilinear products have
+            // the distinct degrees 0..7 in t: matching L(b0,bd) + st L(d1,
+            // d_{d-1}) + (st)^2 L(d2, d_{d-2}) + (st)^3 L(d3, d_{d-3}) term by
+            // term (d_{d-3} = d3 at degree 6).
+            const double d1 = sc[2], dl1 = sc[3], d2 = sc[4], dl2 = sc[5], d3 = sc[6];
+            const double dl3 = D == 6 ? sc[6] : sc[7];
+            T[0] = b[0], T[1] = b[D];
+            T[2] = static_cast<float>(b0 + d1), T[3] = static_cast<float>(bd + dl1);
+            T[4] = static_cast<float>(b0 + d2), T[5] = static_cast<float>(bd + dl2);
+            T[6] = static_cast<float>(b0 + d1 + d2 + d3), T[7] = static_cast<float>(bd + dl1 + dl2 + dl3);
         } else {
             // degree 4: d1, d3, d2; degree 5: d1, d4, d2, d3
             const double d1 = sc[2], dl = sc[3], d2 = sc[4];
@@ -122,11 +136,12 @@ __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
     p = p < 0.0f ? 0.0f : p;  // clamp-to-edge; NaN passes
     p = p > 1.0f ? 1.0f : p;
     const float w = tx_axis_weight(p, a.frac_bits, a.rounding);
-    float wst = 0.0f;
+    float wst = 0.0f, wz = 0.0f;
     if constexpr (MODE == TX_SEILER) {
 #pragma clang fp contract(off)
         const float st = (1.0f - p) * p;
         wst = tx_axis_weight(st, a.frac_bits, a.rounding);
+        wz = D >= 6 ? tx_axis_weight(st * st, a.frac_bits, a.rounding) : wst;
     }
     const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.tex + static_cast<size_t>(cl) * DIM * NT);
 #pragma unroll
@@ -139,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
         }
         float v;
         if constexpr (MODE == TX_SEILER) {
-            v = D <= 3 ? tx_bilinear(L, w, wst) : lerp(tx_bilinear(L, w, wst), tx_bilinear(L + 4, w, wst), wst);
+            v = D <= 3 ? tx_bilinear(L, w, wst) : lerp(tx_bilinear(L, w, wst), tx_bilinear(L + 4, w, wst), wz);
         } else {
             // texture reads: level-3 points (trilinear) in de Casteljau mode
             // from degree 3, level-2 points (bilinear) otherwise; the
@@ -219,7 +234,7 @@ int launch_build_m(int degree, const float *ctrl, float *tex, uint32_t rows, hip
     const uint32_t blocks = (rows + kBlock - 1) / kBlock;
 #define BZI_TB(D)                                                                                   \
     case D:                                                                                         \
-        if constexpr (MODE != TX_SEILER || D <= 5)                                                  \
+        if constexpr (MODE != TX_SEILER || D <= 7)                                                  \
             hipLaunchKernelGGL((k_tex_build<D, MODE>), dim3(blocks), dim3(kBlock), 0, s, ctrl, tex, rows); \
         break;
     switch (degree) {
@@ -251,21 +266,18 @@ int launch_texemu_m(int degree, int dim, const TexArgs &a, hipStream_t s) {
         case 3: return launch_texemu_dm<3, MODE>(dim, a, s);
         case 4: return launch_texemu_dm<4, MODE>(dim, a, s);
         case 5: return launch_texemu_dm<5, MODE>(dim, a, s);
+        case 6: return launch_texemu_dm<6, MODE>(dim, a, s);
+        case 7: return launch_texemu_dm<7, MODE>(dim, a, s);
         default: break;
     }
     if constexpr (MODE != TX_SEILER) {
-        switch (degree) {
-            case 6: return launch_texemu_dm<6, MODE>(dim, a, s);
-            case 7: return launch_texemu_dm<7, MODE>(dim, a, s);
-            case 8: return launch_texemu_dm<8, MODE>(dim, a, s);
-            default: break;
-        }
+        if (degree == 8) return launch_texemu_dm<8, MODE>(dim, a, s);
     }
     return fail(BZ_ERR_SHAPE, "degree %d", degree);
 }
 
 int tex_texels_rt(int degree, int mode) {
-    if (mode == TX_SEILER) return degree >= 2 && degree <= 5 ? (degree <= 3 ? 4 : 8) : 0;
+    if (mode == TX_SEILER) return degree >= 2 && degree <= 7 ? (degree <= 3 ? 4 : 8) : 0;
     if (mode == TX_DC || mode == TX_HYBRID) return degree >= 2 && degree <= kTexMaxDegree ? 4 * (degree - 1) : 0;
     return 0;
 }
@@ -297,7 +309,7 @@ int bz_build_texture(const float *ctrl, int64_t n_curves, int degree, int dim, i
     return guarded("bz_build_texture", [&]() -> int {
         const char *fn = "bz_build_texture";
         if (tex_texels_rt(degree, mode) == 0)
-            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..5)", fn,
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..7)", fn,
                         mode, degree, kTexMaxDegree);
         if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
         if (n_curves < 0 || n_curves * dim > (int64_t(1) << 31)) return fail(BZ_ERR_SHAPE, "%s: n_curves", fn);
@@ -317,7 +329,7 @@ int bz_eval_texture(const float *tex, int64_t n_curves, int degree, int dim, int
         const char *fn = "bz_eval_texture";
         const int ntx = tex_texels_rt(degree, mode);
         if (ntx == 0)
-            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..5)", fn,
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degree %d (de Casteljau / hybrid 2..%d, Seiler 2..7)", fn,
                         mode, degree, kTexMaxDegree);
         if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
         if (n_curves < 0 || n_t < 0 || n_t > (int64_t(1) << 30)) return fail(BZ_ERR_SHAPE, "%s: counts", fn);

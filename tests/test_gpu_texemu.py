@@ -1,4 +1,4 @@
-"""GPU parity: texture-filter emulation (Sec. 2, Sec. 2.3, Sec. 3 with
+"""GPU parity: texture-filter emulation (Sec. 2, Sec. 2.3, Sec. 4 with
 Table 1, Fig. 3) and the zig-zag chain read through the emulated bilinear
 filter (Sec. 2.1), against the FP64 oracle with the same FP32 weight rule."""
 import numpy as np
@@ -12,7 +12,7 @@ from tests._gpu import TOL_F32, bbox_err, extents, host, to_dev
 pytestmark = pytest.mark.gpu
 
 CASES = [("decasteljau", d) for d in range(2, 9)] + [("hybrid", d) for d in range(2, 9)] + \
-        [("seiler", d) for d in range(2, 6)]
+        [("seiler", d) for d in range(2, 8)]
 
 
 def _curves(n, d, dim, seed):
@@ -89,13 +89,29 @@ def test_eval_fig3_errors_match_oracle(orc):
     assert errs["seiler"] < 2 ** -6
 
 
+def test_degree7_single_read_errors(orc):
+    """Degree-7 curves from one 2x2x2 read at (t, st, (st)^2): exact with
+    unrounded weights (to FP32), and the 8-bit rounding error the oracle
+    predicts."""
+    ctrl = _curves(512, 7, 3, 545)
+    t = (np.arange(256) / 255).astype(np.float32)
+    exact = orc.bezier_decasteljau(ctrl, t)
+    tex = bz.build_texture(to_dev(ctrl), "seiler")
+    for F in (0, 8):
+        got = host(bz.eval_texture(tex, 7, "seiler", to_dev(t), F, "nearest"))
+        ref = orc.tex_eval(host(tex).astype(np.float32), 7, "seiler", t, False, F, "nearest")
+        assert bbox_err(got, ref, extents(ctrl), 256) <= TOL_F32
+        if F == 0:
+            assert bbox_err(got, exact, extents(ctrl), 256) <= 4 * TOL_F32
+
+
 def test_errors():
     ctrl = to_dev(_curves(4, 3, 3, 550))
     tex = bz.build_texture(ctrl, "decasteljau")
     t = to_dev(np.zeros(8, np.float32))
-    assert bz.texture_texels(6, "seiler") == 0 and bz.texture_texels(9, "decasteljau") == 0
+    assert bz.texture_texels(8, "seiler") == 0 and bz.texture_texels(9, "decasteljau") == 0
     with pytest.raises(bz.BzError) as e:
-        bz.build_texture(to_dev(_curves(4, 6, 3, 551)), "seiler")
+        bz.build_texture(to_dev(_curves(4, 8, 3, 551)), "seiler")
     assert e.value.code == bz.ERR_UNSUPPORTED
     with pytest.raises(bz.BzError) as e:
         bz.eval_texture(tex, 3, "decasteljau", t, frac_bits=21)

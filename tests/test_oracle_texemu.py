@@ -1,7 +1,7 @@
 """Pins for the oracle's texture-filter emulation: filter weights on a
 two-texel axis after the texel-centre remap, rounded to F fractional bits
 (Sec. 2, Sec. 2.3), the de Casteljau / hybrid / Seiler curve textures
-(Sec. 2, Sec. 3 with Table 1, Fig. 3) and the zig-zag chain read by the
+(Sec. 2, Sec. 4 with Table 1, Fig. 3) and the zig-zag chain read by the
 emulated bilinear filter (Sec. 2.1)."""
 import numpy as np
 import pytest
