@@ -76,6 +76,17 @@ const char *bz_last_error(void);
 int bz_device_cu_count(void);
 
 /*
+ * Measured HBM ceiling for the rooflines (the paper's performance section
+ * compares against the memory system; MI355X publishes 8 TB/s): a streaming
+ * kernel over n floats (n a multiple of 4, buffers 16-byte aligned) with a
+ * persistent grid of blocks_per_cu x (CU count) workgroups of 256 threads.
+ * mode 0: read src (dst[0] is written only if a thread's partial sum equals
+ * -1, which non-negative data never gives); 1: write dst; 2: copy src to dst.
+ * Timing is the caller's (events around the call).
+ */
+int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, int blocks_per_cu, bz_stream stream);
+
+/*
  * Bezier curves (Sec. 2: de Casteljau recursive lerps; Sec. 3: Seiler
  * interpolation; Sec. 5: the Bernstein polynomial form).
  * ctrl: [n_curves][dim][degree+1] in ctrl_dtype.  t: see t_mode.

@@ -61,6 +61,7 @@ _SIGS = {
     "bz_eval_piecewise_texemu": (_I, [_P, _I64, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_tensor_to_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_tensor_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
+    "bz_hbm_probe": (_I, [_I, _P, _P, _I64, _I, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -219,6 +220,12 @@ def eval_piecewise_cubic(grid, T, out=None):
     out = _f32_out((dim, nq), grid.device, out)
     check(lib().bz_eval_piecewise_cubic(_ptr(grid), nseg, dim, _ptr(T), nq, _ptr(out), _stream()))
     return out
+
+
+def hbm_probe(mode, src, dst, blocks_per_cu=4):
+    """One streaming pass (mode "read", "write" or "copy") over float32 buffers."""
+    m = {"read": 0, "write": 1, "copy": 2}[mode]
+    check(lib().bz_hbm_probe(m, _ptr(src), _ptr(dst), dst.numel() if m else src.numel(), blocks_per_cu, _stream()))
 
 
 def texture_texels(degree, mode):

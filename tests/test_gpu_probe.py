@@ -1,0 +1,25 @@
+"""GPU checks of the HBM probe kernels (measurement utility)."""
+import pytest
+import torch
+
+import paper_2603_15447_amd as bz
+
+pytestmark = pytest.mark.gpu
+
+
+def test_probe_modes():
+    n = (1 << 20) + 4 * 37  # not a multiple of the grid's stride
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.zeros(n, dtype=torch.float32, device="cuda")
+    bz.hbm_probe("copy", src, dst, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    bz.hbm_probe("write", src, dst, 2)
+    torch.cuda.synchronize()
+    assert bool((dst == 1.0).all())
+    bz.hbm_probe("read", src, dst, 8)  # non-negative data: dst untouched
+    torch.cuda.synchronize()
+    assert bool((dst == 1.0).all())
+    with pytest.raises(bz.BzError) as e:
+        bz.check(bz.lib().bz_hbm_probe(2, src.data_ptr(), dst.data_ptr(), 6, 4, None))
+    assert e.value.code == bz.ERR_SHAPE
