@@ -318,11 +318,15 @@ def suite_cubic_chain(torch, bz, bz_synth, cpu):
     grid = bz.encode_piecewise_cubic(c_d)
     torch.cuda.synchronize()
     enc_ms = event_time_ms(lambda: bz.encode_piecewise_cubic(c_d, out=grid), 5, torch)
+    tiles = bz.tile_piecewise_cubic(grid)
     out = torch.empty((dim, n_q), device="cuda")
-    ms = timed(lambda: bz.eval_piecewise_cubic(grid, T_d, out=out), torch)
     nbytes = grid.numel() * 4 + n_q * 4 + n_q * dim * 4
-    res = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms),
-           "algorithmic_bytes": nbytes, "encode_ms": enc_ms}
+    ms_grid = timed(lambda: bz.eval_piecewise_cubic(grid, T_d, out=out), torch)
+    ms = timed(lambda: bz.eval_piecewise_cubic_tiled(tiles, n_seg, dim, T_d, out=out), torch)
+    res = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms), "layout": "tiled",
+           "algorithmic_bytes": nbytes, "encode_ms": enc_ms,
+           "grid_layout": {"kernel_ms": ms_grid, "value": n_q / (ms_grid * 1e-3) / 1e9,
+                           "roofline": hbm_roof(nbytes, ms_grid)}}
     if cpu:
         import oracle
         m = 1 << 22
@@ -331,8 +335,9 @@ def suite_cubic_chain(torch, bz, bz_synth, cpu):
                                "kind": "oracle", "sample": "%d x %d random T (FP64 chain definition)" % (reps, m)}
         ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
         res["max_err_bbox"] = float(np.abs(out[:, :m].cpu().numpy().astype(np.float64) - ref).max() / ext)
-    return {"workload": "C0 piecewise cubic chain as two stacked zig-zag layers, 2^20 segments, 2^24 uniform "
-                        "random global T, 3D, FP32", "unit": "G evals/s", **res}
+    return {"workload": "C0 piecewise cubic chain as two stacked zig-zag layers (cache-line tiles; the two-layer "
+                        "grid as comparison), 2^20 segments, 2^24 uniform random global T, 3D, FP32",
+            "unit": "G evals/s", **res}
 
 
 def suite_texemu(torch, bz, bz_synth, cpu):

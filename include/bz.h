@@ -165,6 +165,24 @@ int bz_eval_piecewise_cubic(const float *grid, int64_t n_seg, int dim, const flo
                             bz_stream stream);
 
 /*
+ * Cache-line-tiled placement of the cubic chain (same texel values, same
+ * results bit for bit).  The two layers share their on-path texel, so a
+ * column is stored once as [A_k, x0_k, x1_k] (3*dim floats: the endpoint and
+ * the free texels of layers 0 and 1).  A 128-byte tile holds C = 32/(3*dim)
+ * consecutive columns (zero-padded), consecutive tiles overlapping by one
+ * column, so tile j holds segments [jS, jS+S) with S = C-1 (3D: 2) and each
+ * segment's window lies in one line.  bz_piecewise_cubic_tiled_floats: size
+ * of the tiled array in floats (0 for invalid arguments).
+ * bz_tile_piecewise_cubic: grid (as bz_encode_piecewise_cubic writes it) ->
+ * tiles (16-byte aligned).  bz_eval_piecewise_cubic_tiled: as
+ * bz_eval_piecewise_cubic on the tiles.
+ */
+int64_t bz_piecewise_cubic_tiled_floats(int64_t n_seg, int dim);
+int bz_tile_piecewise_cubic(const float *grid, int64_t n_seg, int dim, float *tiles, bz_stream stream);
+int bz_eval_piecewise_cubic_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q, float *out,
+                                  bz_stream stream);
+
+/*
  * Cache-line-tiled placement of the same zig-zag texels: 128-byte tiles of
  * C = 128/(8*dim) consecutive grid columns (16, 8, 5, 4 for dim 1..4),
  * consecutive tiles overlapping by one column, so tile j holds segments

@@ -62,6 +62,9 @@ _SIGS = {
     "bz_tensor_to_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_tensor_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_hbm_probe": (_I, [_I, _P, _P, _I64, _I, _P]),
+    "bz_piecewise_cubic_tiled_floats": (_I64, [_I64, _I]),
+    "bz_tile_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
+    "bz_eval_piecewise_cubic_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -261,6 +264,22 @@ def eval_piecewise_texemu(grid, T, frac_bits=8, rounding="nearest", out=None):
     out = _f32_out((dim, nq), grid.device, out)
     check(lib().bz_eval_piecewise_texemu(_ptr(grid), nseg, dim, _ptr(T), nq, frac_bits, TEX_ROUNDING[rounding],
                                          _ptr(out), _stream()))
+    return out
+
+
+def tile_piecewise_cubic(grid, out=None):
+    """Two-layer cubic grid[N+1, 2, 2, dim] -> cache-line tiles (flat float32)."""
+    nseg, dim = grid.shape[0] - 1, grid.shape[3]
+    n = lib().bz_piecewise_cubic_tiled_floats(nseg, dim)
+    out = _f32_out((n,), grid.device, out)
+    check(lib().bz_tile_piecewise_cubic(_ptr(grid), nseg, dim, _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_cubic_tiled(tiles, n_seg, dim, T, out=None):
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), tiles.device, out)
+    check(lib().bz_eval_piecewise_cubic_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
     return out
 
 

@@ -3,6 +3,7 @@
 FP64 oracle."""
 import numpy as np
 import pytest
+import torch
 
 import bz_synth
 import paper_2603_15447_amd as bz
@@ -84,3 +85,51 @@ def test_cubic_full_size(orc):
     ref = orc.cubic_chain_eval(chain, T)
     err = np.abs(got - ref).max() / _extent(chain)
     assert err <= TOL_F32, err
+
+
+@pytest.mark.parametrize("n_seg,dim", [(1, 3), (2, 3), (3, 3), (1000, 3), (77, 1), (300, 2), (129, 4), (10, 1)])
+def test_cubic_tiled_layout_and_eval(orc, n_seg, dim):
+    """Tiles hold [A, x0, x1] per column, tiles overlap by one column; the
+    tiled evaluator returns the two-layer grid evaluator's results bit for
+    bit, and the oracle's."""
+    chain, T = bz_synth.cubic_chain_walk(n_seg=n_seg, dim=dim, n_q=5000, seed=11 * n_seg + dim)
+    T = np.concatenate([T, [0.0, float(n_seg), -1.0, n_seg + 3.0, np.nan], np.arange(n_seg + 1.0)]).astype(np.float32)
+    grid = bz.encode_piecewise_cubic(to_dev(chain))
+    tiles = bz.tile_piecewise_cubic(grid)
+    W = 3 * dim
+    S = 32 // W - 1
+    assert tiles.numel() == -(-n_seg // S) * 32
+    tl = host(tiles).reshape(-1, 32)
+    g = host(grid)
+    for k in range(n_seg + 1):
+        r = k & 1
+        for j in ({k // S, (k - 1) // S} if k > 0 else {0}):
+            if j >= tl.shape[0] or not (j * S <= k <= j * S + S):
+                continue
+            c = k - j * S
+            col = tl[j, c * W:(c + 1) * W]
+            np.testing.assert_array_equal(col[:dim], g[k, 0, r])
+            np.testing.assert_array_equal(col[dim:2 * dim], g[k, 0, 1 - r])
+            np.testing.assert_array_equal(col[2 * dim:], g[k, 1, 1 - r])
+            np.testing.assert_array_equal(g[k, 1, r], g[k, 0, r])  # the shared texel
+    Td = to_dev(T)
+    a = host(bz.eval_piecewise_cubic_tiled(tiles, n_seg, dim, Td))
+    b = host(bz.eval_piecewise_cubic(grid, Td))
+    np.testing.assert_array_equal(a, b)
+    ok = ~np.isnan(T)
+    ref = orc.cubic_chain_eval(chain, T[ok])
+    assert np.abs(a[:, ok] - ref).max() <= TOL_F32 * _extent(chain)
+
+
+def test_cubic_tiled_full_size(orc):
+    chain, T = bz_synth.cubic_chain_walk()
+    grid = bz.encode_piecewise_cubic(to_dev(chain))
+    tiles = bz.tile_piecewise_cubic(grid)
+    Td = to_dev(T)
+    a = bz.eval_piecewise_cubic_tiled(tiles, 1 << 20, 3, Td)
+    b = bz.eval_piecewise_cubic(grid, Td)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    got = host(a)
+    ref = orc.cubic_chain_eval(chain, T)
+    assert np.abs(got - ref).max() / _extent(chain) <= TOL_F32
