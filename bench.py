@@ -176,8 +176,21 @@ def suite_plain(torch, bz, bz_synth, cpu):
     for m in ("decasteljau", "bernstein", "seiler"):
         ms = timed(lambda: bz.eval_bezier(c16, t_d, m, out=o16), torch)
         res[m + "_x16"] = {"kernel_ms": ms, "value": o16.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(n16, ms)}
-    return {"workload": "4096 cubic 3D Bezier curves x 256 shared t (1M points), FP32; *_x16: 65536 curves",
-            "unit": "G evals/s", **res}
+    # random t per curve (t[n][256] ~ U[0,1), seed 1001): 4 bytes in and 12 out per point
+    c16h, tr = bz_synth.random_curves(1 << 16, 3, 3, 256, seed=1001 + 16)
+    c16r, tr_d = torch.from_numpy(c16h).cuda(), torch.from_numpy(tr).cuda()
+    nr = o16.numel() * 4 + c16r.numel() * 4 + tr.nbytes
+    for m in ("decasteljau", "bernstein", "seiler"):
+        ms = timed(lambda: bz.eval_bezier(c16r, tr_d, m, out=o16), torch)
+        e = {"kernel_ms": ms, "value": o16.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nr, ms)}
+        if cpu and m == "decasteljau":
+            import oracle
+            k = 1024
+            ref = oracle.bezier_decasteljau(c16h[:k], tr[:k], per_object=True)
+            e["max_err_bbox"] = max_err_bbox(o16[:, :k * 256].cpu().numpy(), ref, extents(c16h[:k]), 256)
+        res[m + "_x16_random_t"] = e
+    return {"workload": "4096 cubic 3D Bezier curves x 256 shared t (1M points), FP32; *_x16: 65536 curves; "
+                        "*_x16_random_t: 65536 curves x 256 random t each", "unit": "G evals/s", **res}
 
 
 def batch_bytes(b, es, n_segs, dim):
@@ -569,6 +582,11 @@ def main():
     probe = hbm_probe(torch, bz)
     probe["headline_frac_of_read"] = roof["achieved"] / probe["read_GB/s"]
     rec["hbm_probe"] = probe
+    if roof["traffic"]:
+        # the bytes the gather actually moves (one 128-byte line per query)
+        rate = roof["traffic"] / (kern_ms * 1e-3) / 1e9
+        rec["actual_traffic"] = {"GB/s": rate, "frac_of_peak": rate / HBM_PEAK_GBS,
+                                 "frac_of_read_probe": rate / probe["read_GB/s"]}
     if not args.no_cpu:
         log("headline: CPU baseline")
         rec["cpu_baseline"], rec["max_err_bbox"] = cpu_baseline_chain(chain, T, out)
