@@ -7,9 +7,12 @@
 // (Sec. 2.2: B-splines become piecewise Bezier curves via Boehm's algorithm)
 // with the breakpoints kept for a per-query span search; tiles are ordered by
 // estimated cost, heaviest first.
-// Evaluation: a grid of (CUs x occupancy) workgroups pulls tiles from an atomic
-// counter; the last workgroup to finish resets the counters, so consecutive
-// launches (and graph replays) need no memset.
+// Evaluation (batched_impl.h): a grid of (CUs x occupancy) workgroups takes
+// tiles round-robin or from an atomic counter; the last workgroup to finish
+// resets the counters, so consecutive launches (and graph replays) need no
+// memset.  (The 16 lanes that evaluate one object load the same addresses,
+// which the memory pipeline merges into one access; sharing the coefficients
+// by DPP row broadcasts instead was measured slower.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,268 +22,12 @@
 #include <numeric>
 #include <vector>
 
-#include "curves_impl.h"
+#include "batched_impl.h"
 
 struct bz_plan_s;
 
 namespace bzi {
 namespace {
-
-constexpr int kNurbsP = 3;
-
-struct ClassInfo {
-    int32_t kind;       // 0 Bezier, 1 rational, 2 NURBS
-    int32_t degree;     // 1..15 (3 for NURBS)
-    int32_t first;      // first slot of the class in perm
-    int32_t count;      // objects in the class
-    int64_t ctrl_base;  // first element of the class in the sorted control points
-    int64_t w_base;     // first element of the class in the sorted weights (rational)
-};
-
-// A tile carries its class record, so a workgroup needs one scalar load per tile.
-struct Tile {
-    ClassInfo ci;
-    uint32_t q0;  // first query of the tile within its class
-    uint32_t pad;
-};
-
-struct BatchArgs {
-    const void *ctrl_s;        // control points in class-sorted order (plan copy)
-    const void *w_s;           // weights of rational objects, class-sorted (plan copy)
-    const int32_t *perm;       // sorted slot -> object
-    const Tile *tiles;
-    uint32_t n_tiles;
-    uint32_t qpt;              // sub-tiles of kBlock queries per tile
-    const int32_t *seg_first;  // [n_nurbs+1], NURBS ranked in sorted order
-    const float *brk;          // breakpoints, nseg+1 per NURBS, at seg_first[r] + r
-    const float *seg;          // [n_segs][4][dim+1] homogeneous
-    const float *t;
-    float *out;
-    int64_t plane;
-    uint32_t n_t;
-    FastDiv div_nt;
-    int dim;
-    unsigned int *counters;    // [0] next tile, [1] finished workgroups
-    int dynamic;               // 1: atomic tile counter, 0: static round robin
-};
-
-// Load n contiguous storage elements as FP32.
-template <typename T, int N>
-__device__ __forceinline__ void load_row(const T *__restrict__ p, float (&v)[N]) {
-    if constexpr (std::is_same<T, float>::value) {
-        typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
-        constexpr int V = N / 4;
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            const f4u x = *reinterpret_cast<const f4u *>(p + 4 * i);
-            v[4 * i] = x[0];
-            v[4 * i + 1] = x[1];
-            v[4 * i + 2] = x[2];
-            v[4 * i + 3] = x[3];
-        }
-#pragma unroll
-        for (int i = 4 * V; i < N; ++i) v[i] = p[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = to_f32<T>(p[i]);
-    }
-}
-
-// One query of a degree-D (rational) Bezier object; P is [dim][D+1].
-template <int D, bool RAT, int F, typename T>
-__device__ __forceinline__ void eval_curve_query(const T *__restrict__ P, const T *__restrict__ W, int dim, float t,
-                                                 float *__restrict__ out, int64_t plane, int64_t q) {
-    float wv[D + 1];
-    if constexpr (RAT) load_row<T, D + 1>(W, wv);
-    if constexpr (F == FORM_BERN) {
-        float B[D + 1];
-        bernstein_basis<D>(t, B);
-        float den = 1.0f;
-        if constexpr (RAT) {
-#pragma unroll
-            for (int i = 0; i <= D; ++i) B[i] *= wv[i];
-            den = B[0];
-#pragma unroll
-            for (int i = 1; i <= D; ++i) den += B[i];
-        }
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) {
-            if (k < dim) {
-                float b[D + 1];
-                load_row<T, D + 1>(P + k * (D + 1), b);
-                const float v = dot_basis<D>(B, b);
-                st_stream(out + k * plane + q, RAT ? v / den : v);
-            }
-        }
-    } else {
-        float den = 1.0f;
-        if constexpr (RAT) den = eval_dc<D>(wv, t);
-#pragma unroll
-        for (int k = 0; k < kMaxDim; ++k) {
-            if (k < dim) {
-                float b[D + 1];
-                load_row<T, D + 1>(P + k * (D + 1), b);
-                if constexpr (RAT) {
-#pragma unroll
-                    for (int i = 0; i <= D; ++i) b[i] *= wv[i];
-                }
-                const float v = eval_dc<D>(b, t);
-                st_stream(out + k * plane + q, RAT ? v / den : v);
-            }
-        }
-    }
-}
-
-// One query of a NURBS object: clamp, binary search of the span among the
-// segment breakpoints, rational cubic Bezier of that segment.
-__device__ __forceinline__ void eval_nurbs_query(const float *__restrict__ brk, const float *__restrict__ seg, int nseg,
-                                                 int dim, float u, float *__restrict__ out, int64_t plane, int64_t q) {
-    const float lo_u = brk[0], hi_u = brk[nseg];
-    u = u < lo_u ? lo_u : u;  // NaN passes
-    u = u > hi_u ? hi_u : u;
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (brk[mid] <= u) lo = mid;
-        else hi = mid - 1;
-    }
-    const float a = brk[lo], b = brk[lo + 1];
-    const float tl = (u - a) / (b - a);
-    float B[4];
-    bernstein_basis<3>(tl, B);
-    const float *__restrict__ S = seg + static_cast<size_t>(lo) * 4 * (dim + 1);
-    float H[kMaxDim + 1] = {};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k <= kMaxDim; ++k)
-            if (k <= dim) H[k] = __builtin_fmaf(B[i], S[i * (dim + 1) + k], H[k]);
-#pragma unroll
-    for (int k = 0; k < kMaxDim; ++k)
-        if (k < dim) st_stream(out + k * plane + q, H[k] / H[dim]);
-}
-
-constexpr int kMaxQpt = 4;
-
-// Index, permutation and parameter loads of every sub-tile are issued before
-// any evaluation, so their latencies overlap instead of adding up.  Tail lanes
-// re-read the last query of the tile and store nothing.
-struct SubTileQueries {
-    uint32_t slot[kMaxQpt], j[kMaxQpt];
-    int64_t q[kMaxQpt];
-    float t[kMaxQpt];
-    bool ok[kMaxQpt];
-};
-
-__device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile &tl, SubTileQueries &sq) {
-    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
-        sq.ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
-        const uint32_t qc = min(qi, nq - 1);
-        sq.slot[s] = fdiv(qc, a.div_nt);
-        sq.j[s] = qc - sq.slot[s] * a.n_t;
-    }
-    int64_t o[kMaxQpt];
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) o[s] = a.perm[tl.ci.first + sq.slot[s]];
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        sq.q[s] = o[s] * a.n_t + sq.j[s];
-        sq.t[s] = a.t[sq.q[s]];
-    }
-}
-
-template <int D, bool RAT, int F, typename T>
-__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &tl) {
-    SubTileQueries sq;
-    prefetch_queries(a, tl, sq);
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        if (!sq.ok[s]) continue;
-        // the control points' address needs no index load: classes are contiguous
-        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(sq.slot[s]) * (D + 1) * a.dim;
-        const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1)
-                         : nullptr;
-        eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], a.out, a.plane, sq.q[s]);
-    }
-}
-
-__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl) {
-    SubTileQueries sq;
-    prefetch_queries(a, tl, sq);
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        if (!sq.ok[s]) continue;
-        const uint32_t r = sq.slot[s];  // NURBS rank = slot in the class
-        const int s0 = a.seg_first[r], nseg = a.seg_first[r + 1] - s0;
-        eval_nurbs_query(a.brk + s0 + r, a.seg + static_cast<size_t>(s0) * 4 * (a.dim + 1), nseg, a.dim, sq.t[s],
-                         a.out, a.plane, sq.q[s]);
-    }
-}
-
-template <bool RAT, int F, typename T>
-__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &tl) {
-    switch (tl.ci.degree) {
-        case 1: run_curve_tile<1, RAT, F, T>(a, tl); break;
-        case 2: run_curve_tile<2, RAT, F, T>(a, tl); break;
-        case 3: run_curve_tile<3, RAT, F, T>(a, tl); break;
-        case 4: run_curve_tile<4, RAT, F, T>(a, tl); break;
-        case 5: run_curve_tile<5, RAT, F, T>(a, tl); break;
-        case 6: run_curve_tile<6, RAT, F, T>(a, tl); break;
-        case 7: run_curve_tile<7, RAT, F, T>(a, tl); break;
-        case 8: run_curve_tile<8, RAT, F, T>(a, tl); break;
-        case 9: run_curve_tile<9, RAT, F, T>(a, tl); break;
-        case 10: run_curve_tile<10, RAT, F, T>(a, tl); break;
-        case 11: run_curve_tile<11, RAT, F, T>(a, tl); break;
-        case 12: run_curve_tile<12, RAT, F, T>(a, tl); break;
-        case 13: run_curve_tile<13, RAT, F, T>(a, tl); break;
-        case 14: run_curve_tile<14, RAT, F, T>(a, tl); break;
-        default: run_curve_tile<15, RAT, F, T>(a, tl); break;
-    }
-}
-
-template <int F, typename T>
-__device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) {
-    const Tile tl = a.tiles[tile];
-    if (tl.ci.kind == 0) dispatch_degree<false, F, T>(a, tl);
-    else if (tl.ci.kind == 1) dispatch_degree<true, F, T>(a, tl);
-    else run_nurbs_tile(a, tl);
-}
-
-// Dynamic schedule: workgroups pull tiles from an atomic counter (the next
-// index is fetched while the current tile is evaluated).  Static schedule:
-// workgroup g takes tiles g, g+G, g+2G, ... -- balanced because tiles are
-// ordered by cost and every tile of a class costs the same.
-template <int F, typename T>
-__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
-    if (!a.dynamic) {
-        for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T>(a, tile);
-        return;
-    }
-    __shared__ unsigned int s_tile;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
-    __syncthreads();
-    unsigned int tile = s_tile;
-    __syncthreads();
-    while (tile < a.n_tiles) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
-        run_tile<F, T>(a, tile);
-        __syncthreads();
-        tile = s_tile;
-        __syncthreads();
-    }
-    // every workgroup has seen the end of the tile list; the last one to get
-    // here resets both counters for the next launch
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
-            atomicExch(&a.counters[0], 0u);
-            atomicExch(&a.counters[1], 0u);
-        }
-    }
-}
 
 // Plan-time gather of control points (and weights of rational objects) into
 // class-sorted, contiguous order: sorted object i of class c lands at
@@ -396,7 +143,7 @@ struct bz_plan_s {
     float *brk = nullptr, *seg = nullptr;
     unsigned int *counters = nullptr;
     std::vector<ClassInfo> classes;
-    uint32_t n_tiles = 0, qpt = 1;
+    uint32_t n_tiles = 0, qpt = 1, vq = 1;
     int64_t n_segs = 0;
     uint32_t workgroups = 0;
     int dynamic = 1;
@@ -423,8 +170,9 @@ int dev_upload(X **dst, const std::vector<X> &src, hipStream_t s) {
 }
 
 int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups, uint32_t qpt,
-                 int dynamic) {
+                 int dynamic, uint32_t vq) {
     BatchArgs a;
+    a.vq = static_cast<int>(vq);
     a.dynamic = dynamic;
     a.ctrl_s = p->ctrl_s;
     a.w_s = p->w_s;
@@ -442,24 +190,20 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
     a.div_nt = make_fastdiv(a.n_t);
     a.dim = p->dim;
     a.counters = p->counters;
-    const dim3 g(workgroups), b(kBlock);
     const bool dc = p->method == BZ_DECASTELJAU;
-    if (p->dtype == BZ_F32) {
-        if (dc) hipLaunchKernelGGL((k_batch_persistent<FORM_DC, float>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_batch_persistent<FORM_BERN, float>), g, b, 0, s, a);
-    } else if (p->dtype == BZ_F16) {
-        if (dc) hipLaunchKernelGGL((k_batch_persistent<FORM_DC, _Float16>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_batch_persistent<FORM_BERN, _Float16>), g, b, 0, s, a);
-    } else {
-        if (dc) hipLaunchKernelGGL((k_batch_persistent<FORM_DC, bf16_t>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_batch_persistent<FORM_BERN, bf16_t>), g, b, 0, s, a);
-    }
-    BZ_CHECK_LAUNCH("k_batch_persistent");
-    return BZ_OK;
+    if (p->dtype == BZ_F32)
+        return dc ? launch_batch_kernel<FORM_DC, float>(workgroups, a, s)
+                  : launch_batch_kernel<FORM_BERN, float>(workgroups, a, s);
+    if (p->dtype == BZ_F16)
+        return dc ? launch_batch_kernel<FORM_DC, _Float16>(workgroups, a, s)
+                  : launch_batch_kernel<FORM_BERN, _Float16>(workgroups, a, s);
+    return dc ? launch_batch_kernel<FORM_DC, bf16_t>(workgroups, a, s)
+              : launch_batch_kernel<FORM_BERN, bf16_t>(workgroups, a, s);
 }
 
-// Rebuild the tile list for `qpt` sub-tiles per tile (heaviest class first).
-int build_tiles(bz_plan_s *p, uint32_t qpt, hipStream_t s) {
+// Rebuild the tile list for `qpt` sub-tiles of 256 lanes x `vq` queries per
+// tile (heaviest class first; NURBS tiles one query per lane).
+int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, hipStream_t s) {
     const std::vector<ClassInfo> &cls = p->classes;
     std::vector<int> order(cls.size());
     std::iota(order.begin(), order.end(), 0);
@@ -468,8 +212,9 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, hipStream_t s) {
                class_cost(cls[y].kind, cls[y].degree, p->method, p->dim);
     });
     std::vector<Tile> tiles;
-    const uint64_t span = static_cast<uint64_t>(kBlock) * qpt;
     for (int c : order) {
+        // NURBS tiles always map one query per lane
+        const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 2 ? 1 : vq);
         const uint64_t nq = static_cast<uint64_t>(cls[c].count) * p->n_t;
         for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), 0});
     }
@@ -480,6 +225,7 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, hipStream_t s) {
     if (rc) return rc;
     p->n_tiles = static_cast<uint32_t>(tiles.size());
     p->qpt = qpt;
+    p->vq = vq;
     return BZ_OK;
 }
 
@@ -614,7 +360,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         int rc = dev_upload(&p->perm, perm, s);
         if (!rc) rc = dev_upload(&p->seg_first, seg_first, s);
         if (!rc) rc = dev_upload(&p->brk, brk, s);
-        if (!rc) rc = build_tiles(p, 1, s);
+        if (!rc) rc = build_tiles(p, 1, 1, s);
         if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);
         if (!rc) rc = dmalloc(&p->w_s, w_elems * es);
         if (!rc) rc = dmalloc(reinterpret_cast<void **>(&p->seg), std::max<int64_t>(p->n_segs, 1) * 4 * (dim + 1) * sizeof(float));
@@ -674,9 +420,8 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             int blocks_per_cu = 0, dev = 0, cus = 0;
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            if (e == hipSuccess)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, k_batch_persistent<FORM_BERN, float>, kBlock, 0);
-            if (e != hipSuccess) rc = hip_fail(e, "occupancy query");
+            if (e != hipSuccess) rc = hip_fail(e, "device query");
+            else rc = batch_kernel_blocks_per_cu(&blocks_per_cu);
             p->workgroups = static_cast<uint32_t>(std::max(1, cus) * std::max(1, blocks_per_cu));
         }
         if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? BZ_OK : fail(BZ_ERR_HIP, "%s: sync", fn);
@@ -695,63 +440,93 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream) {
         if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
         if (!t || !out) return fail(BZ_ERR_NULL, "bz_batch_eval: t and out are required");
         if (!aligned(t, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "bz_batch_eval: misaligned");
-        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->qpt, plan->dynamic);
+        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->qpt, plan->dynamic, plan->vq);
     });
 }
 
-int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best4) {
+int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best5) {
     return guarded("bz_batch_plan_autotune", [&]() -> int {
         if (!plan) return fail(BZ_ERR_NULL, "bz_batch_plan_autotune: plan is required");
         if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
         if (!t || !out) return fail(BZ_ERR_NULL, "bz_batch_plan_autotune: t and out are required");
+        if (!aligned(t, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "bz_batch_plan_autotune: misaligned");
         const hipStream_t s = as_stream(stream);
         hipEvent_t e0, e1;
         BZ_CHECK_HIP(hipEventCreate(&e0));
         BZ_CHECK_HIP(hipEventCreate(&e1));
         const uint32_t base = plan->workgroups;
         float best = 1e30f;
-        uint32_t best_wg = base, best_q = plan->qpt;
+        uint32_t best_wg = base, best_q = plan->qpt, best_vq = plan->vq;
         int best_dyn = plan->dynamic;
         const uint32_t qpts[] = {1, 2, 4};
+        const uint32_t vqs[] = {1, 4};
         const double wgf[] = {0.5, 1.0, 2.0};
-        for (uint32_t q : qpts) {
-            int rc = build_tiles(plan, q, s);
-            if (rc) return rc;
-            for (int dyn = 1; dyn >= 0; --dyn)
-                for (double f : wgf) {
-                    const uint32_t wg = std::max<uint32_t>(1, static_cast<uint32_t>(base * f));
-                    rc = launch_batch(plan, t, out, s, wg, q, dyn);  // warm-up
-                    if (rc) return rc;
-                    BZ_CHECK_HIP(hipEventRecord(e0, s));
-                    for (int r = 0; r < 5; ++r) {
-                        rc = launch_batch(plan, t, out, s, wg, q, dyn);
-                        if (rc) return rc;
+        int rc = BZ_OK;
+        for (uint32_t vq : vqs) {
+            if (vq == 4 && plan->n_t % 4 != 0) continue;  // four queries of one object per lane
+            for (uint32_t q : qpts) {
+                rc = build_tiles(plan, q, vq, s);
+                if (rc) break;
+                for (int dyn = 1; dyn >= 0 && !rc; --dyn)
+                    for (double f : wgf) {
+                        const uint32_t wg = std::max<uint32_t>(1, static_cast<uint32_t>(base * f));
+                        rc = launch_batch(plan, t, out, s, wg, q, dyn, vq);  // warm-up
+                        if (rc) break;
+                        BZ_CHECK_HIP(hipEventRecord(e0, s));
+                        for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, q, dyn, vq);
+                        if (rc) break;
+                        BZ_CHECK_HIP(hipEventRecord(e1, s));
+                        BZ_CHECK_HIP(hipEventSynchronize(e1));
+                        float ms = 0;
+                        BZ_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (ms < best) {
+                            best = ms;
+                            best_wg = wg;
+                            best_q = q;
+                            best_dyn = dyn;
+                            best_vq = vq;
+                        }
                     }
-                    BZ_CHECK_HIP(hipEventRecord(e1, s));
-                    BZ_CHECK_HIP(hipEventSynchronize(e1));
-                    float ms = 0;
-                    BZ_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best) {
-                        best = ms;
-                        best_wg = wg;
-                        best_q = q;
-                        best_dyn = dyn;
-                    }
-                }
+                if (rc) break;
+            }
+            if (rc) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        int rc = build_tiles(plan, best_q, s);
+        if (rc) return rc;
+        rc = build_tiles(plan, best_q, best_vq, s);
         if (rc) return rc;
         plan->workgroups = best_wg;
         plan->dynamic = best_dyn;
         BZ_CHECK_HIP(hipStreamSynchronize(s));
-        if (best4) {
-            best4[0] = best_wg;
-            best4[1] = best_q;
-            best4[2] = static_cast<int64_t>(best * 1000.0f / 5.0f);  // microseconds per launch
-            best4[3] = best_dyn;
+        if (best5) {
+            best5[0] = best_wg;
+            best5[1] = best_q;
+            best5[2] = static_cast<int64_t>(best * 1000.0f / 5.0f);  // microseconds per launch
+            best5[3] = best_dyn;
+            best5[4] = best_vq;
         }
+        return BZ_OK;
+    });
+}
+
+int bz_batch_plan_configure(bz_plan plan, int64_t workgroups, int sub_tiles, int schedule, int queries_per_lane,
+                            bz_stream stream) {
+    return guarded("bz_batch_plan_configure", [&]() -> int {
+        const char *fn = "bz_batch_plan_configure";
+        if (!plan) return fail(BZ_ERR_NULL, "%s: plan is required", fn);
+        if (workgroups < 1 || workgroups > (int64_t(1) << 20)) return fail(BZ_ERR_SHAPE, "%s: workgroups", fn);
+        if (sub_tiles != 1 && sub_tiles != 2 && sub_tiles != 4) return fail(BZ_ERR_SHAPE, "%s: sub_tiles", fn);
+        if (schedule != 0 && schedule != 1) return fail(BZ_ERR_SHAPE, "%s: schedule", fn);
+        if (queries_per_lane != 1 && queries_per_lane != 4) return fail(BZ_ERR_SHAPE, "%s: queries_per_lane", fn);
+        if (queries_per_lane == 4 && plan->n_t % 4 != 0)
+            return fail(BZ_ERR_UNSUPPORTED, "%s: 4 queries per lane need n_t a multiple of 4", fn);
+        const hipStream_t s = as_stream(stream);
+        const int rc = build_tiles(plan, static_cast<uint32_t>(sub_tiles), static_cast<uint32_t>(queries_per_lane), s);
+        if (rc) return rc;
+        plan->workgroups = static_cast<uint32_t>(workgroups);
+        plan->dynamic = schedule;
+        BZ_CHECK_HIP(hipStreamSynchronize(s));
         return BZ_OK;
     });
 }

@@ -1,0 +1,402 @@
+// Device code of the mixed-batch evaluator (see batched.hip for the plan):
+// the persistent kernel and its per-class tile evaluators.  Included by the
+// translation units that instantiate the kernel per storage type, so the six
+// (form x storage) instantiations compile in parallel.
+#pragma once
+#include "curves_impl.h"
+
+namespace bzi {
+
+constexpr int kNurbsP = 3;
+
+struct ClassInfo {
+    int32_t kind;       // 0 Bezier, 1 rational, 2 NURBS
+    int32_t degree;     // 1..15 (3 for NURBS)
+    int32_t first;      // first slot of the class in perm
+    int32_t count;      // objects in the class
+    int64_t ctrl_base;  // first element of the class in the sorted control points
+    int64_t w_base;     // first element of the class in the sorted weights (rational)
+};
+
+// A tile carries its class record, so a workgroup needs one scalar load per tile.
+struct Tile {
+    ClassInfo ci;
+    uint32_t q0;  // first query of the tile within its class
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const void *ctrl_s;        // control points in class-sorted order (plan copy)
+    const void *w_s;           // weights of rational objects, class-sorted (plan copy)
+    const int32_t *perm;       // sorted slot -> object
+    const Tile *tiles;
+    uint32_t n_tiles;
+    uint32_t qpt;              // sub-tiles of kBlock queries per tile
+    const int32_t *seg_first;  // [n_nurbs+1], NURBS ranked in sorted order
+    const float *brk;          // breakpoints, nseg+1 per NURBS, at seg_first[r] + r
+    const float *seg;          // [n_segs][4][dim+1] homogeneous
+    const float *t;
+    float *out;
+    int64_t plane;
+    uint32_t n_t;
+    FastDiv div_nt;
+    int dim;
+    unsigned int *counters;    // [0] next tile, [1] finished workgroups
+    int dynamic;               // 1: atomic tile counter, 0: static round robin
+    int vq;                    // queries per lane: 1, or 4 consecutive parameters of one object
+};
+
+namespace batch_dev {
+
+// Load n contiguous storage elements as FP32.
+template <typename T, int N>
+__device__ __forceinline__ void load_row(const T *__restrict__ p, float (&v)[N]) {
+    if constexpr (std::is_same<T, float>::value) {
+        typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+        constexpr int V = N / 4;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            const f4u x = *reinterpret_cast<const f4u *>(p + 4 * i);
+            v[4 * i] = x[0];
+            v[4 * i + 1] = x[1];
+            v[4 * i + 2] = x[2];
+            v[4 * i + 3] = x[3];
+        }
+#pragma unroll
+        for (int i = 4 * V; i < N; ++i) v[i] = p[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = to_f32<T>(p[i]);
+    }
+}
+
+// One query of a degree-D (rational) Bezier object; P is [dim][D+1].
+template <int D, bool RAT, int F, typename T>
+__device__ __forceinline__ void eval_curve_query(const T *__restrict__ P, const T *__restrict__ W, int dim, float t,
+                                                 float *__restrict__ out, int64_t plane, int64_t q) {
+    float wv[D + 1];
+    if constexpr (RAT) load_row<T, D + 1>(W, wv);
+    if constexpr (F == FORM_BERN) {
+        float B[D + 1];
+        bernstein_basis<D>(t, B);
+        float den = 1.0f;
+        if constexpr (RAT) {
+#pragma unroll
+            for (int i = 0; i <= D; ++i) B[i] *= wv[i];
+            den = B[0];
+#pragma unroll
+            for (int i = 1; i <= D; ++i) den += B[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k < dim) {
+                float b[D + 1];
+                load_row<T, D + 1>(P + k * (D + 1), b);
+                const float v = dot_basis<D>(B, b);
+                st_stream(out + k * plane + q, RAT ? v / den : v);
+            }
+        }
+    } else {
+        float den = 1.0f;
+        if constexpr (RAT) den = eval_dc<D>(wv, t);
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k < dim) {
+                float b[D + 1];
+                load_row<T, D + 1>(P + k * (D + 1), b);
+                if constexpr (RAT) {
+#pragma unroll
+                    for (int i = 0; i <= D; ++i) b[i] *= wv[i];
+                }
+                const float v = eval_dc<D>(b, t);
+                st_stream(out + k * plane + q, RAT ? v / den : v);
+            }
+        }
+    }
+}
+
+// Four consecutive queries (one object, parameters t[0..3]) per lane: the
+// object's coefficients are loaded once for four evaluations, the parameters
+// come in one 16-byte load and each coordinate leaves in one 16-byte store.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int D, bool RAT, int F, typename T>
+__device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const T *__restrict__ W, int dim,
+                                                  const float (&t)[4], float *__restrict__ out, int64_t plane,
+                                                  int64_t q) {
+    float wv[D + 1];
+    if constexpr (RAT) load_row<T, D + 1>(W, wv);
+    if constexpr (F == FORM_BERN) {
+        float B[4][D + 1], den[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bernstein_basis<D>(t[i], B[i]);
+            den[i] = 1.0f;
+            if constexpr (RAT) {
+#pragma unroll
+                for (int e = 0; e <= D; ++e) B[i][e] *= wv[e];
+                den[i] = B[i][0];
+#pragma unroll
+                for (int e = 1; e <= D; ++e) den[i] += B[i][e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k < dim) {
+                float b[D + 1];
+                load_row<T, D + 1>(P + k * (D + 1), b);
+                f4u v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float x = dot_basis<D>(B[i], b);
+                    v[i] = RAT ? x / den[i] : x;
+                }
+                __builtin_nontemporal_store(v, reinterpret_cast<f4u *>(out + k * plane + q));
+            }
+        }
+    } else {
+        float den[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        if constexpr (RAT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) den[i] = eval_dc<D>(wv, t[i]);
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k < dim) {
+                float b[D + 1];
+                load_row<T, D + 1>(P + k * (D + 1), b);
+                if constexpr (RAT) {
+#pragma unroll
+                    for (int e = 0; e <= D; ++e) b[e] *= wv[e];
+                }
+                f4u v;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float x = eval_dc<D>(b, t[i]);
+                    v[i] = RAT ? x / den[i] : x;
+                }
+                __builtin_nontemporal_store(v, reinterpret_cast<f4u *>(out + k * plane + q));
+            }
+        }
+    }
+}
+
+// One query of a NURBS object: clamp, binary search of the span among the
+// segment breakpoints, rational cubic Bezier of that segment.
+__device__ __forceinline__ void eval_nurbs_query(const float *__restrict__ brk, const float *__restrict__ seg, int nseg,
+                                                 int dim, float u, float *__restrict__ out, int64_t plane, int64_t q) {
+    const float lo_u = brk[0], hi_u = brk[nseg];
+    u = u < lo_u ? lo_u : u;  // NaN passes
+    u = u > hi_u ? hi_u : u;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (brk[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    const float a = brk[lo], b = brk[lo + 1];
+    const float tl = (u - a) / (b - a);
+    float B[4];
+    bernstein_basis<3>(tl, B);
+    const float *__restrict__ S = seg + static_cast<size_t>(lo) * 4 * (dim + 1);
+    float H[kMaxDim + 1] = {};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k <= kMaxDim; ++k)
+            if (k <= dim) H[k] = __builtin_fmaf(B[i], S[i * (dim + 1) + k], H[k]);
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+        if (k < dim) st_stream(out + k * plane + q, H[k] / H[dim]);
+}
+
+constexpr int kMaxQpt = 4;
+
+// Index, permutation and parameter loads of every sub-tile are issued before
+// any evaluation, so their latencies overlap instead of adding up.  Tail lanes
+// re-read the last query of the tile and store nothing.
+struct SubTileQueries {
+    uint32_t slot[kMaxQpt], j[kMaxQpt];
+    int64_t q[kMaxQpt];
+    float t[kMaxQpt];
+    bool ok[kMaxQpt];
+};
+
+__device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile &tl, SubTileQueries &sq) {
+    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
+        sq.ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
+        const uint32_t qc = min(qi, nq - 1);
+        sq.slot[s] = fdiv(qc, a.div_nt);
+        sq.j[s] = qc - sq.slot[s] * a.n_t;
+    }
+    int64_t o[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) o[s] = a.perm[tl.ci.first + sq.slot[s]];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        sq.q[s] = o[s] * a.n_t + sq.j[s];
+        sq.t[s] = a.t[sq.q[s]];
+    }
+}
+
+template <int D, bool RAT, int F, typename T>
+__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &tl) {
+    SubTileQueries sq;
+    prefetch_queries(a, tl, sq);
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!sq.ok[s]) continue;
+        // the control points' address needs no index load: classes are contiguous
+        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(sq.slot[s]) * (D + 1) * a.dim;
+        const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1)
+                         : nullptr;
+        eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], a.out, a.plane, sq.q[s]);
+    }
+}
+
+// Lane l of sub-tile s takes the four queries starting at q0 + 4(s*256 + l);
+// n_t is a multiple of 4, so they belong to one object.
+template <int D, bool RAT, int F, typename T>
+__device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &tl) {
+    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
+    uint32_t slot[kMaxQpt];
+    int64_t q[kMaxQpt];
+    bool ok[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const uint32_t qi = tl.q0 + 4 * (s * kBlock + threadIdx.x);
+        ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
+        const uint32_t qc = min(qi, nq - 4);
+        slot[s] = fdiv(qc, a.div_nt);
+        q[s] = qc - slot[s] * a.n_t;  // j for now
+    }
+    int64_t o[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) o[s] = a.perm[tl.ci.first + slot[s]];
+    float tv[kMaxQpt][4];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        q[s] += o[s] * a.n_t;
+        const f4u x = *reinterpret_cast<const f4u *>(a.t + q[s]);
+        tv[s][0] = x[0], tv[s][1] = x[1], tv[s][2] = x[2], tv[s][3] = x[3];
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!ok[s]) continue;
+        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(slot[s]) * (D + 1) * a.dim;
+        const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(slot[s]) * (D + 1)
+                         : nullptr;
+        eval_curve_query4<D, RAT, F, T>(P, W, a.dim, tv[s], a.out, a.plane, q[s]);
+    }
+}
+
+__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl) {
+    SubTileQueries sq;
+    prefetch_queries(a, tl, sq);
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!sq.ok[s]) continue;
+        const uint32_t r = sq.slot[s];  // NURBS rank = slot in the class
+        const int s0 = a.seg_first[r], nseg = a.seg_first[r + 1] - s0;
+        eval_nurbs_query(a.brk + s0 + r, a.seg + static_cast<size_t>(s0) * 4 * (a.dim + 1), nseg, a.dim, sq.t[s],
+                         a.out, a.plane, sq.q[s]);
+    }
+}
+
+template <int D, bool RAT, int F, typename T, int VQ>
+__device__ __forceinline__ void run_curve_tile_vq(const BatchArgs &a, const Tile &tl) {
+    if constexpr (VQ == 4) run_curve_tile4<D, RAT, F, T>(a, tl);
+    else run_curve_tile<D, RAT, F, T>(a, tl);
+}
+
+template <bool RAT, int F, typename T, int VQ>
+__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &tl) {
+    switch (tl.ci.degree) {
+        case 1: run_curve_tile_vq<1, RAT, F, T, VQ>(a, tl); break;
+        case 2: run_curve_tile_vq<2, RAT, F, T, VQ>(a, tl); break;
+        case 3: run_curve_tile_vq<3, RAT, F, T, VQ>(a, tl); break;
+        case 4: run_curve_tile_vq<4, RAT, F, T, VQ>(a, tl); break;
+        case 5: run_curve_tile_vq<5, RAT, F, T, VQ>(a, tl); break;
+        case 6: run_curve_tile_vq<6, RAT, F, T, VQ>(a, tl); break;
+        case 7: run_curve_tile_vq<7, RAT, F, T, VQ>(a, tl); break;
+        case 8: run_curve_tile_vq<8, RAT, F, T, VQ>(a, tl); break;
+        case 9: run_curve_tile_vq<9, RAT, F, T, VQ>(a, tl); break;
+        case 10: run_curve_tile_vq<10, RAT, F, T, VQ>(a, tl); break;
+        case 11: run_curve_tile_vq<11, RAT, F, T, VQ>(a, tl); break;
+        case 12: run_curve_tile_vq<12, RAT, F, T, VQ>(a, tl); break;
+        case 13: run_curve_tile_vq<13, RAT, F, T, VQ>(a, tl); break;
+        case 14: run_curve_tile_vq<14, RAT, F, T, VQ>(a, tl); break;
+        default: run_curve_tile_vq<15, RAT, F, T, VQ>(a, tl); break;
+    }
+}
+
+template <int F, typename T, int VQ>
+__device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) {
+    const Tile tl = a.tiles[tile];
+    if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl);
+    else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl);
+    else run_nurbs_tile(a, tl);
+}
+
+// Dynamic schedule: workgroups pull tiles from an atomic counter (the next
+// index is fetched while the current tile is evaluated).  Static schedule:
+// workgroup g takes tiles g, g+G, g+2G, ... -- balanced because tiles are
+// ordered by cost and every tile of a class costs the same.
+template <int F, typename T, int VQ>
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
+    if (!a.dynamic) {
+        for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T, VQ>(a, tile);
+        return;
+    }
+    __shared__ unsigned int s_tile;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
+    __syncthreads();
+    unsigned int tile = s_tile;
+    __syncthreads();
+    while (tile < a.n_tiles) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
+        run_tile<F, T, VQ>(a, tile);
+        __syncthreads();
+        tile = s_tile;
+        __syncthreads();
+    }
+    // every workgroup has seen the end of the tile list; the last one to get
+    // here resets both counters for the next launch
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
+            atomicExch(&a.counters[0], 0u);
+            atomicExch(&a.counters[1], 0u);
+        }
+    }
+}
+
+}  // namespace batch_dev
+
+// Launch of the persistent kernel (instantiated in batched_f32/f16/bf16.hip).
+template <int F, typename T>
+int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) {
+    if (a.vq == 4)
+        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 4>), dim3(workgroups), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 1>), dim3(workgroups), dim3(kBlock), 0, s, a);
+    BZ_CHECK_LAUNCH("k_batch_persistent");
+    return BZ_OK;
+}
+
+// Resident workgroups per CU of the kernel (FP32 Bernstein instantiation).
+int batch_kernel_blocks_per_cu(int *blocks);
+
+#define BZI_BATCH_EXTERN(F, T) extern template int launch_batch_kernel<F, T>(uint32_t, const BatchArgs &, hipStream_t);
+BZI_BATCH_EXTERN(FORM_DC, float)
+BZI_BATCH_EXTERN(FORM_BERN, float)
+BZI_BATCH_EXTERN(FORM_DC, _Float16)
+BZI_BATCH_EXTERN(FORM_BERN, _Float16)
+BZI_BATCH_EXTERN(FORM_DC, bf16_t)
+BZI_BATCH_EXTERN(FORM_BERN, bf16_t)
+#undef BZI_BATCH_EXTERN
+
+}  // namespace bzi

@@ -69,12 +69,15 @@ def test_mixed_batch(orc, method, n_t):
     np.testing.assert_array_equal(again, got)
 
 
-def test_mixed_batch_dims_and_kinds(orc):
+@pytest.mark.parametrize("n_t", [8, 16])
+def test_mixed_batch_dims_and_kinds(orc, n_t):
+    """n_t = 16 takes the DPP row-broadcast path (one object per 16-lane
+    row), other n_t the per-lane loads; every dim, degrees 1..15."""
     for dim in (1, 2, 4):
-        b = bz_synth.mixed_batch(n_bezier=500, n_nurbs=60, dim=dim, n_t=8, seed=dim)
+        b = bz_synth.mixed_batch(n_bezier=500, n_nurbs=60, dim=dim, n_t=n_t, deg_lo=1, seed=dim + n_t)
         plan, _ = _plan(b)
         got = host(plan(to_dev(b.t)))
-        assert _err(got, orc.batch_eval(b), _extents(b), 8) <= TOL_F32
+        assert _err(got, orc.batch_eval(b), _extents(b), n_t) <= TOL_F32
     b = bz_synth.mixed_batch(n_bezier=700, n_nurbs=0, n_t=5, seed=4)  # no NURBS, no knots needed
     plan, _ = _plan(b)
     assert _err(host(plan(to_dev(b.t))), orc.batch_eval(b), _extents(b), 5) <= TOL_F32
@@ -113,14 +116,46 @@ def test_low_precision_storage(orc, dtype):
     assert _err(got, orc.batch_eval(rb), _extents(rb), 16) <= TOL_F32
 
 
+@pytest.mark.parametrize("n_t", [16, 8, 4, 12])
+def test_every_launch_configuration(orc, n_t):
+    """Both lane mappings (1 query per lane; 4 consecutive parameters of one
+    object per lane), every tile size, both schedules, small and large
+    grids: within the tolerance of the oracle, and bit-identical across
+    schedules, tile sizes and grids of one mapping."""
+    b = bz_synth.mixed_batch(n_bezier=3000, n_nurbs=300, n_t=n_t, deg_lo=1, seed=40 + n_t)
+    plan, _ = _plan(b)
+    t = to_dev(b.t)
+    ref = orc.batch_eval(b)
+    for vq in (1, 4):
+        first = None  # schedules and tile sizes must not change a bit; the
+        # two lane mappings contract their FMAs differently (1 ulp apart)
+        for sub in (1, 2, 4):
+            for sched in ("dynamic", "static"):
+                for wg in (7, 600):
+                    plan.configure(wg, sub, sched, vq)
+                    out = torch.full((3, b.n_obj * n_t), float("nan"), device=t.device)
+                    got = host(plan(t, out=out))  # every query must be written
+                    assert _err(got, ref, _extents(b), n_t) <= TOL_F32, (vq, sub, sched, wg)
+                    if first is None:
+                        first = got
+                    else:
+                        np.testing.assert_array_equal(got, first)
+    b2 = bz_synth.mixed_batch(n_bezier=50, n_nurbs=5, n_t=6, seed=49)
+    plan2, _ = _plan(b2)
+    with pytest.raises(bz.BzError) as e:
+        plan2.configure(64, 1, "dynamic", 4)
+    assert e.value.code == bz.ERR_UNSUPPORTED
+
+
 def test_autotune_keeps_results(orc):
     b = bz_synth.mixed_batch(n_bezier=20000, n_nurbs=2000, n_t=16, seed=8)
     plan, _ = _plan(b)
     t = to_dev(b.t)
     out = torch.empty((3, b.n_obj * 16), device=t.device)
     best = plan.autotune(t, out)
-    assert best["workgroups"] >= 1 and best["tile_multiple"] in (1, 2, 4)
-    got = host(plan(t))
+    assert best["workgroups"] >= 1 and best["tile_multiple"] in (1, 2, 4) and best["queries_per_lane"] in (1, 4)
+    out.fill_(float("nan"))
+    got = host(plan(t, out=out))
     assert _err(got, orc.batch_eval(b), _extents(b), 16) <= TOL_F32
 
 
