@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
 
 }  // namespace batch_dev
 
-// Launch of the persistent kernel (instantiated in batched_f32/f16/bf16.hip).
+// Launch of the persistent kernel (instantiated in batched_{dc,bern}_{f32,f16,bf16}.hip).
 template <int F, typename T>
 int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) {
     if (a.vq == 4)
