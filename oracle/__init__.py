@@ -384,3 +384,30 @@ def tensor_seiler_grid(sc, du, dv, nu, nv):
     v = np.arange(nv) / max(nv - 1, 1)
     uv = np.stack(np.meshgrid(u, v, indexing="ij"), axis=-1).reshape(1, nu * nv, 2)
     return tensor_seiler_points(sc, du, dv, 0, np.repeat(uv, n, axis=0))
+
+
+def tex_patch_texels(du, dv, mode):
+    return lib().bzo_tex_patch_texels(ctypes.c_int(du), ctypes.c_int(dv), ctypes.c_int(TEX_MODES[mode]))
+
+
+def tex_patch_build(ctrl, du, dv, mode):
+    """Surface textures tex[n][dim][(dv+1)*texels] (float64) of patches ctrl[n][dim][(du+1)(dv+1)]."""
+    ctrl = _d(ctrl)
+    n, dim, _ = ctrl.shape
+    tex = np.empty((n, dim, tex_patch_texels(du, dv, mode)))
+    lib().bzo_tex_patch_build(_ptr(ctrl), _I64(n), ctypes.c_int(du), ctypes.c_int(dv), ctypes.c_int(dim),
+                              ctypes.c_int(TEX_MODES[mode]), _ptr(tex))
+    return tex
+
+
+def tex_patch_eval(tex, du, dv, mode, uv, frac_bits=8, rounding="nearest"):
+    """Emulated reads of float32 surface textures at uv[n][n_per][2] -> out[dim][n*n_per]."""
+    tex = _f(tex)
+    n, dim, _ = tex.shape
+    uv = _f(uv)
+    n_per = uv.shape[1]
+    out = np.empty((dim, n * n_per))
+    lib().bzo_tex_patch_eval(_ptr(tex), _I64(n), ctypes.c_int(du), ctypes.c_int(dv), ctypes.c_int(dim),
+                             ctypes.c_int(TEX_MODES[mode]), _ptr(uv), _I64(n_per), ctypes.c_int(frac_bits),
+                             ctypes.c_int(ROUNDINGS[rounding]), _ptr(out))
+    return out

@@ -862,3 +862,98 @@ void bzo_tensor_seiler_points(const double *sc, int64_t n, int du, int dv, int d
             }
         }
 }
+
+/* ------------------------------------------------------------------ */
+/* Surfaces through the emulated filter (Sec. 2.2: a surface splits its
+ * order between the texture and the shader; Sec. 6: Seiler surfaces in the
+ * interpolator).  Patch ctrl[n][dim][(du+1)(dv+1)] (u major), du in {2, 3},
+ * dv in 1..4.  For every v-index j the u-fibre gets its own curve texture:
+ *   de Casteljau (BZO_TEX_DC): the layers of bzo_tex_build for (P_0j..P_duj),
+ *     read at (u,u[,u]) -> the isoline control point R_j(u); the shader then
+ *     runs de Casteljau over R_0..R_dv at the exact v.
+ *   Seiler (BZO_TEX_SEILER): the net converted to per-axis Seiler terms s_kj
+ *     (bzo_tensor_to_seiler), fibre j as the 2x2 Seiler texture of degree du
+ *     (Table 1); textures j and j+1 stacked front to back form a 2x2x2
+ *     texture whose trilinear read at (u, su, v) is L(c_j, c_j+1, v), c_j the
+ *     v-direction Seiler terms of the isoline at u.  The shader finishes the
+ *     v recursion: pairs (0,1), (2,3) by trilinear reads, an unpaired middle
+ *     term (even dv) by a bilinear read, then c = r0 + sv (r1 + sv c_mid).
+ * Texels per coordinate: (dv+1) x 4(du-1) (de Casteljau) or (dv+1) x 4 (Seiler).
+ * Weights as bzo_tex_axis_weight; v is clamped to [0,1] like u.            */
+int bzo_tex_patch_texels(int du, int dv, int mode)
+{
+    return (dv + 1) * (mode == BZO_TEX_SEILER ? 4 : 4 * (du - 1));
+}
+
+void bzo_tex_patch_build(const double *ctrl, int64_t n, int du, int dv, int dim, int mode, double *tex)
+{
+    const int ncp = (du + 1) * (dv + 1), per = mode == BZO_TEX_SEILER ? 4 : 4 * (du - 1);
+    double *sc = (double *)malloc(sizeof(double) * (size_t)(n * dim * ncp));
+    if (mode == BZO_TEX_SEILER) bzo_tensor_to_seiler(ctrl, n, du, dv, 0, dim, sc);
+    else memcpy(sc, ctrl, sizeof(double) * (size_t)(n * dim * ncp));
+    for (int64_t r = 0; r < n * dim; ++r)
+        for (int j = 0; j <= dv; ++j) {
+            double fib[4];
+            for (int i = 0; i <= du; ++i) fib[i] = sc[r * ncp + i * (dv + 1) + j];
+            double *T = tex + (r * (dv + 1) + j) * per;
+            if (mode != BZO_TEX_SEILER) {
+                for (int i = 0; i < du - 1; ++i) {
+                    T[4 * i + 0] = fib[i];
+                    T[4 * i + 1] = fib[i + 1];
+                    T[4 * i + 2] = fib[i + 1];
+                    T[4 * i + 3] = fib[i + 2];
+                }
+            } else if (du == 2) { /* [b0, b2, d1] */
+                T[0] = fib[0], T[1] = fib[1], T[2] = fib[0] + fib[2], T[3] = fib[1] + fib[2];
+            } else { /* [b0, b3, d1, d2] */
+                T[0] = fib[0], T[1] = fib[1], T[2] = fib[0] + fib[2], T[3] = fib[1] + fib[3];
+            }
+        }
+    free(sc);
+}
+
+void bzo_tex_patch_eval(const float *tex, int64_t n, int du, int dv, int dim, int mode, const float *uv,
+                        int64_t n_per, int frac_bits, int rounding, double *out)
+{
+    const int per = mode == BZO_TEX_SEILER ? 4 : 4 * (du - 1);
+    const int64_t nq = n * n_per;
+#pragma omp parallel for schedule(static)
+    for (int64_t o = 0; o < n; ++o)
+        for (int64_t q = 0; q < n_per; ++q) {
+            float u = uv[(o * n_per + q) * 2], v = uv[(o * n_per + q) * 2 + 1];
+            u = u < 0.0f ? 0.0f : (u > 1.0f ? 1.0f : u);
+            v = v < 0.0f ? 0.0f : (v > 1.0f ? 1.0f : v);
+            const double wu = bzo_tex_axis_weight(u, frac_bits, rounding);
+            const double wsu = bzo_tex_axis_weight((1.0f - u) * u, frac_bits, rounding);
+            const double wv = bzo_tex_axis_weight(v, frac_bits, rounding);
+            for (int c = 0; c < dim; ++c) {
+                double L[5 * 8];
+                const float *T = tex + (o * dim + c) * (int64_t)(dv + 1) * per;
+                for (int e = 0; e < (dv + 1) * per; ++e) L[e] = (double)T[e];
+                double val;
+                if (isnan(u) || isnan(v)) {
+                    val = NAN;
+                } else if (mode != BZO_TEX_SEILER) {
+                    double R[5];
+                    for (int j = 0; j <= dv; ++j)
+                        R[j] = du == 3 ? tex_trilinear(L + j * 8, L + j * 8 + 4, wu, wu, wu)
+                                       : tex_bilinear(L + j * 4, wu, wu);
+                    val = decasteljau(R, 1, dv, (double)v);
+                } else {
+                    const double sv = (1.0 - (double)v) * (double)v;
+                    /* v-Seiler terms in storage order [b0, bd, d1, d_{d-1}, d2 ...]:
+                     * pairs (0,1) and (2,3) by trilinear reads, the middle term
+                     * of even dv (index dv) by a bilinear read                 */
+                    const double r0 = tex_trilinear(L, L + 4, wu, wsu, wv);
+                    double acc = 0.0;
+                    if (dv == 2) acc = tex_bilinear(L + 8, wu, wsu);
+                    if (dv >= 3) {
+                        const double r1 = tex_trilinear(L + 8, L + 12, wu, wsu, wv);
+                        acc = r1 + (dv == 4 ? sv * tex_bilinear(L + 16, wu, wsu) : 0.0);
+                    }
+                    val = r0 + sv * acc;
+                }
+                out[c * nq + o * n_per + q] = val;
+            }
+        }
+}

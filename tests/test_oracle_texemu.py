@@ -340,3 +340,65 @@ def test_degree_6_7_layout_exact(orc, d):
             v = (1 - z) * ((1 - y) * lx(T[0], T[1]) + y * lx(T[2], T[3])) + \
                 z * ((1 - y) * lx(T[4], T[5]) + y * lx(T[6], T[7]))
             assert abs(v - ex.bezier(b, t)) < Fraction(1, 2 ** 40)
+
+
+# ------------------------------------------------------------ surfaces
+PATCH_CASES = [(du, dv) for du in (2, 3) for dv in (1, 2, 3, 4)]
+
+
+def _patches(n, du, dv, dim, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1, 1, size=(n, dim, (du + 1) * (dv + 1))).astype(np.float32)
+
+
+def test_patch_texel_counts(orc):
+    assert orc.tex_patch_texels(3, 3, "decasteljau") == 32 and orc.tex_patch_texels(3, 3, "seiler") == 16
+    assert orc.tex_patch_texels(2, 4, "decasteljau") == 20 and orc.tex_patch_texels(2, 1, "seiler") == 8
+
+
+@pytest.mark.parametrize("du,dv", PATCH_CASES)
+@pytest.mark.parametrize("mode", ["decasteljau", "seiler"])
+def test_patch_unrounded_weights_give_the_surface(orc, du, dv, mode):
+    """F = 0: both surface textures read the tensor-product surface itself
+    (the separable oracle, pinned on its own)."""
+    rng = np.random.default_rng(700 + 10 * du + dv)
+    P = _patches(11, du, dv, 3, 710 + du + dv)
+    uv = rng.random((11, 50, 2)).astype(np.float32)
+    uv[:, :4] = [[0, 0], [1, 1], [0, 1], [1, 0]]
+    tex = orc.tex_patch_build(P, du, dv, mode).astype(np.float32)
+    got = orc.tex_patch_eval(tex, du, dv, mode, uv, frac_bits=0)
+    ref = orc.tensor_points(P, du, dv, 0, uv)
+    assert np.abs(got - ref).max() <= 4e-6 * _ext(P)
+
+
+@pytest.mark.parametrize("du,dv", PATCH_CASES)
+def test_patch_decasteljau_is_the_surface_at_the_rounded_u(orc, du, dv):
+    """De Casteljau surface textures round only u (all of the u reads share
+    one weight w); v is the shader's: the result is S(w(u), v) exactly."""
+    rng = np.random.default_rng(720 + 10 * du + dv)
+    P = _patches(9, du, dv, 2, 730 + du + dv)
+    uv = rng.random((9, 40, 2)).astype(np.float32)
+    tex = orc.tex_patch_build(P, du, dv, "decasteljau").astype(np.float32)
+    got = orc.tex_patch_eval(tex, du, dv, "decasteljau", uv, 8, "nearest")
+    w = orc.tex_axis_weights(uv[:, :, 0].ravel(), 8).reshape(9, 40)
+    ref = orc.tensor_points(P, du, dv, 0, np.stack([w, uv[:, :, 1].astype(np.float64)], axis=-1))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("du,dv", PATCH_CASES)
+def test_patch_seiler_dyadic_parameters_are_exact(orc, du, dv):
+    """Seiler surface textures round u, su and v: where all three are on the
+    8-bit grid the read is the surface."""
+    us = np.array([0.0, 1.0, 0.5, 0.25, 0.75, 0.125, 1 / 16], np.float64)
+    vs = np.array([0.0, 1.0, 0.5, 37 / 256, 200 / 256], np.float64)
+    assert (((1 - us) * us * 256) % 1 == 0).all()
+    uv = np.array([[[u, v] for u in us for v in vs]] * 6, np.float32)
+    P = _patches(6, du, dv, 3, 740 + du + dv)
+    tex = orc.tex_patch_build(P, du, dv, "seiler").astype(np.float32)
+    got = orc.tex_patch_eval(tex, du, dv, "seiler", uv, 8, "nearest")
+    ref = orc.tensor_points(P, du, dv, 0, uv)
+    assert np.abs(got - ref).max() <= 4e-6 * _ext(P)
+    # elsewhere the rounding shows
+    uv2 = np.random.default_rng(750).random((6, 64, 2)).astype(np.float32)
+    e = np.abs(orc.tex_patch_eval(tex, du, dv, "seiler", uv2, 8) - orc.tensor_points(P, du, dv, 0, uv2)).max()
+    assert 1e-5 < e < 0.1 * _ext(P)
