@@ -401,6 +401,25 @@ def suite_texemu(torch, bz, bz_synth, cpu):
         ref = oracle.tex_eval(tex7[:sub].cpu().numpy(), 7, "seiler", t, False, 8, "nearest")
         r["max_err_bbox_vs_oracle_emulation"] = max_err_bbox(got, ref, e7, nt)
     res["seiler_degree7"] = r
+    # bicubic patches through the emulated filter: 2^16 patches x 256 random (u, v)
+    P = bz_synth.patches(n_obj=1 << 16)
+    uvp = np.random.default_rng(1004 + 1).random((1 << 16, 256, 2)).astype(np.float32)
+    P_d, uv_d = torch.from_numpy(P).cuda(), torch.from_numpy(uvp).cuda()
+    op = torch.empty((3, (1 << 16) * 256), device="cuda")
+    kp = 512
+    exact_p = oracle.tensor_points(P[:kp], 3, 3, 0, uvp[:kp]) if cpu else None
+    for mode in ("decasteljau", "seiler"):
+        texp = bz.build_texture_patch(P_d, 3, 3, mode)
+        ms = timed(lambda: bz.eval_texture_patch(texp, 3, 3, mode, uv_d, 8, "nearest", out=op), torch)
+        r = {"kernel_ms": ms, "value": op.shape[1] / (ms * 1e-3) / 1e9,
+             "roofline": hbm_roof(texp.numel() * 4 + uvp.nbytes + op.numel() * 4, ms)}
+        if cpu:
+            got = op[:, :kp * 256].cpu().numpy()
+            ref = oracle.tex_patch_eval(texp[:kp].cpu().numpy(), 3, 3, mode, uvp[:kp])
+            r["quantisation_err_bbox"] = max_err_bbox(got, exact_p, extents(P[:kp]), 256)
+            r["max_err_bbox_vs_oracle_emulation"] = max_err_bbox(got, ref, extents(P[:kp]), 256)
+        res["patch_" + mode] = r
+    del op
     del out
     chain, T = bz_synth.chain_walk()
     nseg, nq = (chain.shape[0] - 1) // 2, T.shape[0]
@@ -428,7 +447,8 @@ def suite_texemu(torch, bz, bz_synth, cpu):
                                "kind": "oracle", "sample": "1024 curves x 256 t, trilinear mode"}
     return {"workload": "texture-filter emulation, 8 fractional weight bits: 65536 cubic 3D curves x 256 shared t "
                         "in the trilinear / hybrid / Seiler modes (quantisation error on the first 1024 curves), 16384 "
-                        "degree-7 curves in one 2x2x2 Seiler texture, "
+                        "degree-7 curves in one 2x2x2 Seiler texture, 2^16 bicubic patches at 256 random (u, v) "
+                        "(de Casteljau isoline reads / Seiler surface reads), "
                         "and the 2^20-segment chain at 2^24 random T", "unit": "G evals/s", **res}
 
 

@@ -249,6 +249,32 @@ int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const fl
                              int rounding, float *out, bz_stream stream);
 
 /*
+ * Surfaces through the emulated filter (Sec. 2.2: the surface's order splits
+ * between texture reads in u and shader lerps in v; Sec. 6: Seiler surfaces
+ * in the interpolator).  ctrl[n_obj][dim][(du+1)(dv+1)] FP32 (u major), du
+ * 2..3, dv 1..4; tex[n_obj][dim][texels], one u-curve texture per v-index j
+ * (16-byte aligned); uv[n_obj][n_per][2] (8-byte aligned), out[dim][n_obj*n_per];
+ * weight rule, frac_bits and rounding as bz_eval_texture, u and v clamped to
+ * [0,1].
+ *   BZ_TEX_DECASTELJAU: texture j = the de Casteljau layers of the u-fibre
+ *     P_0j..P_duj (4(du-1) texels), read at (u,u[,u]) -> isoline control point
+ *     R_j(u); then de Casteljau over R_0..R_dv at the exact v in FP32.
+ *   BZ_TEX_SEILER: the net converted to per-axis Seiler terms s (as
+ *     bz_tensor_to_seiler, FP64, sums rounded once); texture j = the 2x2
+ *     Seiler texture of the u-fibre of s (4 texels, Table 1).  Textures j,
+ *     j+1 form a 2x2x2 texture read at (u, su, v) = L(c_j, c_j+1, v), c the
+ *     isoline's v-direction Seiler terms; pairs (0,1), (2,3) by trilinear
+ *     reads, the middle term of even dv by a bilinear read, then
+ *     c = r0 + sv (r1 + sv c_mid) in FP32.
+ * bz_texture_patch_texels: texels per patch and coordinate, 0 if unsupported.
+ */
+int bz_texture_patch_texels(int du, int dv, int mode);
+int bz_build_texture_patch(const float *ctrl, int64_t n_obj, int du, int dv, int dim, int mode, float *tex,
+                           bz_stream stream);
+int bz_eval_texture_patch(const float *tex, int64_t n_obj, int du, int dv, int dim, int mode, const float *uv,
+                          int64_t n_per, int frac_bits, int rounding, float *out, bz_stream stream);
+
+/*
  * Tensor-product surfaces and volumes (Sec. 2.2: per-axis order split).
  * ctrl: [n_obj][dim][(du+1)(dv+1)(dw+1)] in dtype, index (i*(dv+1)+j)*(dw+1)+k
  * (u major).  dw = 0 for surfaces.  Degrees 1..4 per axis (dw 0..4).

@@ -65,6 +65,9 @@ _SIGS = {
     "bz_piecewise_cubic_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_cubic_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_texture_patch_texels": (_I, [_I, _I, _I]),
+    "bz_build_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
+    "bz_eval_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -255,6 +258,25 @@ def eval_texture(tex, degree, mode, t, frac_bits=8, rounding="nearest", out=None
     check(lib().bz_eval_texture(_ptr(tex), n, degree, dim, TEX_MODES[mode], _ptr(t), nt,
                                 T_PER_OBJECT if per_object else T_SHARED, frac_bits, TEX_ROUNDING[rounding],
                                 _ptr(out), _stream()))
+    return out
+
+
+def build_texture_patch(ctrl, du, dv, mode, out=None):
+    """FP32 patches [n, dim, (du+1)(dv+1)] -> emulated surface textures [n, dim, texels]."""
+    n, dim, _ = ctrl.shape
+    ntx = lib().bz_texture_patch_texels(du, dv, TEX_MODES[mode])
+    out = _f32_out((n, dim, max(ntx, 1)), ctrl.device, out)
+    check(lib().bz_build_texture_patch(_ptr(ctrl), n, du, dv, dim, TEX_MODES[mode], _ptr(out), _stream()))
+    return out
+
+
+def eval_texture_patch(tex, du, dv, mode, uv, frac_bits=8, rounding="nearest", out=None):
+    """Surface textures read through the emulated filter at uv[n, n_per, 2] -> out[dim, n*n_per]."""
+    n, dim, _ = tex.shape
+    n_per = uv.shape[1]
+    out = _f32_out((dim, n * n_per), tex.device, out)
+    check(lib().bz_eval_texture_patch(_ptr(tex), n, du, dv, dim, TEX_MODES[mode], _ptr(uv), n_per, frac_bits,
+                                      TEX_ROUNDING[rounding], _ptr(out), _stream()))
     return out
 
 

@@ -16,6 +16,10 @@
 //                    6 and 7, (t, st, (st)^2).
 //  k_piecewise_texemu  the zig-zag chain (Sec. 2.1) read through the same
 //                    emulated bilinear filter in texel space.
+//  k_tex_patch_build / k_texemu_patch  surfaces (Sec. 2.2): per v-index a
+//                    u-curve texture; de Casteljau isoline reads + v in FP32,
+//                    or per-axis Seiler u-textures paired into 2x2x2 reads at
+//                    (u, su, v) (Seiler surfaces in the filter, Sec. 6).
 //
 // The weight decisions are FP32 with every operation rounded as written (no
 // contraction), so they match any other FP32 evaluation of the same rule.
@@ -293,6 +297,184 @@ int launch_chain_texemu(const float *grid, uint32_t n_seg, const float *T, uint3
     return BZ_OK;
 }
 
+
+// ------------------------------------------------------------------ surfaces
+// Patch ctrl[n][dim][(DU+1)(DV+1)] (u major), DU in {2, 3}, DV in 1..4.  Every
+// v-index j gets the u-curve texture of its fibre: de Casteljau layers of
+// (P_0j..P_DUj), or -- Seiler mode -- the Table 1 texture of the fibre of the
+// per-axis Seiler terms (converted along v, then u, in FP64).
+template <int DU, int MODE>
+constexpr int patch_fibre_texels() {
+    return MODE == TX_SEILER ? 4 : 4 * (DU - 1);
+}
+
+template <int DU, int DV, int MODE>
+__global__ __launch_bounds__(kBlock) void k_tex_patch_build(const float *__restrict__ ctrl, float *__restrict__ tex,
+                                                             uint32_t n_rows) {
+    constexpr int NV = DV + 1, NCP = (DU + 1) * NV, PER = patch_fibre_texels<DU, MODE>();
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n_rows) return;
+    double a[NCP];
+#pragma unroll
+    for (int e = 0; e < NCP; ++e) a[e] = static_cast<double>(ctrl[static_cast<size_t>(r) * NCP + e]);
+    if constexpr (MODE == TX_SEILER) {
+#pragma unroll
+        for (int i = 0; i <= DU; ++i) {  // v fibres
+            double b[DV + 1], sc[DV + 1];
+#pragma unroll
+            for (int j = 0; j <= DV; ++j) b[j] = a[i * NV + j];
+            seiler_terms<DV, double, double, double>(b, sc);
+#pragma unroll
+            for (int j = 0; j <= DV; ++j) a[i * NV + j] = sc[j];
+        }
+#pragma unroll
+        for (int j = 0; j <= DV; ++j) {  // u fibres
+            double b[DU + 1], sc[DU + 1];
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) b[i] = a[i * NV + j];
+            seiler_terms<DU, double, double, double>(b, sc);
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) a[i * NV + j] = sc[i];
+        }
+    }
+    float *__restrict__ o = tex + static_cast<size_t>(r) * NV * PER;
+#pragma unroll
+    for (int j = 0; j <= DV; ++j) {
+        float T[PER];
+        if constexpr (MODE != TX_SEILER) {
+#pragma unroll
+            for (int i = 0; i < DU - 1; ++i) {
+                T[4 * i] = static_cast<float>(a[i * NV + j]);
+                T[4 * i + 1] = static_cast<float>(a[(i + 1) * NV + j]);
+                T[4 * i + 2] = static_cast<float>(a[(i + 1) * NV + j]);
+                T[4 * i + 3] = static_cast<float>(a[(i + 2) * NV + j]);
+            }
+        } else {
+            // fibre terms [b0, bd, d1(, d2)]: degree 2 [[b0, b2], [b0+d1, b2+d1]],
+            // degree 3 [[b0, b3], [b0+d1, b3+d2]]
+            const double b0 = a[j], bd = a[NV + j], d1 = a[2 * NV + j];
+            const double dl = DU == 2 ? d1 : a[3 * NV + j];
+            T[0] = static_cast<float>(b0), T[1] = static_cast<float>(bd);
+            T[2] = static_cast<float>(b0 + d1), T[3] = static_cast<float>(bd + dl);
+        }
+#pragma unroll
+        for (int e = 0; e < PER / 4; ++e)
+            reinterpret_cast<float4 *>(o + j * PER)[e] = make_float4(T[4 * e], T[4 * e + 1], T[4 * e + 2], T[4 * e + 3]);
+    }
+}
+
+struct TexPatchArgs {
+    const float *tex;  // textures of patches [o0, o0+n)
+    const float *uv;   // base of the full parameter array [n_obj][n_per][2]
+    float *out;
+    int64_t plane;
+    int64_t q0;        // first query of this launch
+    uint32_t nq;
+    FastDiv div_per;
+    int frac_bits;
+    int rounding;
+};
+
+template <int DU, int DV, int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_texemu_patch(TexPatchArgs a) {
+    constexpr int PER = patch_fibre_texels<DU, MODE>(), NT = (DV + 1) * PER;
+    const uint32_t ql = blockIdx.x * kBlock + threadIdx.x;
+    if (ql >= a.nq) return;
+    const uint32_t ol = fdiv(ql, a.div_per);
+    const int64_t qg = a.q0 + ql;
+    const float2 p2 = reinterpret_cast<const float2 *>(a.uv)[qg];
+    float u = p2.x < 0.0f ? 0.0f : p2.x, v = p2.y < 0.0f ? 0.0f : p2.y;  // clamp-to-edge; NaN passes
+    u = u > 1.0f ? 1.0f : u;
+    v = v > 1.0f ? 1.0f : v;
+    const float wu = tx_axis_weight(u, a.frac_bits, a.rounding);
+    float wsu = 0.0f, wv = 0.0f;
+    if constexpr (MODE == TX_SEILER) {
+#pragma clang fp contract(off)
+        wsu = tx_axis_weight((1.0f - u) * u, a.frac_bits, a.rounding);
+        wv = tx_axis_weight(v, a.frac_bits, a.rounding);
+    }
+    const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.tex + static_cast<size_t>(ol) * DIM * NT);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        float L[NT];
+#pragma unroll
+        for (int e = 0; e < NT / 4; ++e) {
+            const float4 x = src[c * (NT / 4) + e];
+            L[4 * e] = x.x, L[4 * e + 1] = x.y, L[4 * e + 2] = x.z, L[4 * e + 3] = x.w;
+        }
+        float val;
+        if constexpr (MODE != TX_SEILER) {
+            float R[DV + 1];  // isoline control points R_j(u), then de Casteljau in v
+#pragma unroll
+            for (int j = 0; j <= DV; ++j)
+                R[j] = DU == 3 ? lerp(tx_bilinear(L + j * PER, wu, wu), tx_bilinear(L + j * PER + 4, wu, wu), wu)
+                               : tx_bilinear(L + j * PER, wu, wu);
+#pragma unroll
+            for (int lvl = 1; lvl <= DV; ++lvl)
+#pragma unroll
+                for (int j = 0; j <= DV - lvl; ++j) R[j] = lerp(R[j], R[j + 1], v);
+            val = R[0];
+        } else {
+            // v-Seiler terms in storage order [b0, bd, d1, d_{d-1}, d2]: pairs
+            // (0,1) and (2,3) by trilinear reads at (u, su, v), the middle
+            // term of even DV by a bilinear read at (u, su)
+            const float sv = (1.0f - v) * v;
+            const float r0 = lerp(tx_bilinear(L, wu, wsu), tx_bilinear(L + 4, wu, wsu), wv);
+            float acc = 0.0f;
+            if constexpr (DV == 2) acc = tx_bilinear(L + 8, wu, wsu);
+            if constexpr (DV >= 3) {
+                acc = lerp(tx_bilinear(L + 8, wu, wsu), tx_bilinear(L + 12, wu, wsu), wv);
+                if constexpr (DV == 4) acc = __builtin_fmaf(sv, tx_bilinear(L + 16, wu, wsu), acc);
+            }
+            val = __builtin_fmaf(sv, acc, r0);
+        }
+        st_stream(a.out + c * a.plane + qg, val);
+    }
+}
+
+template <int MODE>
+int launch_patch_build(int du, int dv, const float *ctrl, float *tex, uint32_t rows, hipStream_t s) {
+    const uint32_t blocks = (rows + kBlock - 1) / kBlock;
+#define BZI_PB(U, V)                                                                                        \
+    if (du == U && dv == V) {                                                                               \
+        hipLaunchKernelGGL((k_tex_patch_build<U, V, MODE>), dim3(blocks), dim3(kBlock), 0, s, ctrl, tex, rows); \
+        BZ_CHECK_LAUNCH("k_tex_patch_build");                                                               \
+        return BZ_OK;                                                                                       \
+    }
+    BZI_PB(2, 1) BZI_PB(2, 2) BZI_PB(2, 3) BZI_PB(2, 4) BZI_PB(3, 1) BZI_PB(3, 2) BZI_PB(3, 3) BZI_PB(3, 4)
+#undef BZI_PB
+    return fail(BZ_ERR_SHAPE, "degrees (%d, %d)", du, dv);
+}
+
+template <int DU, int DV, int MODE>
+int launch_patch_eval_d(int dim, const TexPatchArgs &a, hipStream_t s) {
+    const uint32_t blocks = (a.nq + kBlock - 1) / kBlock;
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 1, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 2, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 3, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 4, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
+    BZ_CHECK_LAUNCH("k_texemu_patch");
+    return BZ_OK;
+}
+
+template <int MODE>
+int launch_patch_eval(int du, int dv, int dim, const TexPatchArgs &a, hipStream_t s) {
+#define BZI_PE(U, V) \
+    if (du == U && dv == V) return launch_patch_eval_d<U, V, MODE>(dim, a, s);
+    BZI_PE(2, 1) BZI_PE(2, 2) BZI_PE(2, 3) BZI_PE(2, 4) BZI_PE(3, 1) BZI_PE(3, 2) BZI_PE(3, 3) BZI_PE(3, 4)
+#undef BZI_PE
+    return fail(BZ_ERR_SHAPE, "degrees (%d, %d)", du, dv);
+}
+
+int patch_texels_rt(int du, int dv, int mode) {
+    if (du < 2 || du > 3 || dv < 1 || dv > 4) return 0;
+    if (mode == TX_SEILER) return (dv + 1) * 4;
+    if (mode == TX_DC) return (dv + 1) * 4 * (du - 1);
+    return 0;
+}
+
 constexpr int kMaxFracBits = 20;
 
 }  // namespace
@@ -398,6 +580,70 @@ int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const fl
                 case 3: rc = launch_chain_texemu<3>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
                 default: rc = launch_chain_texemu<4>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
             }
+            if (rc) return rc;
+        }
+        return BZ_OK;
+    });
+}
+
+int bz_texture_patch_texels(int du, int dv, int mode) { return patch_texels_rt(du, dv, mode); }
+
+int bz_build_texture_patch(const float *ctrl, int64_t n_obj, int du, int dv, int dim, int mode, float *tex,
+                           bz_stream stream) {
+    return guarded("bz_build_texture_patch", [&]() -> int {
+        const char *fn = "bz_build_texture_patch";
+        if (patch_texels_rt(du, dv, mode) == 0)
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degrees (%d, %d) (du 2..3, dv 1..4, de Casteljau or Seiler)",
+                        fn, mode, du, dv);
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_obj < 0 || n_obj * dim > (int64_t(1) << 31)) return fail(BZ_ERR_SHAPE, "%s: n_obj", fn);
+        if (n_obj == 0) return BZ_OK;
+        if (!ctrl || !tex) return fail(BZ_ERR_NULL, "%s: ctrl and tex are required", fn);
+        if (!aligned(ctrl, 4) || !aligned(tex, 16)) return fail(BZ_ERR_ALIGN, "%s: tex needs 16-byte alignment", fn);
+        const uint32_t rows = static_cast<uint32_t>(n_obj * dim);
+        const hipStream_t s = as_stream(stream);
+        if (mode == TX_SEILER) return launch_patch_build<TX_SEILER>(du, dv, ctrl, tex, rows, s);
+        return launch_patch_build<TX_DC>(du, dv, ctrl, tex, rows, s);
+    });
+}
+
+int bz_eval_texture_patch(const float *tex, int64_t n_obj, int du, int dv, int dim, int mode, const float *uv,
+                          int64_t n_per, int frac_bits, int rounding, float *out, bz_stream stream) {
+    return guarded("bz_eval_texture_patch", [&]() -> int {
+        const char *fn = "bz_eval_texture_patch";
+        const int ntx = patch_texels_rt(du, dv, mode);
+        if (ntx == 0)
+            return fail(BZ_ERR_UNSUPPORTED, "%s: mode %d at degrees (%d, %d) (du 2..3, dv 1..4, de Casteljau or Seiler)",
+                        fn, mode, du, dv);
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_obj < 0 || n_per < 0 || n_per > (int64_t(1) << 30)) return fail(BZ_ERR_SHAPE, "%s: counts", fn);
+        if (n_obj > 0 && n_per > 0 && n_obj > (int64_t(1) << 62) / n_per)
+            return fail(BZ_ERR_SHAPE, "%s: n_obj*n_per overflows", fn);
+        if (frac_bits < 0 || frac_bits > kMaxFracBits)
+            return fail(BZ_ERR_SHAPE, "%s: frac_bits %d not in 0..%d", fn, frac_bits, kMaxFracBits);
+        if (rounding != BZ_TEXW_NEAREST && rounding != BZ_TEXW_TRUNCATE)
+            return fail(BZ_ERR_SHAPE, "%s: rounding %d", fn, rounding);
+        if (n_obj == 0 || n_per == 0) return BZ_OK;
+        if (!tex || !uv || !out) return fail(BZ_ERR_NULL, "%s: tex, uv and out are required", fn);
+        if (!aligned(tex, 16) || !aligned(uv, 8) || !aligned(out, 4))
+            return fail(BZ_ERR_ALIGN, "%s: tex needs 16-byte, uv 8-byte alignment", fn);
+        const hipStream_t s = as_stream(stream);
+        const int64_t nq = n_obj * n_per;
+        const int64_t per = std::max<int64_t>(1, (int64_t(1) << 30) / n_per);
+        for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
+            const int64_t no = std::min(per, n_obj - o0);
+            TexPatchArgs a;
+            a.tex = tex + o0 * dim * ntx;
+            a.uv = uv;
+            a.out = out;
+            a.plane = nq;
+            a.q0 = o0 * n_per;
+            a.nq = static_cast<uint32_t>(no * n_per);
+            a.div_per = make_fastdiv(static_cast<uint32_t>(n_per));
+            a.frac_bits = frac_bits;
+            a.rounding = rounding;
+            const int rc = mode == TX_SEILER ? launch_patch_eval<TX_SEILER>(du, dv, dim, a, s)
+                                             : launch_patch_eval<TX_DC>(du, dv, dim, a, s);
             if (rc) return rc;
         }
         return BZ_OK;

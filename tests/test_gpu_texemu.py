@@ -161,3 +161,69 @@ def test_chain_texemu_full_size(orc):
     ref = orc.chain_texemu_eval(gh, T)
     scale = max(float((chain.max(axis=0) - chain.min(axis=0)).max()), float(np.abs(gh).max()))
     assert np.abs(got - ref).max() / scale <= TOL_F32
+
+
+# ------------------------------------------------------------ surfaces
+PATCH_CASES = [(du, dv) for du in (2, 3) for dv in (1, 2, 3, 4)]
+
+
+def _patches(n, du, dv, dim, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1, 1, size=(n, dim, (du + 1) * (dv + 1))).astype(np.float32)
+
+
+@pytest.mark.parametrize("du,dv", PATCH_CASES)
+@pytest.mark.parametrize("mode", ["decasteljau", "seiler"])
+def test_patch_build_parity(orc, du, dv, mode):
+    P = _patches(123, du, dv, 3, 800 + du + 5 * dv)
+    got = host(bz.build_texture_patch(to_dev(P), du, dv, mode))
+    ref = orc.tex_patch_build(P, du, dv, mode)
+    assert got.shape == ref.shape
+    if mode == "decasteljau":
+        np.testing.assert_array_equal(got, ref)
+    else:
+        assert (np.abs(got - ref) <= np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)).all()
+
+
+@pytest.mark.parametrize("du,dv", PATCH_CASES)
+@pytest.mark.parametrize("mode", ["decasteljau", "seiler"])
+@pytest.mark.parametrize("frac_bits,rounding", [(8, "nearest"), (8, "truncate"), (0, "nearest")])
+def test_patch_eval_parity(orc, du, dv, mode, frac_bits, rounding):
+    rng = np.random.default_rng(810 + du + 5 * dv + frac_bits)
+    for dim, n_per in ((3, 77), (1, 300), (4, 256)):
+        P = _patches(19, du, dv, dim, 820 + du + dv + dim)
+        tex = orc.tex_patch_build(P, du, dv, mode).astype(np.float32)
+        uv = rng.random((19, n_per, 2)).astype(np.float32)
+        uv[:, :3] = [[0, 0], [1, 1], [0.5, 0.25]]
+        got = host(bz.eval_texture_patch(to_dev(tex), du, dv, mode, to_dev(uv), frac_bits, rounding))
+        ref = orc.tex_patch_eval(tex, du, dv, mode, uv, frac_bits, rounding)
+        assert bbox_err(got, ref, extents(P), n_per) <= TOL_F32, (dim, n_per)
+
+
+def test_patch_fig3_style_errors(orc):
+    """Bicubic patches, 8-bit nearest weights: the GPU's deviation from the
+    exact surface per mode is the oracle's; de Casteljau (u rounded, v exact
+    in the shader) errs less than Seiler (u, su and v rounded)."""
+    P = bz_synth.patches(n_obj=1024)
+    uv = np.random.default_rng(830).random((1024, 64, 2)).astype(np.float32)
+    exact = orc.tensor_points(P, 3, 3, 0, uv)
+    errs = {}
+    for mode in ("decasteljau", "seiler"):
+        tex = bz.build_texture_patch(to_dev(P), 3, 3, mode)
+        got = host(bz.eval_texture_patch(tex, 3, 3, mode, to_dev(uv)))
+        ref = orc.tex_patch_eval(host(tex).astype(np.float32), 3, 3, mode, uv)
+        assert bbox_err(got, ref, extents(P), 64) <= TOL_F32
+        errs[mode] = bbox_err(got, exact, extents(P), 64)
+    assert errs["decasteljau"] < errs["seiler"] < 2 ** -5
+
+
+def test_patch_errors():
+    P = to_dev(_patches(3, 3, 3, 3, 840))
+    assert bz.lib().bz_texture_patch_texels(4, 3, 0) == 0 and bz.lib().bz_texture_patch_texels(3, 3, 1) == 0
+    with pytest.raises(bz.BzError) as e:
+        bz.build_texture_patch(P, 3, 3, "hybrid")
+    assert e.value.code == bz.ERR_UNSUPPORTED
+    tex = bz.build_texture_patch(P, 3, 3, "seiler")
+    with pytest.raises(bz.BzError) as e:
+        bz.eval_texture_patch(tex, 3, 3, "seiler", to_dev(np.zeros((3, 4, 2), np.float32)), frac_bits=30)
+    assert e.value.code == bz.ERR_SHAPE
