@@ -18,7 +18,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 SEEDS = {"plain": 1001, "chain": 1002, "batched": 1003, "patch": 1004,
-         "volume": 1005, "fit": 1006}
+         "volume": 1005, "fit": 1006, "particles": 1007}
 
 KIND_BEZIER = 0
 KIND_RATIONAL = 1
@@ -211,3 +211,27 @@ def fit_problem(n_curves=65536, n_samples=128, dim=3, degree=3, noise=0.01, seed
     tau = _f32(np.sort(rng.random((n_curves, n_samples)), axis=1))
     eps = _f32(rng.normal(0.0, noise, size=(dim, n_curves * n_samples)))
     return gt, tau, eps
+
+
+# ---------------------------------------------------------------- particle ring
+def particle_ring(n_seg=16, n_particles=1 << 20, jitter=0.15, seed=SEEDS["particles"]):
+    """A closed C0 ring of n_seg cubic Bezier segments and particles on it
+    (Sec. 5's particle test: cubic curves chained into a ring, particles
+    moving along them).  Shared endpoints lie on the unit circle at angles
+    2 pi k / n_seg in the z = 0 plane; each inner control point is a third
+    of the way along the chord plus U[-jitter, jitter]^3.  Returns
+    segments[n_seg][3][4] (per-segment control points, endpoints repeated,
+    the last segment ending at the first point), particle phases
+    T ~ U[0, n_seg) and speeds ~ U[0.5, 1.5] segments per unit time."""
+    rng = np.random.default_rng(seed)
+    ang = 2.0 * np.pi * np.arange(n_seg) / n_seg
+    A = np.stack([np.cos(ang), np.sin(ang), np.zeros(n_seg)], axis=1)
+    seg = np.empty((n_seg, 3, 4))
+    for k in range(n_seg):
+        a, b = A[k], A[(k + 1) % n_seg]
+        p1 = a + (b - a) / 3.0 + rng.uniform(-jitter, jitter, 3)
+        p2 = a + 2.0 * (b - a) / 3.0 + rng.uniform(-jitter, jitter, 3)
+        seg[k] = np.stack([a, p1, p2, b], axis=1)
+    T = _f32(rng.uniform(0.0, 1.0, size=n_particles) * n_seg)
+    speed = _f32(rng.uniform(0.5, 1.5, size=n_particles))
+    return _f32(seg), T, speed

@@ -411,3 +411,21 @@ def tex_patch_eval(tex, du, dv, mode, uv, frac_bits=8, rounding="nearest"):
                              ctypes.c_int(TEX_MODES[mode]), _ptr(uv), _I64(n_per), ctypes.c_int(frac_bits),
                              ctypes.c_int(ROUNDINGS[rounding]), _ptr(out))
     return out
+
+
+# ------------------------------------------------ particle ring
+PARTICLE_METHODS = {"polynomial": 0, "seiler": 1, "seiler_texture": 2, "table": 3}
+
+
+def particles_step(seg, T, speed, dt, method, iters, samples=64):
+    """One frame of the particle ring: returns (T_new float32, pos[3][P], shade[P])."""
+    seg = _d(seg)
+    T = _f(T).copy()
+    speed = _f(speed)
+    P = T.shape[0]
+    pos = np.empty((3, P))
+    shade = np.empty(P)
+    lib().bzo_particles_step(_ptr(seg), _I64(seg.shape[0]), ctypes.c_int(PARTICLE_METHODS[method]),
+                             ctypes.c_int(samples), _ptr(T), _ptr(speed), ctypes.c_float(dt), _I64(P),
+                             ctypes.c_int(iters), _ptr(pos), _ptr(shade))
+    return T, pos, shade

@@ -957,3 +957,73 @@ void bzo_tex_patch_eval(const float *tex, int64_t n, int du, int dv, int dim, in
             }
         }
 }
+
+/* ------------------------------------------------------------------ */
+/* Particle ring (Sec. 5: particles moving along cubic Bezier curves chained
+ * into a ring, the curve evaluated per particle per frame, beside other
+ * work).  seg[N][3][4] per-segment cubic control points (closed ring).  One
+ * frame per particle p:
+ *   T <- T + speed * dt, wrapped into [0, N) -- FP32, operations as written;
+ *   k = min(floor T, N-1), t = T - k (FP32);
+ *   position by the method:
+ *     0 polynomial (Bernstein), 1 Seiler terms: the cubic at (k, t) (FP64);
+ *     2 emulated 8-bit Seiler texture: the segment's Table 1 texture read at
+ *       (t, st) through the emulated filter (frac_bits 8, nearest);
+ *     3 sampled table of S points per segment: x = T * S (FP32),
+ *       i = min(floor x, N*S - 1), f = x - i, lerp of the exact samples
+ *       C(i) and C(i+1) (C(j) the ring at segment j / S, local (j mod S) / S,
+ *       C(N*S) = C(0));
+ *   consumer (K steps of arithmetic on the position):
+ *     v_0 = 0, v_{i+1} = a v_i + (b x + c y + d z)
+ *     with a = 23/32, b = 1/4, c = -1/8, d = 1/16 (FP64 here).
+ * Reading: the paper's consumer is a shader's other work; a fixed K-step
+ * linear recurrence stands in for it (its cost scales with K).              */
+static double ring_point(const double *seg, int64_t k, int c, double t)
+{
+    return decasteljau(seg + (k * 3 + c) * 4, 1, 3, t);
+}
+
+void bzo_particles_step(const double *seg, int64_t nseg, int method, int samples, float *T, const float *speed,
+                        float dt, int64_t np, int iters, double *pos, double *shade)
+{
+    const double a = 23.0 / 32.0, b = 0.25, cc = -0.125, d = 0.0625;
+    const int64_t ntab = nseg * samples;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        float Tn = T[p] + speed[p] * dt;
+        const float nf = (float)nseg;
+        if (Tn >= nf) Tn -= nf;
+        if (Tn < 0.0f) Tn += nf;
+        if (Tn >= nf) Tn = 0.0f; /* only if the subtraction rounded up to N */
+        T[p] = Tn;
+        int64_t k = (int64_t)floorf(Tn);
+        if (k > nseg - 1) k = nseg - 1;
+        const float t = Tn - (float)k;
+        double xyz[3];
+        for (int c = 0; c < 3; ++c) {
+            if (method == 0 || method == 1) {
+                xyz[c] = ring_point(seg, k, c, (double)t);
+            } else if (method == 2) {
+                double sc[4];
+                seiler_coeffs(seg + (k * 3 + c) * 4, 3, sc);
+                const double L[4] = {sc[0], sc[1], sc[0] + sc[2], sc[1] + sc[3]};
+                const float st = (1.0f - t) * t;
+                xyz[c] = tex_bilinear(L, bzo_tex_axis_weight(t, 8, 0), bzo_tex_axis_weight(st, 8, 0));
+            } else {
+                const float x = Tn * (float)samples;
+                int64_t i = (int64_t)floorf(x);
+                if (i > ntab - 1) i = ntab - 1;
+                const float f = x - (float)i;
+                const int64_t i1 = (i + 1) % ntab;
+                const double c0 = ring_point(seg, i / samples, c, (double)(i % samples) / samples);
+                const double c1 = ring_point(seg, i1 / samples, c, (double)(i1 % samples) / samples);
+                xyz[c] = lerp(c0, c1, (double)f);
+            }
+            pos[c * np + p] = xyz[c];
+        }
+        double v = 0.0;
+        const double drive = b * xyz[0] + cc * xyz[1] + d * xyz[2];
+        for (int i = 0; i < iters; ++i) v = a * v + drive;
+        shade[p] = v;
+    }
+}
