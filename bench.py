@@ -14,9 +14,10 @@ forms), the C0 cubic chain stored as two stacked zig-zag layers, the
 texture-filter emulation (Fig. 3's three read modes and the chain through an
 emulated bilinear filter, 8-bit weights), the mixed batch in one persistent
 launch (FP32 vs FP16 storage), bicubic patch tessellation (VALU vs
-FP32/BF16/FP16/FP16x3 MFMA), tricubic volumes at random points, and the
+FP32/BF16/FP16/FP16x3 MFMA), tricubic volumes at random points, the
 fitting loop (fused loss + adjoint + Adam, 200 steps in one register-resident
-launch).
+launch), and the particle ring of the paper's performance section (frame
+time per position method as the consumer's arithmetic grows).
 
 Prints one JSON line.
 """
@@ -452,6 +453,42 @@ def suite_texemu(torch, bz, bz_synth, cpu):
                         "and the 2^20-segment chain at 2^24 random T", "unit": "G evals/s", **res}
 
 
+def suite_particles(torch, bz, bz_synth, cpu):
+    """Sec. 5's particle test on MI355X: particles on a ring of 16 chained
+    cubics, one frame = phase update + position + a K-step consumer, for
+    1M / 5M / 10M particles and K = 0 / 64 / 256, each position method."""
+    log("suite: particle ring")
+    methods = ("polynomial", "seiler", "seiler_texture", "table")
+    res = {}
+    for n in (1_000_000, 5_000_000, 10_000_000):
+        seg, T, speed = bz_synth.particle_ring(n_particles=n)
+        seg_d, s_d = torch.from_numpy(seg).cuda(), torch.from_numpy(speed).cuda()
+        T_d = torch.from_numpy(T).cuda()
+        pos = torch.empty((3, n), device="cuda")
+        shade = torch.empty(n, device="cuda")
+        rings = {m: bz.particle_ring_data(seg_d, m, 64) for m in methods}
+        for K in (0, 64, 256):
+            row = {}
+            for m in methods:
+                ms = timed(lambda: bz.particles_step(m, rings[m], 16, T_d, s_d, 1 / 60, K, 64, pos, shade), torch)
+                row[m] = {"ms_per_frame": ms, "G particles/s": n / (ms * 1e-3) / 1e9}
+            # frame bytes: T read + written, speed read, 3 coordinates and the shade written
+            row["hbm_frac_polynomial"] = n * 24 / (row["polynomial"]["ms_per_frame"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+            # consumer: K FMAs = 2K flop per particle
+            row["consumer_alu_frac_polynomial"] = (2 * K * n / (row["polynomial"]["ms_per_frame"] * 1e-3) / 1e12
+                                                   / FP32_VALU_PEAK_TFLOPS)
+            res["%dM_K%d" % (n // 1_000_000, K)] = row
+    if cpu:
+        import oracle
+        seg, T, speed = bz_synth.particle_ring(n_particles=1 << 20)
+        _, sec, _ = oracle_timed(lambda: oracle.particles_step(seg, T, speed, 1 / 60, "polynomial", 64), 3.0)
+        res["cpu_baseline"] = {"value": (1 << 20) / sec / 1e9, "unit": "G particles/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "2^20 particles, one frame, polynomial, K = 64"}
+    return {"workload": "particle ring (16 chained cubic segments), one frame per launch: phase update, position "
+                        "by polynomial / Seiler terms / 8-bit Seiler texture emulation / 64-sample table, K-step "
+                        "consumer", "unit": "G particles/s", **res}
+
+
 def suite_fit(torch, bz, bz_synth, cpu):
     log("suite: fit")
     gt_ctrl, tau, eps = bz_synth.fit_problem()
@@ -510,7 +547,7 @@ def main():
     ap.add_argument("--n-q", type=int, default=1 << 24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
-    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit"], default=None,
+    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit", "particles"], default=None,
                     help="run one suite workload only (no headline) and print its record")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
                     help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
@@ -539,7 +576,7 @@ def main():
         return
     suites = {"plain": suite_plain, "cubic_chain": suite_cubic_chain, "texemu": suite_texemu,
               "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
-              "fit": suite_fit}
+              "fit": suite_fit, "particles": suite_particles}
     if args.suite_only:
         print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}), flush=True)
         return

@@ -368,6 +368,29 @@ int bz_batch_plan_info(bz_plan plan, int64_t *info4);
 int bz_plan_destroy(bz_plan plan);
 
 /*
+ * One frame of the particle ring (Sec. 5's particle test: particles moving
+ * along cubic Bezier curves chained into a closed ring, evaluated per
+ * particle per frame next to other shader work).  Per particle p:
+ *   T[p] <- T[p] + speed[p]*dt wrapped into [0, n_seg) (FP32, no contraction;
+ *   T in [0, n_seg) and |speed*dt| < n_seg), k = min(floor T, n_seg-1),
+ *   t = T - k; position pos[3][n_particles] from `ring` by method
+ *     0 polynomial: ring = control points [n_seg][3][4] (Bernstein form);
+ *     1 Seiler: ring = Seiler terms [n_seg][3][4] (bz_bezier_to_seiler);
+ *     2 Seiler texture: ring = Seiler textures [n_seg][3][4]
+ *       (bz_build_texture, BZ_TEX_SEILER) read through the emulated filter
+ *       with 8-bit nearest weights at (t, st);
+ *     3 sampled table: ring = [3][n_seg*samples] curve samples at segment
+ *       j / samples, local (j mod samples)/samples (bz_eval_bezier with
+ *       t_j = j/samples); x = T*samples, i = min(floor x, n_seg*samples-1),
+ *       lerp of samples i and i+1 (wrapping to sample 0) with x - i;
+ *   then shade[p] = v_K of v_0 = 0, v_{i+1} = fma(23/32, v_i, x/4 - y/8 + z/16)
+ *   (iters = K >= 0), a stand-in for the shader's other work.
+ * ring 16-byte aligned; T is updated in place.
+ */
+int bz_particles_step(int method, const float *ring, int64_t n_seg, int samples, float *T, const float *speed,
+                      float dt, int64_t n_particles, int iters, float *pos, float *shade, bz_stream stream);
+
+/*
  * Adjoint of curve evaluation (the derivative of Sec. 2's curves): given
  * grad_out[dim][n_curves*n_t] = dL/dC, writes (overwrites)
  *   grad_ctrl[n_curves][dim][degree+1]  dL/db_i = sum_j g_j w_i B_i(t_j)/W

@@ -68,6 +68,7 @@ _SIGS = {
     "bz_texture_patch_texels": (_I, [_I, _I, _I]),
     "bz_build_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
+    "bz_particles_step": (_I, [_I, _P, _I64, _I, _P, _P, _F, _I64, _I, _P, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -304,6 +305,31 @@ def eval_piecewise_cubic_tiled(tiles, n_seg, dim, T, out=None):
     out = _f32_out((dim, nq), tiles.device, out)
     check(lib().bz_eval_piecewise_cubic_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
     return out
+
+
+PARTICLE_METHODS = {"polynomial": 0, "seiler": 1, "seiler_texture": 2, "table": 3}
+
+
+def particle_ring_data(seg, method, samples=64):
+    """Device ring representation for a particle method from seg[N, 3, 4]."""
+    if method == "polynomial":
+        return seg.contiguous()
+    if method == "seiler":
+        return bezier_to_seiler(seg)
+    if method == "seiler_texture":
+        return build_texture(seg, "seiler")
+    t = torch.arange(samples, device=seg.device, dtype=torch.float32) / samples
+    return eval_bezier(seg, t)  # [3][N*samples]
+
+
+def particles_step(method, ring, n_seg, T, speed, dt, iters, samples=64, pos=None, shade=None):
+    """One frame: updates T in place, returns (pos[3, P], shade[P])."""
+    P = T.shape[0]
+    pos = _f32_out((3, P), T.device, pos)
+    shade = _f32_out((P,), T.device, shade)
+    check(lib().bz_particles_step(PARTICLE_METHODS[method], _ptr(ring), n_seg, samples, _ptr(T), _ptr(speed), dt, P,
+                                  iters, _ptr(pos), _ptr(shade), _stream()))
+    return pos, shade
 
 
 def tile_piecewise(grid, out=None):

@@ -23,7 +23,7 @@
 //
 // The weight decisions are FP32 with every operation rounded as written (no
 // contraction), so they match any other FP32 evaluation of the same rule.
-#include "curves_impl.h"
+#include "texfilter.h"
 
 namespace bzi {
 namespace {
@@ -34,32 +34,6 @@ constexpr int kTexMaxDegree = 8;
 template <int D, int MODE>
 constexpr int tex_texels() {
     return MODE == TX_SEILER ? (D <= 3 ? 4 : 8) : 4 * (D - 1);
-}
-
-// Fraction f in [0,1] held with F fractional bits: nearest with halves up
-// (rnd 0) or truncation (rnd 1); F = 0 leaves it unrounded.
-__device__ __forceinline__ float tx_round(float f, int F, int rnd) {
-#pragma clang fp contract(off)
-    if (F == 0) return f;
-    const float sc = __builtin_ldexpf(f, F);
-    const float q = rnd == 0 ? __builtin_floorf(sc + 0.5f) : __builtin_floorf(sc);
-    return __builtin_ldexpf(q, -F);
-}
-
-// Weight of a two-texel axis sampled at parameter p in [0,1].
-__device__ __forceinline__ float tx_axis_weight(float p, int F, int rnd) {
-#pragma clang fp contract(off)
-    const float x = 0.25f + 0.5f * p;  // normalised coordinate
-    const float xb = 2.0f * x - 0.5f;  // texel-space position, centres at 0 and 1
-    if (xb != xb) return xb;
-    if (xb <= 0.0f) return 0.0f;
-    if (xb >= 1.0f) return 1.0f;
-    return tx_round(xb, F, rnd);
-}
-
-// Bilinear blend of a 2x2 layer L[row*2 + col]: x along a row, y across rows.
-__device__ __forceinline__ float tx_bilinear(const float *L, float wx, float wy) {
-    return lerp(lerp(L[0], L[1], wx), lerp(L[2], L[3], wx), wy);
 }
 
 template <int D, int MODE>
