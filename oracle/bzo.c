@@ -998,6 +998,7 @@ void bzo_particles_step(const double *seg, int64_t nseg, int method, int samples
         T[p] = Tn;
         int64_t k = (int64_t)floorf(Tn);
         if (k > nseg - 1) k = nseg - 1;
+        if (k < 0) k = 0; /* only for |speed dt| >= N, outside the documented domain */
         const float t = Tn - (float)k;
         double xyz[3];
         for (int c = 0; c < 3; ++c) {
@@ -1013,6 +1014,7 @@ void bzo_particles_step(const double *seg, int64_t nseg, int method, int samples
                 const float x = Tn * (float)samples;
                 int64_t i = (int64_t)floorf(x);
                 if (i > ntab - 1) i = ntab - 1;
+                if (i < 0) i = 0;
                 const float f = x - (float)i;
                 const int64_t i1 = (i + 1) % ntab;
                 const double c0 = ring_point(seg, i / samples, c, (double)(i % samples) / samples);
