@@ -408,7 +408,9 @@ int bz_adjoint_bezier(const float *ctrl, const float *w, int64_t n_curves, int d
  * One fused least-squares fitting step for integral curves with per-curve
  * parameters: loss L = (1/M) sum_q |C(t_q) - y_q|^2 (M = n_curves*n_t), its
  * gradients by the adjoint above, and an Adam update (bias-corrected, step
- * counted from 1) of ctrl and t in place, t clamped to [0,1].
+ * counted from 1; bias corrections applied as FP64-computed reciprocals, the
+ * square root and the final reciprocal by the hardware approximations, about
+ * 1 ulp) of ctrl and t in place, t clamped to [0,1].
  * y: [dim][n_curves*n_t].  m_*, v_*: Adam moments, same shapes as ctrl / t.
  * loss_part (nullable): [n_curves] per-curve contributions to L before the
  * update.  Requires n_t <= 1024.

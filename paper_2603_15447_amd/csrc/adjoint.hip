@@ -171,23 +171,28 @@ struct FitArgs {
     float *loss_part;
     int64_t n_curves, n_t, plane;
     float inv_m;        // 1 / (n_curves * n_t)
-    float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^step, c2 = 1 - b2^step
+    float lr, b1, b2, eps;
+    float ic1, ic2;  // 1 / (1 - b1^step), 1 / (1 - b2^step), rounded once from FP64
 };
 
-// Adam update (bias corrections c1 = 1 - b1^step, c2 = 1 - b2^step); every
-// rounding step is written out so that all kernels produce identical bits.
-__device__ __forceinline__ float adam_c(float p, float g, float *m, float *v, const FitArgs &a, float c1, float c2) {
+// Adam update with the bias corrections as multiplications by host-side
+// reciprocals and the hardware square root and reciprocal (v_sqrt_f32,
+// v_rcp_f32, about 1 ulp) instead of correctly rounded division and square
+// root sequences: the update is a heuristic step, and the IEEE sequences cost
+// a third of the fitting step's instructions.  Every rounding step is written
+// out so that all kernels produce identical bits.
+__device__ __forceinline__ float adam_c(float p, float g, float *m, float *v, const FitArgs &a, float ic1, float ic2) {
     const float mm = __builtin_fmaf(a.b1, *m, (1.0f - a.b1) * g);
     const float vv = __builtin_fmaf(a.b2, *v, ((1.0f - a.b2) * g) * g);
     *m = mm;
     *v = vv;
-    const float mh = mm / c1, vh = vv / c2;
-    const float upd = mh / (__builtin_sqrtf(vh) + a.eps);
+    const float mh = mm * ic1, vh = vv * ic2;
+    const float upd = mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + a.eps);
     return __builtin_fmaf(-a.lr, upd, p);
 }
 
 __device__ __forceinline__ float adam(float p, float g, float *m, float *v, const FitArgs &a) {
-    return adam_c(p, g, m, v, a, a.c1, a.c2);
+    return adam_c(p, g, m, v, a, a.ic1, a.ic2);
 }
 
 // Fused step: L = (1/M) sum |C(t) - y|^2, gradients, Adam on t (clamped to
@@ -268,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
 // a wavefront can keep its curves' samples, parameters and Adam moments in
 // registers across all steps: HBM is read once and written once.  Each step
 // performs exactly the arithmetic of k_fit_step, in the same order.  SPL:
-// samples per lane (n_t <= SPL * lanes per curve).  bias[step] = (c1, c2).
+// samples per lane (n_t <= SPL * lanes per curve).  bias[step] = (ic1, ic2).
 template <int D, int DIM, int SPL>
 __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__restrict__ bias, int n_steps) {
     constexpr int NP = DIM * (D + 1);
@@ -501,8 +506,8 @@ FitArgs make_fit_args(float *ctrl, float *t, const float *y, int64_t n_curves, i
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;
-    a.c1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
-    a.c2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+    a.ic1 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta1), step)));
+    a.ic2 = static_cast<float>(1.0 / (1.0 - std::pow(static_cast<double>(beta2), step)));
     return a;
 }
 
@@ -565,8 +570,8 @@ int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int
             for (int i = 0; i < n_steps; ++i) {
                 const FitArgs ai = make_fit_args(ctrl, t, y, n_curves, n_t, m_ctrl, v_ctrl, m_t, v_t, first_step + i,
                                                  lr, beta1, beta2, eps, loss_part);
-                tab[2 * i] = ai.c1;
-                tab[2 * i + 1] = ai.c2;
+                tab[2 * i] = ai.ic1;
+                tab[2 * i + 1] = ai.ic2;
             }
             float2 *bias = nullptr;
             hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&bias), tab.size() * sizeof(float), s);
