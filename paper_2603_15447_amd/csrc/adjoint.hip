@@ -50,6 +50,67 @@ __device__ __forceinline__ float half_sum(float v) {
     return (threadIdx.x & 32) ? hi : lo;
 }
 
+// Exchange with lane ^ D inside each 32-lane half: DPP for D = 1, 2 (quad
+// permutations), ds_swizzle in xor mode (and-mask 31) for D = 4..16.
+template <int D>
+__device__ __forceinline__ float xor_lane(float v) {
+    if constexpr (D == 1) return dpp_mov<0xB1>(v);
+    else if constexpr (D == 2) return dpp_mov<0x4E>(v);
+    else return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), (D << 10) | 0x1F));
+}
+
+// Reduce-scatter over a 32-lane half: NV values per lane in, and lane l of
+// the half leaves with the half's sum of value l mod NV (NV = 16 or 32).  At
+// each exchange a lane keeps the half of its values selected by one bit of
+// its index (most significant first) and adds its partner's copy of that
+// half, so the work halves with every exchange.
+template <int NV, int D = NV / 2>
+__device__ __forceinline__ void reduce_scatter_level(float (&v)[NV], int sub) {
+    if constexpr (D >= 1) {
+        const bool hi = (sub & D) != 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float lo_v = v[j], hi_v = v[j + D];
+            v[j] = (hi ? hi_v : lo_v) + xor_lane<D>(hi ? lo_v : hi_v);
+        }
+        reduce_scatter_level<NV, D / 2>(v, sub);
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ float reduce_scatter32(float (&v)[NV], int sub) {
+    reduce_scatter_level<NV>(v, sub);
+    float r = v[0];
+    if constexpr (NV == 16) r += xor_lane<16>(r);
+    return r;
+}
+
+// Per-curve sums of the gradient partials gb[k][i], delivered to the lane
+// that owns parameter sub = k*(D+1)+i (lanes past NP get unused values).
+// Two curves per wavefront: reduce-scatter in each half; one curve: one
+// wave sum per parameter.
+template <int D, int DIM, int CPW>
+__device__ __forceinline__ float reduce_grads(const float (&gb)[DIM][D + 1], int sub) {
+    constexpr int NP = DIM * (D + 1);
+    if constexpr (CPW == 2) {
+        constexpr int NV = NP <= 16 ? 16 : 32;
+        float v[NV];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) v[e] = e < NP ? gb[e / (D + 1)][e % (D + 1)] : 0.0f;
+        return reduce_scatter32<NV>(v, sub);
+    } else {
+        float mine = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+            for (int i = 0; i <= D; ++i) {
+                const float v = wave_sum(gb[k][i]);
+                if (sub == k * (D + 1) + i) mine = v;
+            }
+        return mine;
+    }
+}
+
 struct AdjArgs {
     const float *ctrl;
     const float *w;
@@ -253,14 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
     }
     loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
     if (a.loss_part && sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
-    float mine = 0.0f;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int i = 0; i <= D; ++i) {
-            const float v = CPW == 2 ? half_sum(gb[k][i]) : wave_sum(gb[k][i]);
-            if (sub == k * (D + 1) + i) mine = v;
-        }
+    const float mine = reduce_grads<D, DIM, CPW>(gb, sub);
     if (sub < NP && live) {
         const float pn = adam(p_own, mine, &m_own, &v_own, a);
         a.ctrl[pidx] = pn;
@@ -337,14 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__r
             ts[s] = tn < 0.0f ? 0.0f : (tn > 1.0f ? 1.0f : tn);
         }
         loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
-        float mine = 0.0f;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-#pragma unroll
-            for (int i = 0; i <= D; ++i) {
-                const float v = CPW == 2 ? half_sum(gb[k][i]) : wave_sum(gb[k][i]);
-                if (sub == k * (D + 1) + i) mine = v;
-            }
+        const float mine = reduce_grads<D, DIM, CPW>(gb, sub);
         if (sub < NP && live) p_own = adam_c(p_own, mine, &m_own, &v_own, a, bc.x, bc.y);
     }
     if (a.loss_part && sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
