@@ -85,3 +85,62 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(bz, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         bz.lib()
+
+
+def test_cubic_chain_errors(L):
+    assert L.bz_encode_piecewise_cubic(None, 0, 3, None, None) == bz.OK
+    assert L.bz_encode_piecewise_cubic(FAKE, 4, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_encode_piecewise_cubic(None, 4, 3, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_piecewise_cubic(FAKE, 0, 3, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_cubic(FAKE + 8, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_cubic(FAKE, 4, 3, FAKE, 0, FAKE, None) == bz.OK
+    assert L.bz_piecewise_cubic_tiled_floats(1000, 3) == 500 * 32  # 2 segments per 128-byte tile in 3D
+    assert L.bz_piecewise_cubic_tiled_floats(9, 1) == 32 and L.bz_piecewise_cubic_tiled_floats(0, 3) == 0
+    assert L.bz_tile_piecewise_cubic(FAKE, 4, 3, FAKE + 4, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_cubic_tiled(FAKE, 4, 7, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_piecewise_tiled_floats(1 << 20, 3) == (1 << 18) * 32  # 4 segments per tile
+
+
+def test_texture_errors(L):
+    assert [L.bz_texture_texels(d, 0) for d in (1, 2, 3, 8, 9)] == [0, 4, 8, 28, 0]
+    assert [L.bz_texture_texels(d, 2) for d in (1, 2, 3, 4, 7, 8)] == [0, 4, 4, 8, 8, 0]
+    assert L.bz_texture_texels(3, 5) == 0
+    assert L.bz_build_texture(FAKE, 4, 8, 3, 2, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_build_texture(FAKE, 4, 3, 3, 0, FAKE + 4, None) == bz.ERR_ALIGN
+    assert L.bz_eval_texture(FAKE, 4, 3, 3, 0, FAKE, 8, 0, 21, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_texture(FAKE, 4, 3, 3, 0, FAKE, 8, 0, 8, 2, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_texture(FAKE, 4, 3, 3, 1, FAKE, 8, 3, 8, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_texture(None, 4, 3, 3, 1, FAKE, 8, 0, 8, 0, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_piecewise_texemu(FAKE, 1 << 25, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_texemu(FAKE + 4, 4, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_texture_patch_texels(3, 3, 0) == 32 and L.bz_texture_patch_texels(2, 4, 2) == 20
+    assert L.bz_texture_patch_texels(4, 3, 0) == 0 and L.bz_texture_patch_texels(3, 3, 1) == 0
+    assert L.bz_build_texture_patch(FAKE, 4, 3, 5, 3, 2, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_eval_texture_patch(FAKE, 4, 3, 3, 3, 2, FAKE + 4, 8, 8, 0, FAKE, None) == bz.ERR_ALIGN
+
+
+def test_tensor_seiler_and_patch_errors(L):
+    assert L.bz_tensor_to_seiler(FAKE, 4, 5, 3, 0, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_tensor_to_seiler(None, 0, 3, 3, 0, 3, None, None) == bz.OK
+    assert L.bz_eval_tensor_seiler(FAKE, 4, 3, 3, 1, 3, None, 0, 32, 32, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_eval_tensor_seiler(FAKE, 4, 3, 3, 0, 3, None, 0, 0, 32, FAKE, None) == bz.ERR_SHAPE
+    # MFMA engines: bicubic FP32 on 32x32 only; FP16x3 is engine 4, 5 is unknown
+    assert L.bz_eval_tensor_patch(FAKE, 0, 4, 3, 3, 0, 3, None, 0, 16, 16, 4, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_eval_tensor_patch(FAKE, 0, 4, 3, 3, 0, 3, None, 0, 32, 32, 5, FAKE, None) == bz.ERR_UNSUPPORTED
+
+
+def test_particles_probe_and_plan_errors(L):
+    assert L.bz_particles_step(4, FAKE, 16, 64, FAKE, FAKE, ctypes.c_float(0.01), 8, 0, FAKE, FAKE, None) \
+        == bz.ERR_UNSUPPORTED
+    assert L.bz_particles_step(3, FAKE, 16, 0, FAKE, FAKE, ctypes.c_float(0.01), 8, 0, FAKE, FAKE, None) \
+        == bz.ERR_SHAPE
+    assert L.bz_particles_step(0, FAKE + 4, 16, 64, FAKE, FAKE, ctypes.c_float(0.01), 8, 0, FAKE, FAKE, None) \
+        == bz.ERR_ALIGN
+    assert L.bz_particles_step(0, FAKE, 16, 64, FAKE, FAKE, ctypes.c_float(0.01), 0, 0, None, None, None) == bz.OK
+    assert L.bz_hbm_probe(3, FAKE, FAKE, 16, 4, None) == bz.ERR_SHAPE
+    assert L.bz_hbm_probe(2, FAKE, FAKE, 6, 4, None) == bz.ERR_SHAPE
+    assert L.bz_hbm_probe(2, FAKE, FAKE, 16, 0, None) == bz.ERR_SHAPE
+    assert L.bz_hbm_probe(1, None, FAKE + 4, 16, 4, None) == bz.ERR_ALIGN
+    assert L.bz_batch_plan_configure(None, 64, 1, 1, 1, None) == bz.ERR_NULL
+    assert L.bz_batch_plan_autotune(None, FAKE, FAKE, None, None) == bz.ERR_NULL
+    assert L.bz_batch_eval(None, FAKE, FAKE, None) == bz.ERR_NULL
