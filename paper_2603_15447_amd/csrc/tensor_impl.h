@@ -135,10 +135,15 @@ __global__ __launch_bounds__(kBlock) void k_tensor_points(const T *__restrict__ 
             if constexpr (DW > 0) basis_at<DW, BASIS>(p[2], Bw[s]);
             else Bw[s][0] = 1.0f;
         }
+        // One (coordinate, i) slab of (DV+1)(DW+1) coefficients at a time: the
+        // slab loop is not unrolled, so the scalar loads of one slab are in
+        // flight while the previous slab's FMAs run, and the coefficients never
+        // outnumber the scalar registers (a fully unrolled nest would hoist all
+        // DIM * NCP loads and spill them into vector-register lanes).
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             float acc[kPtsQ] = {};
-#pragma unroll
+#pragma unroll 1
             for (int i = 0; i <= DU; ++i) {
                 float Ri[kPtsQ] = {};
 #pragma unroll
