@@ -87,18 +87,19 @@ __device__ __forceinline__ void eval_curve_query(const T *__restrict__ P, const 
 #pragma unroll
             for (int i = 1; i <= D; ++i) den += B[i];
         }
+        const float rden = RAT ? 1.0f / den : 1.0f;  // one division per query, not per coordinate
 #pragma unroll
         for (int k = 0; k < kMaxDim; ++k) {
             if (k < dim) {
                 float b[D + 1];
                 load_row<T, D + 1>(P + k * (D + 1), b);
                 const float v = dot_basis<D>(B, b);
-                st_stream(out + k * plane + q, RAT ? v / den : v);
+                st_stream(out + k * plane + q, RAT ? v * rden : v);
             }
         }
     } else {
-        float den = 1.0f;
-        if constexpr (RAT) den = eval_dc<D>(wv, t);
+        float rden = 1.0f;
+        if constexpr (RAT) rden = 1.0f / eval_dc<D>(wv, t);
 #pragma unroll
         for (int k = 0; k < kMaxDim; ++k) {
             if (k < dim) {
@@ -109,7 +110,7 @@ __device__ __forceinline__ void eval_curve_query(const T *__restrict__ P, const 
                     for (int i = 0; i <= D; ++i) b[i] *= wv[i];
                 }
                 const float v = eval_dc<D>(b, t);
-                st_stream(out + k * plane + q, RAT ? v / den : v);
+                st_stream(out + k * plane + q, RAT ? v * rden : v);
             }
         }
     }
@@ -127,7 +128,7 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
     float wv[D + 1];
     if constexpr (RAT) load_row<T, D + 1>(W, wv);
     if constexpr (F == FORM_BERN) {
-        float B[4][D + 1], den[4];
+        float B[4][D + 1], den[4];  // den: reciprocal of the weight sum (rational)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             bernstein_basis<D>(t[i], B[i]);
@@ -138,6 +139,7 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
                 den[i] = B[i][0];
 #pragma unroll
                 for (int e = 1; e <= D; ++e) den[i] += B[i][e];
+                den[i] = 1.0f / den[i];  // reciprocal: one division per query
             }
         }
 #pragma unroll
@@ -149,16 +151,16 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float x = dot_basis<D>(B[i], b);
-                    v[i] = RAT ? x / den[i] : x;
+                    v[i] = RAT ? x * den[i] : x;
                 }
                 __builtin_nontemporal_store(v, reinterpret_cast<f4u *>(out + k * plane + q));
             }
         }
     } else {
-        float den[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+        float den[4] = {1.0f, 1.0f, 1.0f, 1.0f};  // reciprocals of the weight sums
         if constexpr (RAT) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) den[i] = eval_dc<D>(wv, t[i]);
+            for (int i = 0; i < 4; ++i) den[i] = 1.0f / eval_dc<D>(wv, t[i]);  // reciprocals
         }
 #pragma unroll
         for (int k = 0; k < kMaxDim; ++k) {
@@ -173,7 +175,7 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float x = eval_dc<D>(b, t[i]);
-                    v[i] = RAT ? x / den[i] : x;
+                    v[i] = RAT ? x * den[i] : x;
                 }
                 __builtin_nontemporal_store(v, reinterpret_cast<f4u *>(out + k * plane + q));
             }
@@ -205,9 +207,10 @@ __device__ __forceinline__ void eval_nurbs_query(const float *__restrict__ brk, 
 #pragma unroll
         for (int k = 0; k <= kMaxDim; ++k)
             if (k <= dim) H[k] = __builtin_fmaf(B[i], S[i * (dim + 1) + k], H[k]);
+    const float rw = 1.0f / H[dim];
 #pragma unroll
     for (int k = 0; k < kMaxDim; ++k)
-        if (k < dim) st_stream(out + k * plane + q, H[k] / H[dim]);
+        if (k < dim) st_stream(out + k * plane + q, H[k] * rw);
 }
 
 constexpr int kMaxQpt = 4;
@@ -345,8 +348,13 @@ __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) 
 // index is fetched while the current tile is evaluated).  Static schedule:
 // workgroup g takes tiles g, g+G, g+2G, ... -- balanced because tiles are
 // ordered by cost and every tile of a class costs the same.
+// FP32 storage with four queries per lane runs at four waves per SIMD (the
+// register budget then spills a few dwords on the degree-15 path; measured
+// faster than three waves without spills); FP16/BF16 storage is faster at the
+// compiler's own choice.
 template <int F, typename T, int VQ>
-__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchArgs a) {
+__global__ __launch_bounds__(kBlock, (VQ == 4 && std::is_same<T, float>::value) ? 4 : 1) void k_batch_persistent(
+    BatchArgs a) {
     if (!a.dynamic) {
         for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T, VQ>(a, tile);
         return;
