@@ -163,6 +163,49 @@ def hbm_probe(torch, bz, mib=1024, iters=10):
     return res
 
 
+def gather_ceiling(torch, bz, buf, n_reads, kern_ms, iters=20):
+    """The measured ceiling of the chain query's access pattern: as many
+    reads of 48 contiguous bytes at the start of uniformly random 128-byte
+    lines of `buf` (the tiled grid itself, so the footprint is the grid's) as
+    the chain has queries, and the evaluator's query rate as a fraction of
+    that line rate."""
+    sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
+    fn = lambda: bz.gather_probe(buf, n_reads, 3, sink)
+    for _ in range(3):
+        fn()
+    ms = event_time_ms(fn, iters, torch)
+    rate = n_reads / (ms * 1e-3) / 1e9
+    return {"G_lines/s": rate, "footprint_MB": buf.numel() * 4 / 1e6, "bytes_per_read": 48, "probe_ms": ms,
+            "evaluator_frac": (n_reads / (kern_ms * 1e-3) / 1e9) / rate}
+
+
+def suite_chain_footprint(torch, bz, bz_synth, cpu):
+    """The tiled chain evaluator and the random-line gather probe over chains
+    of 2^15 .. 2^23 segments (tiled grid 1 MB .. 268 MB) at 2^24 queries: where
+    the grid leaves an XCD's 4 MB L2 and the 256 MB Infinity Cache."""
+    log("suite: chain footprint sweep")
+    n_q, dim = 1 << 24, 3
+    rows = []
+    for lg in range(15, 24):
+        n_seg = 1 << lg
+        chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=n_q)
+        chain_d, T_d = torch.from_numpy(chain).cuda(), torch.from_numpy(T).cuda()
+        tiles = bz.tile_piecewise(bz.encode_piecewise(chain_d))
+        out = torch.empty((dim, n_q), dtype=torch.float32, device="cuda")
+        fn = lambda: bz.eval_piecewise_tiled(tiles, n_seg, dim, T_d, out=out)
+        for _ in range(3):
+            fn()
+        ms = event_time_ms(fn, 20, torch)
+        g = gather_ceiling(torch, bz, tiles, n_q, ms)
+        rows.append({"n_seg": n_seg, "tiled_MB": g["footprint_MB"], "kernel_ms": ms,
+                     "G evals/s": n_q / (ms * 1e-3) / 1e9, "gather_G_lines/s": g["G_lines/s"],
+                     "frac_of_gather": g["evaluator_frac"],
+                     "hbm_frac": hbm_roof(chain_bytes(n_seg, dim, n_q), ms)["frac"]})
+        del chain_d, T_d, tiles, out
+    return {"workload": "C0 quadratic chain (tiled), 2^15..2^23 segments, 2^24 uniform random global T, 3D, FP32",
+            "unit": "G evals/s", "rows": rows}
+
+
 # ---------------------------------------------------------------- headline
 def cpu_baseline_chain(chain, T, out_dev, budget_s=10.0):
     """CPU-baseline leg: the oracle's chain definition on the first 4M queries,
@@ -582,7 +625,7 @@ def main():
     ap.add_argument("--n-q", type=int, default=1 << 24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--no-suite", action="store_true", help="headline workload only")
-    ap.add_argument("--suite-only", choices=["plain", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit", "particles"], default=None,
+    ap.add_argument("--suite-only", choices=["plain", "chain_footprint", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit", "particles"], default=None,
                     help="run one suite workload only (no headline) and print its record")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
                     help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
@@ -609,7 +652,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
         return
-    suites = {"plain": suite_plain, "cubic_chain": suite_cubic_chain, "texemu": suite_texemu,
+    suites = {"plain": suite_plain, "chain_footprint": suite_chain_footprint, "cubic_chain": suite_cubic_chain, "texemu": suite_texemu,
               "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
               "fit": suite_fit, "particles": suite_particles}
     if args.suite_only:
@@ -674,6 +717,8 @@ def main():
     probe = hbm_probe(torch, bz)
     probe["headline_frac_of_read"] = roof["achieved"] / probe["read_GB/s"]
     rec["hbm_probe"] = probe
+    if args.layout == "tiled":
+        rec["gather_ceiling"] = gather_ceiling(torch, bz, tiles, args.n_q, kern_ms)
     if roof["traffic"]:
         # the bytes the gather actually moves (one 128-byte line per query)
         rate = roof["traffic"] / (kern_ms * 1e-3) / 1e9

@@ -87,6 +87,19 @@ int bz_device_cu_count(void);
 int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, int blocks_per_cu, bz_stream stream);
 
 /*
+ * Random-line gather ceiling, the access pattern of a chain query (Sec. 2.1:
+ * one filtered read per query at an arbitrary position along the zig-zag
+ * grid; with the grid in 128-byte tiles that is one line): n_reads reads, read r loading
+ * vec16 (1..4) consecutive 16-byte vectors from the start of line
+ * floor(h(r) * n_lines / 2^32) of src, h the lowbias32 hash of
+ * r * 0x9e3779b9 + 12345 and n_lines = n / 32.  src: n floats (a multiple of
+ * 32 below 2^37), 128-byte aligned, device.  sink: one device float, written
+ * only if a thread's partial sum equals -1 (never for non-negative data).
+ * n_reads 0..2^31-1; 0 launches nothing.  Timing is the caller's.
+ */
+int bz_gather_probe(const float *src, int64_t n, int64_t n_reads, int vec16, float *sink, bz_stream stream);
+
+/*
  * Bezier curves (Sec. 2: de Casteljau recursive lerps; Sec. 3: Seiler
  * interpolation; Sec. 5: the Bernstein polynomial form).
  * ctrl: [n_curves][dim][degree+1] in ctrl_dtype.  t: see t_mode.

@@ -62,6 +62,7 @@ _SIGS = {
     "bz_tensor_to_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_tensor_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_hbm_probe": (_I, [_I, _P, _P, _I64, _I, _P]),
+    "bz_gather_probe": (_I, [_P, _I64, _I64, _I, _P, _P]),
     "bz_piecewise_cubic_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_cubic_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -234,6 +235,12 @@ def hbm_probe(mode, src, dst, blocks_per_cu=4):
     """One streaming pass (mode "read", "write" or "copy") over float32 buffers."""
     m = {"read": 0, "write": 1, "copy": 2}[mode]
     check(lib().bz_hbm_probe(m, _ptr(src), _ptr(dst), dst.numel() if m else src.numel(), blocks_per_cu, _stream()))
+
+
+def gather_probe(src, n_reads, vec16, sink):
+    """n_reads random 128-byte-line reads of vec16 16-byte vectors from the
+    float32 buffer src (the chain query's access pattern)."""
+    check(lib().bz_gather_probe(_ptr(src), src.numel(), n_reads, vec16, _ptr(sink), _stream()))
 
 
 def texture_texels(degree, mode):

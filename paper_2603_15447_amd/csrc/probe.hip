@@ -36,10 +36,76 @@ __global__ __launch_bounds__(kBlock) void k_probe_copy(const v4f *__restrict__ s
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// lowbias32, a 32-bit integer finaliser published by C. Wellons (hash-prospector):
+// two xorshift-multiply rounds and a final xorshift.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Read r (r < n_reads) loads NV consecutive 16-byte vectors from the start of
+// line floor(h(r) * n_lines / 2^32); four reads per thread, all issued before
+// any is consumed, as in the chain evaluator.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_probe_gather(const v4f *__restrict__ src, uint32_t n_lines,
+                                                         uint32_t n_reads, float *__restrict__ sink) {
+    constexpr int QPT = 4;
+    const uint32_t base = blockIdx.x * (kBlock * QPT) + threadIdx.x;
+    v4f v[QPT][NV];
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+        const uint32_t r = min(base + i * kBlock, n_reads - 1);
+        const uint32_t h = lowbias32(r * 0x9e3779b9u + 0x3039u);
+        const uint32_t line = static_cast<uint32_t>((static_cast<uint64_t>(h) * n_lines) >> 32);
+        const v4f *p = src + static_cast<size_t>(line) * 8;
+#pragma unroll
+        for (int e = 0; e < NV; ++e) v[i][e] = p[e];
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+        for (int e = 0; e < NV; ++e) acc += v[i][e].x + v[i][e].w;
+    if (acc == -1.0f) sink[0] = acc;  // never true for non-negative data
+}
+
 }  // namespace
 }  // namespace bzi
 
 using namespace bzi;
+
+extern "C" int bz_gather_probe(const float *src, int64_t n, int64_t n_reads, int vec16, float *sink,
+                               bz_stream stream) {
+    return guarded("bz_gather_probe", [&]() -> int {
+        const char *fn = "bz_gather_probe";
+        if (vec16 < 1 || vec16 > 4) return fail(BZ_ERR_SHAPE, "%s: vec16 %d not in 1..4", fn, vec16);
+        if (n < 0 || n % 32 != 0 || n / 32 > 0xffffffffll)
+            return fail(BZ_ERR_SHAPE, "%s: n %lld not a multiple of 32 floats (one line) below 2^37", fn,
+                        (long long)n);
+        if (n_reads < 0 || n_reads > 0x7fffffffll) return fail(BZ_ERR_SHAPE, "%s: n_reads not in 0..2^31-1", fn);
+        if (n_reads == 0) return BZ_OK;
+        if (n == 0) return fail(BZ_ERR_SHAPE, "%s: reads from an empty buffer", fn);
+        if (!src || !sink) return fail(BZ_ERR_NULL, "%s: src and sink are required", fn);
+        if (!aligned(src, 128) || !aligned(sink, 4)) return fail(BZ_ERR_ALIGN, "%s: src needs 128-byte alignment", fn);
+        const hipStream_t s = as_stream(stream);
+        const uint32_t nl = static_cast<uint32_t>(n / 32), nr = static_cast<uint32_t>(n_reads);
+        const uint32_t per_block = kBlock * 4;
+        const dim3 grid((nr + per_block - 1) / per_block);
+        const v4f *p = reinterpret_cast<const v4f *>(src);
+        switch (vec16) {
+            case 1: hipLaunchKernelGGL(k_probe_gather<1>, grid, dim3(kBlock), 0, s, p, nl, nr, sink); break;
+            case 2: hipLaunchKernelGGL(k_probe_gather<2>, grid, dim3(kBlock), 0, s, p, nl, nr, sink); break;
+            case 3: hipLaunchKernelGGL(k_probe_gather<3>, grid, dim3(kBlock), 0, s, p, nl, nr, sink); break;
+            default: hipLaunchKernelGGL(k_probe_gather<4>, grid, dim3(kBlock), 0, s, p, nl, nr, sink); break;
+        }
+        BZ_CHECK_LAUNCH("k_probe_gather");
+        return BZ_OK;
+    });
+}
 
 extern "C" int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, int blocks_per_cu, bz_stream stream) {
     return guarded("bz_hbm_probe", [&]() -> int {

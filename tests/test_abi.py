@@ -141,6 +141,14 @@ def test_particles_probe_and_plan_errors(L):
     assert L.bz_hbm_probe(2, FAKE, FAKE, 6, 4, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(2, FAKE, FAKE, 16, 0, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(1, None, FAKE + 4, 16, 4, None) == bz.ERR_ALIGN
+    assert L.bz_gather_probe(FAKE, 64, 8, 5, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_gather_probe(FAKE, 48, 8, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_gather_probe(FAKE, 0, 8, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_gather_probe(FAKE, 64, -1, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_gather_probe(FAKE, 64, 1 << 31, 3, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_gather_probe(None, 64, 8, 3, FAKE, None) == bz.ERR_NULL
+    assert L.bz_gather_probe(FAKE + 64, 64, 8, 3, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_gather_probe(FAKE, 64, 0, 3, None, None) == bz.OK
     assert L.bz_batch_plan_configure(None, 64, 1, 1, 1, None) == bz.ERR_NULL
     assert L.bz_batch_plan_autotune(None, FAKE, FAKE, None, None) == bz.ERR_NULL
     assert L.bz_batch_eval(None, FAKE, FAKE, None) == bz.ERR_NULL

@@ -23,3 +23,13 @@ def test_probe_modes():
     with pytest.raises(bz.BzError) as e:
         bz.check(bz.lib().bz_hbm_probe(2, src.data_ptr(), dst.data_ptr(), 6, 4, None))
     assert e.value.code == bz.ERR_SHAPE
+
+
+@pytest.mark.parametrize("vec16", [1, 2, 3, 4])
+def test_gather_probe(vec16):
+    n_lines = 1000  # not a power of two: the line map is a multiply-high, not a mask
+    src = torch.ones(n_lines * 32, dtype=torch.float32, device="cuda")
+    sink = torch.full((1,), 7.0, dtype=torch.float32, device="cuda")
+    bz.gather_probe(src, (1 << 16) + 5, vec16, sink)  # ragged last block
+    torch.cuda.synchronize()
+    assert float(sink[0]) == 7.0  # non-negative data: never written
