@@ -52,17 +52,19 @@ def chain_bytes(n_seg, dim, n_q):
     return (n_seg + 1) * 2 * dim * 4 + n_q * 4 + n_q * dim * 4
 
 
-def recorded_traffic(name):
+def recorded_traffic(name, n_seg, n_q):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source has changed since the counters were taken."""
+    None when the kernel source has changed since the counters were taken or
+    the workload is not the one they were taken on."""
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
         with open(os.path.join(ROOT, d["kernel_source"]), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
+        same = sha == d["kernel_source_sha256"] and (d["n_seg"], d["n_q"]) == (n_seg, n_q)
     except (OSError, KeyError, ValueError):
         return None
-    return d["traffic_bytes_per_dispatch"] if sha == d["kernel_source_sha256"] else None
+    return d["traffic_bytes_per_dispatch"] if same else None
 
 
 def event_time_ms(fn, iters, torch):
@@ -163,19 +165,19 @@ def hbm_probe(torch, bz, mib=1024, iters=10):
     return res
 
 
-def gather_ceiling(torch, bz, buf, n_reads, kern_ms, iters=20):
+def gather_ceiling(torch, bz, buf, n_reads, kern_ms, vec16=3, iters=20):
     """The measured ceiling of the chain query's access pattern: as many
-    reads of 48 contiguous bytes at the start of uniformly random 128-byte
-    lines of `buf` (the tiled grid itself, so the footprint is the grid's) as
-    the chain has queries, and the evaluator's query rate as a fraction of
-    that line rate."""
+    reads of 16*vec16 contiguous bytes at the start of uniformly random
+    128-byte lines of `buf` (the tiled grid itself, so the footprint is the
+    grid's) as the chain has queries, and the evaluator's query rate as a
+    fraction of that line rate."""
     sink = torch.zeros(1, dtype=torch.float32, device=buf.device)
-    fn = lambda: bz.gather_probe(buf, n_reads, 3, sink)
+    fn = lambda: bz.gather_probe(buf, n_reads, vec16, sink)
     for _ in range(3):
         fn()
     ms = event_time_ms(fn, iters, torch)
     rate = n_reads / (ms * 1e-3) / 1e9
-    return {"G_lines/s": rate, "footprint_MB": buf.numel() * 4 / 1e6, "bytes_per_read": 48, "probe_ms": ms,
+    return {"G_lines/s": rate, "footprint_MB": buf.numel() * 4 / 1e6, "bytes_per_read": 16 * vec16, "probe_ms": ms,
             "evaluator_frac": (n_reads / (kern_ms * 1e-3) / 1e9) / rate}
 
 
@@ -415,7 +417,9 @@ def suite_cubic_chain(torch, bz, bz_synth, cpu):
     res = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms), "layout": "tiled",
            "algorithmic_bytes": nbytes, "encode_ms": enc_ms,
            "grid_layout": {"kernel_ms": ms_grid, "value": n_q / (ms_grid * 1e-3) / 1e9,
-                           "roofline": hbm_roof(nbytes, ms_grid)}}
+                           "roofline": hbm_roof(nbytes, ms_grid)},
+           # a query's 72-byte window lies in one line; the probe reads 64 of them
+           "gather_ceiling": gather_ceiling(torch, bz, tiles, n_q, ms, vec16=4)}
     if cpu:
         import oracle
         m = 1 << 22
@@ -690,7 +694,7 @@ def main():
 
     nbytes = chain_bytes(args.n_seg, dim, args.n_q)
     roof = hbm_roof(nbytes, kern_ms)
-    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout])
+    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout], args.n_seg, args.n_q)
     rec = {
         "metric": METRIC,
         "value": args.n_q / (ms_per_step * 1e-3) / 1e9,

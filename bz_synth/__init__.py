@@ -169,7 +169,8 @@ def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_
     for o in nurbs_objs:
         a, b = knot_offset[o], knot_offset[o + 1]
         k = b - a
-        v = np.sort(inner[a:a + k - 8])
+        # interior knots strictly inside (0, 1) also after rounding to FP32
+        v = np.clip(np.sort(inner[a:a + k - 8]), np.finfo(np.float32).tiny, np.nextafter(np.float32(1), np.float32(0)))
         knots[a:a + 4] = 0.0
         knots[a + 4:b - 4] = v
         knots[b - 4:b] = 1.0

@@ -361,8 +361,10 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
  * query per lane, or -- when n_t is a multiple of 4 -- four consecutive
  * parameters of one object per lane) x 3 tile sizes (1, 2 or 4 sub-tiles of
  * 256 lanes per tile) x 2 schedules (atomic tile counter, static round
- * robin) x 3 grid sizes (0.5, 1, 2 x CUs x occupancy) and keeps the fastest
- * in the plan.  Synchronises the stream.  best5 (nullable, host, 5 values):
+ * robin) x 4 grid sizes (4, 8, 12, 16 workgroups per CU) and keeps the
+ * fastest in the plan.  Without autotuning a plan launches 8 workgroups per
+ * CU, 4 sub-tiles per tile, the static schedule and four parameters per lane
+ * when n_t is a multiple of 4.  Synchronises the stream.  best5 (nullable, host, 5 values):
  * workgroups, sub-tiles per tile, microseconds per launch, schedule (1
  * dynamic, 0 static), queries per lane.
  */

@@ -120,6 +120,46 @@ __global__ __launch_bounds__(kBlock) void k_nurbs_extract(int n_nurbs, const int
     }
 }
 
+// Span lookup tables of the NURBS (see NurbsHead): for bucket m, the first
+// segment whose end breakpoint lies in bucket m or later; a parameter of
+// bucket m then lies in segments tab[m].s .. tab[m+1].s, because the bucket
+// function is monotone.  Returns false if an entry is out of range (which the
+// construction excludes; checked before anything reaches the device).
+bool build_nurbs_tables(const std::vector<int32_t> &seg_first, const std::vector<float> &brk,
+                        std::vector<NurbsHead> &head, std::vector<NurbsTab> &tab) {
+    const size_t n = seg_first.size() - 1;
+    head.resize(n);
+    tab.clear();
+    tab.reserve(2 * static_cast<size_t>(seg_first.back()) + n);
+    std::vector<int> bk;
+    for (size_t r = 0; r < n; ++r) {
+        NurbsHead h{};
+        h.s0 = seg_first[r];
+        h.nseg = seg_first[r + 1] - seg_first[r];
+        h.brk0 = h.s0 + static_cast<int32_t>(r);
+        h.tab0 = static_cast<int32_t>(tab.size());
+        const float *b = brk.data() + h.brk0;
+        h.lo = b[0];
+        h.hi = b[h.nseg];
+        const int M = 2 * h.nseg;
+        h.inv_h = static_cast<float>(M) / (h.hi - h.lo);
+        if (!std::isfinite(h.inv_h)) h.inv_h = 0.0f;  // one bucket holds every segment
+        bk.resize(h.nseg + 1);
+        for (int i = 0; i <= h.nseg; ++i) bk[i] = nurbs_bucket(b[i], h.lo, h.inv_h, M);
+        int i = 0;
+        for (int m = 0; m <= M; ++m) {
+            while (i < h.nseg - 1 && bk[i + 1] < m) ++i;
+            tab.push_back(NurbsTab{i, b[i + 1]});
+        }
+        for (int m = 0; m <= M; ++m) {
+            const int32_t v = tab[h.tab0 + m].s;
+            if (v < 0 || v >= h.nseg || (m > 0 && v < tab[h.tab0 + m - 1].s)) return false;
+        }
+        head[r] = h;
+    }
+    return true;
+}
+
 int class_cost(int kind, int degree, int method, int dim) {
     const int ch = dim + (kind != 0 ? 1 : 0);
     if (kind == 2) return 60 + 4 * ch;
@@ -140,12 +180,14 @@ struct bz_plan_s {
     int32_t *perm = nullptr;
     Tile *tiles = nullptr;
     int32_t *seg_first = nullptr;
+    NurbsHead *nhead = nullptr;
+    NurbsTab *ntab = nullptr;
     float *brk = nullptr, *seg = nullptr;
     unsigned int *counters = nullptr;
     std::vector<ClassInfo> classes;
     uint32_t n_tiles = 0, qpt = 1, vq = 1;
     int64_t n_segs = 0;
-    uint32_t workgroups = 0;
+    uint32_t workgroups = 0, cus = 1;
     int dynamic = 1;
 };
 
@@ -153,7 +195,8 @@ namespace {
 
 void plan_free(bz_plan_s *p) {
     if (!p) return;
-    void *bufs[] = {p->ctrl_s, p->w_s, p->perm, p->tiles, p->seg_first, p->brk, p->seg, p->counters};
+    void *bufs[] = {p->ctrl_s, p->w_s, p->perm, p->tiles, p->seg_first, p->nhead, p->ntab, p->brk, p->seg,
+                    p->counters};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -169,7 +212,7 @@ int dev_upload(X **dst, const std::vector<X> &src, hipStream_t s) {
     return BZ_OK;
 }
 
-int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups, uint32_t qpt,
+int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups,
                  int dynamic, uint32_t vq) {
     BatchArgs a;
     a.vq = static_cast<int>(vq);
@@ -179,8 +222,8 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
     a.perm = p->perm;
     a.tiles = p->tiles;
     a.n_tiles = p->n_tiles;
-    a.qpt = qpt;
-    a.seg_first = p->seg_first;
+    a.nhead = p->nhead;
+    a.ntab = p->ntab;
     a.brk = p->brk;
     a.seg = p->seg;
     a.t = t;
@@ -216,7 +259,7 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, hipStream_t s) {
         // NURBS tiles always map one query per lane
         const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 2 ? 1 : vq);
         const uint64_t nq = static_cast<uint64_t>(cls[c].count) * p->n_t;
-        for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), 0});
+        for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), qpt});
     }
     if (p->tiles) BZ_CHECK_HIP(hipStreamSynchronize(s));
     if (p->tiles) BZ_CHECK_HIP(hipFree(p->tiles));
@@ -360,7 +403,15 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         int rc = dev_upload(&p->perm, perm, s);
         if (!rc) rc = dev_upload(&p->seg_first, seg_first, s);
         if (!rc) rc = dev_upload(&p->brk, brk, s);
-        if (!rc) rc = build_tiles(p, 1, 1, s);
+        if (!rc) {
+            std::vector<NurbsHead> nh;
+            std::vector<NurbsTab> nt;
+            if (!build_nurbs_tables(seg_first, brk, nh, nt)) rc = fail(BZ_ERR_INTERNAL, "%s: NURBS span table", fn);
+            if (!rc) rc = dev_upload(&p->nhead, nh, s);
+            if (!rc) rc = dev_upload(&p->ntab, nt, s);
+            if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? BZ_OK : fail(BZ_ERR_HIP, "%s: sync", fn);
+        }
+        if (!rc) rc = build_tiles(p, 4, n_t % 4 == 0 ? 4 : 1, s);
         if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);
         if (!rc) rc = dmalloc(&p->w_s, w_elems * es);
         if (!rc) rc = dmalloc(reinterpret_cast<void **>(&p->seg), std::max<int64_t>(p->n_segs, 1) * 4 * (dim + 1) * sizeof(float));
@@ -417,12 +468,16 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             }
         }
         if (!rc) {
-            int blocks_per_cu = 0, dev = 0, cus = 0;
+            // default launch: the configuration the autotuner picks on MI355X for
+            // mixed batches (static schedule, four sub-tiles per tile, four
+            // parameters per lane where n_t allows, eight workgroups per CU)
+            int dev = 0, cus = 0;
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             if (e != hipSuccess) rc = hip_fail(e, "device query");
-            else rc = batch_kernel_blocks_per_cu(&blocks_per_cu);
-            p->workgroups = static_cast<uint32_t>(std::max(1, cus) * std::max(1, blocks_per_cu));
+            p->cus = static_cast<uint32_t>(std::max(1, cus));
+            p->workgroups = 8 * p->cus;
+            p->dynamic = 0;
         }
         if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? BZ_OK : fail(BZ_ERR_HIP, "%s: sync", fn);
         if (rc) {
@@ -440,7 +495,7 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream) {
         if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
         if (!t || !out) return fail(BZ_ERR_NULL, "bz_batch_eval: t and out are required");
         if (!aligned(t, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "bz_batch_eval: misaligned");
-        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->qpt, plan->dynamic, plan->vq);
+        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->dynamic, plan->vq);
     });
 }
 
@@ -454,13 +509,13 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
         hipEvent_t e0, e1;
         BZ_CHECK_HIP(hipEventCreate(&e0));
         BZ_CHECK_HIP(hipEventCreate(&e1));
-        const uint32_t base = plan->workgroups;
+        const uint32_t cus = plan->cus;
         float best = 1e30f;
-        uint32_t best_wg = base, best_q = plan->qpt, best_vq = plan->vq;
+        uint32_t best_wg = plan->workgroups, best_q = plan->qpt, best_vq = plan->vq;
         int best_dyn = plan->dynamic;
         const uint32_t qpts[] = {1, 2, 4};
         const uint32_t vqs[] = {1, 4};
-        const double wgf[] = {0.5, 1.0, 2.0};
+        const uint32_t wg_per_cu[] = {4, 8, 12, 16};
         int rc = BZ_OK;
         for (uint32_t vq : vqs) {
             if (vq == 4 && plan->n_t % 4 != 0) continue;  // four queries of one object per lane
@@ -468,16 +523,16 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
                 rc = build_tiles(plan, q, vq, s);
                 if (rc) break;
                 for (int dyn = 1; dyn >= 0 && !rc; --dyn)
-                    for (double f : wgf) {
-                        const uint32_t wg = std::max<uint32_t>(1, static_cast<uint32_t>(base * f));
-                        rc = launch_batch(plan, t, out, s, wg, q, dyn, vq);  // warm-up
+                    for (uint32_t f : wg_per_cu) {
+                        const uint32_t wg = f * cus;
+                        rc = launch_batch(plan, t, out, s, wg, dyn, vq);  // warm-up
                         if (rc) break;
                         // best of three rounds of 5 launches: one round is noisy enough
                         // to rank close configurations wrongly
                         float ms = 1e30f;
                         for (int round = 0; round < 3 && !rc; ++round) {
                             BZ_CHECK_HIP(hipEventRecord(e0, s));
-                            for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, q, dyn, vq);
+                            for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, dyn, vq);
                             if (rc) break;
                             BZ_CHECK_HIP(hipEventRecord(e1, s));
                             BZ_CHECK_HIP(hipEventSynchronize(e1));

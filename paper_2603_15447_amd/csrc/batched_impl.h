@@ -22,8 +22,43 @@ struct ClassInfo {
 struct Tile {
     ClassInfo ci;
     uint32_t q0;  // first query of the tile within its class
-    uint32_t pad;
+    uint32_t qpt; // sub-tiles of kBlock lanes in this tile (1..4)
 };
+
+// Span lookup of a NURBS query.  The parameter range [lo, hi] of NURBS r is cut
+// into M = 2*nseg equal buckets; a parameter of bucket m lies in one of the
+// segments tab[m].s .. tab[m+1].s (indices relative to the NURBS), and when
+// those are two segments, tab[m].split (the breakpoint between them) decides.
+// More than two candidates (two or more breakpoints in one bucket) fall back
+// to a binary search over the breakpoints of that range.
+struct NurbsHead {
+    int32_t s0;    // first segment of the NURBS in the plan's segment array
+    int32_t nseg;  // segments (non-empty knot spans)
+    int32_t tab0;  // first of its 2*nseg+1 table entries
+    int32_t brk0;  // first of its nseg+1 breakpoints (s0 + rank)
+    float lo, hi;  // parameter range
+    float inv_h;   // M / (hi - lo); 0 when that is not finite (one bucket)
+    int32_t pad;
+};
+
+struct NurbsTab {
+    int32_t s;    // first candidate segment of the bucket
+    float split;  // breakpoint after segment s (start of segment s+1)
+};
+
+// Bucket of parameter u (already clamped to [lo, hi]).  Evaluated identically
+// on the host (table construction) and on the device (queries): one
+// subtraction, one multiplication, clamp and floor, so it is a monotone
+// function of u and a breakpoint's bucket bounds the buckets of the
+// parameters on either side of it.  NaN lands in bucket 0.
+__host__ __device__ inline int nurbs_bucket(float u, float lo, float inv_h, int n_buckets) {
+    float x = (u - lo) * inv_h;
+    x = x > 0.0f ? x : 0.0f;
+    x = floorf(x);
+    const float top = static_cast<float>(n_buckets - 1);
+    x = x < top ? x : top;
+    return static_cast<int>(x);
+}
 
 struct BatchArgs {
     const void *ctrl_s;        // control points in class-sorted order (plan copy)
@@ -31,9 +66,9 @@ struct BatchArgs {
     const int32_t *perm;       // sorted slot -> object
     const Tile *tiles;
     uint32_t n_tiles;
-    uint32_t qpt;              // sub-tiles of kBlock queries per tile
-    const int32_t *seg_first;  // [n_nurbs+1], NURBS ranked in sorted order
-    const float *brk;          // breakpoints, nseg+1 per NURBS, at seg_first[r] + r
+    const NurbsHead *nhead;    // [n_nurbs], NURBS ranked in sorted order
+    const NurbsTab *ntab;      // span lookup tables, 2*nseg+1 entries per NURBS
+    const float *brk;          // breakpoints, nseg+1 per NURBS, from NurbsHead::brk0
     const float *seg;          // [n_segs][4][dim+1] homogeneous
     const float *t;
     float *out;
@@ -183,36 +218,6 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
     }
 }
 
-// One query of a NURBS object: clamp, binary search of the span among the
-// segment breakpoints, rational cubic Bezier of that segment.
-__device__ __forceinline__ void eval_nurbs_query(const float *__restrict__ brk, const float *__restrict__ seg, int nseg,
-                                                 int dim, float u, float *__restrict__ out, int64_t plane, int64_t q) {
-    const float lo_u = brk[0], hi_u = brk[nseg];
-    u = u < lo_u ? lo_u : u;  // NaN passes
-    u = u > hi_u ? hi_u : u;
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (brk[mid] <= u) lo = mid;
-        else hi = mid - 1;
-    }
-    const float a = brk[lo], b = brk[lo + 1];
-    const float tl = (u - a) / (b - a);
-    float B[4];
-    bernstein_basis<3>(tl, B);
-    const float *__restrict__ S = seg + static_cast<size_t>(lo) * 4 * (dim + 1);
-    float H[kMaxDim + 1] = {};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k <= kMaxDim; ++k)
-            if (k <= dim) H[k] = __builtin_fmaf(B[i], S[i * (dim + 1) + k], H[k]);
-    const float rw = 1.0f / H[dim];
-#pragma unroll
-    for (int k = 0; k < kMaxDim; ++k)
-        if (k < dim) st_stream(out + k * plane + q, H[k] * rw);
-}
-
 constexpr int kMaxQpt = 4;
 
 // Index, permutation and parameter loads of every sub-tile are issued before
@@ -230,7 +235,7 @@ __device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile 
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
-        sq.ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
+        sq.ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
         const uint32_t qc = min(qi, nq - 1);
         sq.slot[s] = fdiv(qc, a.div_nt);
         sq.j[s] = qc - sq.slot[s] * a.n_t;
@@ -271,7 +276,7 @@ __device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const uint32_t qi = tl.q0 + 4 * (s * kBlock + threadIdx.x);
-        ok[s] = s < static_cast<int>(a.qpt) && qi < nq;
+        ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
         const uint32_t qc = min(qi, nq - 4);
         slot[s] = fdiv(qc, a.div_nt);
         q[s] = qc - slot[s] * a.n_t;  // j for now
@@ -296,16 +301,104 @@ __device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &
     }
 }
 
+// NURBS queries, staged across the sub-tiles so that the dependent loads of
+// one stage (header and object index; parameter; table entries; breakpoints
+// and segment) overlap over all of a lane's queries: clamp u to the NURBS's
+// range, find its bucket and segment, and evaluate that segment's rational
+// cubic.  Every stage moves its bytes in as few vector loads as it can: the
+// address unit serves about one distinct cache line per cycle, and a wave's
+// 64 queries spread over many segments.
+typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+template <int DIM>
 __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl) {
-    SubTileQueries sq;
-    prefetch_queries(a, tl, sq);
+    constexpr int H = DIM + 1;  // homogeneous coordinates; a segment is 4*H floats = H vectors
+    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
+    uint32_t slot[kMaxQpt];
+    bool ok[kMaxQpt];
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
-        if (!sq.ok[s]) continue;
-        const uint32_t r = sq.slot[s];  // NURBS rank = slot in the class
-        const int s0 = a.seg_first[r], nseg = a.seg_first[r + 1] - s0;
-        eval_nurbs_query(a.brk + s0 + r, a.seg + static_cast<size_t>(s0) * 4 * (a.dim + 1), nseg, a.dim, sq.t[s],
-                         a.out, a.plane, sq.q[s]);
+        const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
+        ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
+        slot[s] = min(qi, nq - 1);
+    }
+    NurbsHead h[kMaxQpt];
+    int64_t q[kMaxQpt];
+    uint32_t j[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const uint32_t r = fdiv(slot[s], a.div_nt);  // NURBS rank = slot in the class
+        j[s] = slot[s] - r * a.n_t;
+        slot[s] = r;
+        h[s] = a.nhead[r];
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) q[s] = static_cast<int64_t>(a.perm[tl.ci.first + slot[s]]) * a.n_t + j[s];
+    float u[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const float v = a.t[q[s]];
+        float c = v < h[s].lo ? h[s].lo : v;  // NaN passes
+        u[s] = c > h[s].hi ? h[s].hi : c;
+    }
+    i4u e[kMaxQpt];  // table entries m and m+1: {s, split bits, s, split bits}
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const int m = nurbs_bucket(u[s], h[s].lo, h[s].inv_h, 2 * h[s].nseg);
+        e[s] = *reinterpret_cast<const i4u *>(a.ntab + h[s].tab0 + m);
+    }
+    int32_t sg[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        int lo = e[s][0], hi = e[s][2];
+        if (hi - lo <= 1) {
+            sg[s] = (hi > lo && __int_as_float(e[s][1]) <= u[s]) ? hi : lo;
+        } else {  // two or more breakpoints inside the bucket
+            const float *b = a.brk + h[s].brk0;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (b[mid] <= u[s]) lo = mid;
+                else hi = mid - 1;
+            }
+            sg[s] = lo;
+        }
+    }
+    f2u br[kMaxQpt];
+    float S[kMaxQpt][4 * H];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        br[s] = *reinterpret_cast<const f2u *>(a.brk + h[s].brk0 + sg[s]);
+        const float *__restrict__ p = a.seg + static_cast<size_t>(h[s].s0 + sg[s]) * 4 * H;
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+            const f4u x = *reinterpret_cast<const f4u *>(p + 4 * v);
+            S[s][4 * v] = x[0], S[s][4 * v + 1] = x[1], S[s][4 * v + 2] = x[2], S[s][4 * v + 3] = x[3];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!ok[s]) continue;
+        const float tseg = (u[s] - br[s][0]) / (br[s][1] - br[s][0]);
+        float B[4];
+        bernstein_basis<3>(tseg, B);
+        float acc[H] = {};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < H; ++k) acc[k] = __builtin_fmaf(B[i], S[s][i * H + k], acc[k]);
+        const float rw = 1.0f / acc[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) st_stream(a.out + k * a.plane + q[s], acc[k] * rw);
+    }
+}
+
+__device__ __forceinline__ void run_nurbs_tile_dim(const BatchArgs &a, const Tile &tl) {
+    switch (a.dim) {
+        case 1: run_nurbs_tile<1>(a, tl); break;
+        case 2: run_nurbs_tile<2>(a, tl); break;
+        case 3: run_nurbs_tile<3>(a, tl); break;
+        default: run_nurbs_tile<4>(a, tl); break;
     }
 }
 
@@ -341,7 +434,7 @@ __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) 
     const Tile tl = a.tiles[tile];
     if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl);
     else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl);
-    else run_nurbs_tile(a, tl);
+    else run_nurbs_tile_dim(a, tl);
 }
 
 // Dynamic schedule: workgroups pull tiles from an atomic counter (the next
@@ -395,8 +488,6 @@ int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) 
     return BZ_OK;
 }
 
-// Resident workgroups per CU of the kernel (FP32 Bernstein instantiation).
-int batch_kernel_blocks_per_cu(int *blocks);
 
 #define BZI_BATCH_EXTERN(F, T) extern template int launch_batch_kernel<F, T>(uint32_t, const BatchArgs &, hipStream_t);
 BZI_BATCH_EXTERN(FORM_DC, float)

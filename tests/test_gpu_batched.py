@@ -103,6 +103,37 @@ def test_nurbs_clamp_and_ends(orc):
     np.testing.assert_allclose(got, ref, atol=2e-6)
 
 
+def test_nurbs_clustered_knots(orc):
+    """Interior knots packed into a narrow cluster put many breakpoints in one
+    bucket of the span lookup (the binary-search fallback); parameters at, just
+    beside and between the clustered breakpoints, and at random."""
+    b = bz_synth.mixed_batch(n_bezier=0, n_nurbs=240, n_t=16, seed=12)
+    rng = np.random.default_rng(13)
+    for o in range(b.n_obj):
+        a, e = b.knot_offset[o], b.knot_offset[o + 1]
+        n_in = e - a - 8
+        if n_in < 2:
+            continue
+        if o % 3 == 0:  # all interior knots in [0.5, 0.5 + 2^-10)
+            v = 0.5 + rng.choice(256, n_in, replace=False) * 2.0 ** -18
+        elif o % 3 == 1:  # half uniform, half clustered
+            h = n_in // 2
+            v = np.concatenate([rng.uniform(0.01, 0.99, n_in - h), 0.25 + rng.choice(64, h, replace=False) * 2.0 ** -20])
+        else:
+            continue
+        b.knots[a + 4:e - 4] = np.sort(v).astype(np.float32)
+        inner = b.knots[a + 4:e - 4]
+        pick = rng.integers(0, n_in, 16)
+        t = inner[pick].copy()
+        t[4:8] = np.nextafter(t[4:8], np.float32(0))
+        t[8:12] = np.nextafter(t[8:12], np.float32(1))
+        t[12:] = rng.uniform(0.0, 1.0, 4)
+        b.t[o] = t
+    plan, _ = _plan(b)
+    got = host(plan(to_dev(b.t)))
+    assert _err(got, orc.batch_eval(b), _extents(b), 16) <= TOL_F32
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 def test_low_precision_storage(orc, dtype):
     """FP16/BF16 control points and weights, FP32 arithmetic: within FP32
