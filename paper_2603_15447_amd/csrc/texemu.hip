@@ -102,12 +102,15 @@ struct TexArgs {
     int rounding;
 };
 
-template <int D, int DIM, int MODE>
+// UNI: n_t is a multiple of 64, so each wavefront reads one curve's texture;
+// its index is made wave-uniform and the texels come in through scalar loads.
+template <int D, int DIM, int MODE, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
     constexpr int NT = tex_texels<D, MODE>();
     const uint32_t ql = blockIdx.x * kBlock + threadIdx.x;
     if (ql >= a.nq) return;
-    const uint32_t cl = fdiv(ql, a.div_nt);
+    uint32_t cl = fdiv(ql, a.div_nt);
+    if constexpr (UNI) cl = __builtin_amdgcn_readfirstlane(cl);
     const uint32_t j = ql - cl * a.div_nt.d;
     const int64_t qg = a.q0 + ql;
     float p = a.per_object ? a.t[qg] : a.t[j];
@@ -224,15 +227,21 @@ int launch_build_m(int degree, const float *ctrl, float *tex, uint32_t rows, hip
     return BZ_OK;
 }
 
-template <int D, int MODE>
-int launch_texemu_dm(int dim, const TexArgs &a, hipStream_t s) {
+template <int D, int MODE, bool UNI>
+void launch_texemu_dmu(int dim, const TexArgs &a, hipStream_t s) {
     const uint32_t blocks = (a.nq + kBlock - 1) / kBlock;
     switch (dim) {
-        case 1: hipLaunchKernelGGL((k_texemu<D, 1, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_texemu<D, 2, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_texemu<D, 3, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_texemu<D, 4, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_texemu<D, 1, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_texemu<D, 2, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_texemu<D, 3, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_texemu<D, 4, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
     }
+}
+
+template <int D, int MODE>
+int launch_texemu_dm(int dim, const TexArgs &a, hipStream_t s) {
+    if (a.div_nt.d % 64 == 0) launch_texemu_dmu<D, MODE, true>(dim, a, s);
+    else launch_texemu_dmu<D, MODE, false>(dim, a, s);
     BZ_CHECK_LAUNCH("k_texemu");
     return BZ_OK;
 }
@@ -349,12 +358,15 @@ struct TexPatchArgs {
     int rounding;
 };
 
-template <int DU, int DV, int DIM, int MODE>
+// UNI: n_per is a multiple of 64, so each wavefront reads one patch's
+// textures, through scalar loads of a wave-uniform address.
+template <int DU, int DV, int DIM, int MODE, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_texemu_patch(TexPatchArgs a) {
     constexpr int PER = patch_fibre_texels<DU, MODE>(), NT = (DV + 1) * PER;
     const uint32_t ql = blockIdx.x * kBlock + threadIdx.x;
     if (ql >= a.nq) return;
-    const uint32_t ol = fdiv(ql, a.div_per);
+    uint32_t ol = fdiv(ql, a.div_per);
+    if constexpr (UNI) ol = __builtin_amdgcn_readfirstlane(ol);
     const int64_t qg = a.q0 + ql;
     const float2 p2 = reinterpret_cast<const float2 *>(a.uv)[qg];
     float u = p2.x < 0.0f ? 0.0f : p2.x, v = p2.y < 0.0f ? 0.0f : p2.y;  // clamp-to-edge; NaN passes
@@ -420,15 +432,21 @@ int launch_patch_build(int du, int dv, const float *ctrl, float *tex, uint32_t r
     return fail(BZ_ERR_SHAPE, "degrees (%d, %d)", du, dv);
 }
 
-template <int DU, int DV, int MODE>
-int launch_patch_eval_d(int dim, const TexPatchArgs &a, hipStream_t s) {
+template <int DU, int DV, int MODE, bool UNI>
+void launch_patch_eval_du(int dim, const TexPatchArgs &a, hipStream_t s) {
     const uint32_t blocks = (a.nq + kBlock - 1) / kBlock;
     switch (dim) {
-        case 1: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 1, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 2, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 3, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 4, MODE>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 1, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 2, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 3, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_texemu_patch<DU, DV, 4, MODE, UNI>), dim3(blocks), dim3(kBlock), 0, s, a); break;
     }
+}
+
+template <int DU, int DV, int MODE>
+int launch_patch_eval_d(int dim, const TexPatchArgs &a, hipStream_t s) {
+    if (a.div_per.d % 64 == 0) launch_patch_eval_du<DU, DV, MODE, true>(dim, a, s);
+    else launch_patch_eval_du<DU, DV, MODE, false>(dim, a, s);
     BZ_CHECK_LAUNCH("k_texemu_patch");
     return BZ_OK;
 }

@@ -37,20 +37,21 @@ def test_build_parity(orc, mode, d):
 def test_eval_parity(orc, mode, d, frac_bits, rounding):
     """Same FP32 textures on both sides; every weight decision must agree
     (one flip would cost ~2^-8 of the curve's extent, far above the
-    tolerance)."""
-    n, nt = 67, 130  # ragged against the 256-thread blocks
+    tolerance).  Parameter counts ragged against the 256-thread blocks, and
+    multiples of 64 (one curve per wavefront, scalar texel loads)."""
+    n = 67
     rng = np.random.default_rng(510 + d + 20 * frac_bits)
-    for dim in (3, 1):
+    for dim, nt, nt_obj in ((3, 130, 7), (1, 130, 7), (3, 128, 64), (2, 64, 192)):
         ctrl = _curves(n, d, dim, 520 + d + dim)
         tex = orc.tex_build(ctrl, mode).astype(np.float32)
         t = np.concatenate([[0.0, 1.0, 0.5], rng.random(nt - 3)]).astype(np.float32)
         got = host(bz.eval_texture(to_dev(tex), d, mode, to_dev(t), frac_bits, rounding))
         ref = orc.tex_eval(tex, d, mode, t, False, frac_bits, rounding)
-        assert bbox_err(got, ref, extents(ctrl), nt) <= TOL_F32, dim
-        tp = rng.random((n, 7)).astype(np.float32)  # per-object parameters
+        assert bbox_err(got, ref, extents(ctrl), nt) <= TOL_F32, (dim, nt)
+        tp = rng.random((n, nt_obj)).astype(np.float32)  # per-object parameters
         got = host(bz.eval_texture(to_dev(tex), d, mode, to_dev(tp), frac_bits, rounding))
         ref = orc.tex_eval(tex, d, mode, tp, True, frac_bits, rounding)
-        assert bbox_err(got, ref, extents(ctrl), 7) <= TOL_F32, dim
+        assert bbox_err(got, ref, extents(ctrl), nt_obj) <= TOL_F32, (dim, nt_obj)
 
 
 def test_eval_edges(orc):
