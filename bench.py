@@ -509,10 +509,16 @@ def suite_texemu(torch, bz, bz_synth, cpu):
     m = 1 << 22
     cext = float((chain.max(axis=0) - chain.min(axis=0)).max())
     chain_exact = oracle.chain_eval(chain, T[:m]) if cpu else None
-    ch = {}
+    tiles = bz.tile_piecewise(grid)
+    ch = {"layout": "tiled"}
     for rounding in ("nearest", "truncate"):
-        ms = timed(lambda: bz.eval_piecewise_texemu(grid, T_d, 8, rounding, out=out), torch)
+        ms = timed(lambda: bz.eval_piecewise_texemu_tiled(tiles, nseg, 3, T_d, 8, rounding, out=out), torch)
         r = {"kernel_ms": ms, "value": nq / (ms * 1e-3) / 1e9, "roofline": hbm_roof(chain_bytes(nseg, 3, nq), ms)}
+        if rounding == "nearest":
+            ms_g = timed(lambda: bz.eval_piecewise_texemu(grid, T_d, 8, rounding, out=out), torch)
+            r["grid_layout"] = {"kernel_ms": ms_g, "value": nq / (ms_g * 1e-3) / 1e9,
+                                "roofline": hbm_roof(chain_bytes(nseg, 3, nq), ms_g)}
+            bz.eval_piecewise_texemu_tiled(tiles, nseg, 3, T_d, 8, rounding, out=out)  # out: the tiled result again
         if cpu:
             got = out[:, :m].cpu().numpy().astype(np.float64)
             ref = oracle.chain_texemu_eval(grid.cpu().numpy(), T[:m], 8, rounding)

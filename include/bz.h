@@ -251,6 +251,9 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
  *   1/2), N-1), the column weight is the rounded fraction x - 1/2 - k, the
  *   row coordinate runs from the centre of row k mod 2 to the other row.
  *   n_seg 1..2^24 (FP32 texel-space coordinates); grid 8-byte aligned.
+ * bz_eval_piecewise_texemu_tiled: the same reads of the same texels placed
+ *   in the cache-line tiles of bz_tile_piecewise (128-byte aligned); results
+ *   identical to bz_eval_piecewise_texemu on the grid the tiles came from.
  * Errors: BZ_ERR_UNSUPPORTED for a (degree, mode) pair outside the above,
  * BZ_ERR_SHAPE for counts, dim, frac_bits or rounding out of range.
  */
@@ -260,6 +263,8 @@ int bz_eval_texture(const float *tex, int64_t n_curves, int degree, int dim, int
                     int t_mode, int frac_bits, int rounding, float *out, bz_stream stream);
 int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, int frac_bits,
                              int rounding, float *out, bz_stream stream);
+int bz_eval_piecewise_texemu_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q,
+                                   int frac_bits, int rounding, float *out, bz_stream stream);
 
 /*
  * Surfaces through the emulated filter (Sec. 2.2: the surface's order splits

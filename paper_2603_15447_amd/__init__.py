@@ -59,6 +59,7 @@ _SIGS = {
     "bz_build_texture": (_I, [_P, _I64, _I, _I, _I, _P, _P]),
     "bz_eval_texture": (_I, [_P, _I64, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
     "bz_eval_piecewise_texemu": (_I, [_P, _I64, _I, _P, _I64, _I, _I, _P, _P]),
+    "bz_eval_piecewise_texemu_tiled": (_I, [_P, _I64, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_tensor_to_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_tensor_seiler": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_hbm_probe": (_I, [_I, _P, _P, _I64, _I, _P]),
@@ -295,6 +296,15 @@ def eval_piecewise_texemu(grid, T, frac_bits=8, rounding="nearest", out=None):
     out = _f32_out((dim, nq), grid.device, out)
     check(lib().bz_eval_piecewise_texemu(_ptr(grid), nseg, dim, _ptr(T), nq, frac_bits, TEX_ROUNDING[rounding],
                                          _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_texemu_tiled(tiles, n_seg, dim, T, frac_bits=8, rounding="nearest", out=None):
+    """The chain's cache-line tiles (tile_piecewise) read by the emulated bilinear filter at T -> out[dim, n_q]."""
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), tiles.device, out)
+    check(lib().bz_eval_piecewise_texemu_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, frac_bits,
+                                               TEX_ROUNDING[rounding], _ptr(out), _stream()))
     return out
 
 

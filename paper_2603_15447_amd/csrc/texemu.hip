@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_tex_build(const float *__restrict__ 
         } else {
             // degree 4: d1, d3, d2; degree 5: d1, d4, d2, d3
             const double d1 = sc[2], dl = sc[3], d2 = sc[4];
-            const double dm = D == 4 ? sc[4] : sc[5];
+            const double dm = sc[D == 4 ? 4 : 5];
             T[0] = b[0], T[1] = b[D], T[2] = b[0], T[3] = b[D];
             T[4] = static_cast<float>(b0 + d1), T[5] = static_cast<float>(bd + dl);
             T[6] = static_cast<float>(b0 + d1 + d2), T[7] = static_cast<float>(bd + dl + dm);
@@ -159,7 +159,11 @@ __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
     }
 }
 
-template <int DIM, int QPT>
+// TILED: the texels in the 128-byte cache-line tiles of bz_tile_piecewise
+// (C = 128/(8*DIM) columns per tile, consecutive tiles sharing a column, so
+// segment k's window is columns r, r+1 of tile k/(C-1)); otherwise the
+// column-major grid.
+template <int DIM, int QPT, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_piecewise_texemu(const float *__restrict__ grid, uint32_t n_seg,
                                                              const float *__restrict__ T, uint32_t nq,
                                                              float *__restrict__ out, int64_t plane, int F,
@@ -192,9 +196,16 @@ __global__ __launch_bounds__(kBlock) void k_piecewise_texemu(const float *__rest
     float2 g[QPT][2 * DIM];
     const float2 *__restrict__ g2 = reinterpret_cast<const float2 *>(grid);
 #pragma unroll
-    for (int i = 0; i < QPT; ++i)
+    for (int i = 0; i < QPT; ++i) {
+        size_t off = static_cast<size_t>(kk[i]) * DIM;  // in float2 units
+        if constexpr (TILED) {
+            constexpr uint32_t S = 128 / (8 * DIM) - 1;  // segments per tile
+            const uint32_t j = kk[i] / S, r = kk[i] - j * S;
+            off = static_cast<size_t>(j) * 16 + r * DIM;
+        }
 #pragma unroll
-        for (int e = 0; e < 2 * DIM; ++e) g[i][e] = g2[static_cast<size_t>(kk[i]) * DIM + e];
+        for (int e = 0; e < 2 * DIM; ++e) g[i][e] = g2[off + e];
+    }
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
         float f[4 * DIM];  // [column k, k+1][row 0, 1][dim]
@@ -269,17 +280,52 @@ int tex_texels_rt(int degree, int mode) {
     return 0;
 }
 
-template <int DIM>
+template <int DIM, bool TILED>
 int launch_chain_texemu(const float *grid, uint32_t n_seg, const float *T, uint32_t nq, float *out, int64_t plane,
                         int F, int rnd, hipStream_t s) {
     constexpr int Q = 4;
     const uint32_t blocks = (nq + kBlock * Q - 1) / (kBlock * Q);
-    hipLaunchKernelGGL((k_piecewise_texemu<DIM, Q>), dim3(blocks), dim3(kBlock), 0, s, grid, n_seg, T, nq, out, plane,
-                       F, rnd);
+    hipLaunchKernelGGL((k_piecewise_texemu<DIM, Q, TILED>), dim3(blocks), dim3(kBlock), 0, s, grid, n_seg, T, nq, out,
+                       plane, F, rnd);
     BZ_CHECK_LAUNCH("k_piecewise_texemu");
     return BZ_OK;
 }
 
+constexpr int kMaxFracBits = 20;
+
+// Validation and chunked launches of the chain read through the filter, for
+// the column-major grid or its cache-line tiles.
+template <bool TILED>
+int chain_texemu_entry(const char *fn, const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q,
+                       int frac_bits, int rounding, float *out, bz_stream stream) {
+    if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+    if (n_q < 0) return fail(BZ_ERR_SHAPE, "%s: n_q", fn);
+    if (n_seg < 1 || n_seg > (int64_t(1) << 24))
+        return fail(BZ_ERR_SHAPE, "%s: n_seg not in 1..2^24 (FP32 texel-space coordinates)", fn);
+    if (frac_bits < 0 || frac_bits > kMaxFracBits)
+        return fail(BZ_ERR_SHAPE, "%s: frac_bits %d not in 0..%d", fn, frac_bits, kMaxFracBits);
+    if (rounding != BZ_TEXW_NEAREST && rounding != BZ_TEXW_TRUNCATE)
+        return fail(BZ_ERR_SHAPE, "%s: rounding %d", fn, rounding);
+    if (n_q == 0) return BZ_OK;
+    if (!grid || !T || !out) return fail(BZ_ERR_NULL, "%s: texels, T and out are required", fn);
+    if (!aligned(grid, TILED ? 128 : 8) || !aligned(T, 4) || !aligned(out, 4))
+        return fail(BZ_ERR_ALIGN, "%s: texels need %d-byte alignment", fn, TILED ? 128 : 8);
+    const hipStream_t s = as_stream(stream);
+    const int64_t per = int64_t(1) << 30;
+    for (int64_t q0 = 0; q0 < n_q; q0 += per) {
+        const uint32_t nq = static_cast<uint32_t>(std::min(per, n_q - q0));
+        const uint32_t ns = static_cast<uint32_t>(n_seg);
+        int rc;
+        switch (dim) {
+            case 1: rc = launch_chain_texemu<1, TILED>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+            case 2: rc = launch_chain_texemu<2, TILED>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+            case 3: rc = launch_chain_texemu<3, TILED>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+            default: rc = launch_chain_texemu<4, TILED>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
+        }
+        if (rc) return rc;
+    }
+    return BZ_OK;
+}
 
 // ------------------------------------------------------------------ surfaces
 // Patch ctrl[n][dim][(DU+1)(DV+1)] (u major), DU in {2, 3}, DV in 1..4.  Every
@@ -467,7 +513,6 @@ int patch_texels_rt(int du, int dv, int mode) {
     return 0;
 }
 
-constexpr int kMaxFracBits = 20;
 
 }  // namespace
 }  // namespace bzi
@@ -547,34 +592,16 @@ int bz_eval_texture(const float *tex, int64_t n_curves, int degree, int dim, int
 int bz_eval_piecewise_texemu(const float *grid, int64_t n_seg, int dim, const float *T, int64_t n_q, int frac_bits,
                              int rounding, float *out, bz_stream stream) {
     return guarded("bz_eval_piecewise_texemu", [&]() -> int {
-        const char *fn = "bz_eval_piecewise_texemu";
-        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
-        if (n_q < 0) return fail(BZ_ERR_SHAPE, "%s: n_q", fn);
-        if (n_seg < 1 || n_seg > (int64_t(1) << 24))
-            return fail(BZ_ERR_SHAPE, "%s: n_seg not in 1..2^24 (FP32 texel-space coordinates)", fn);
-        if (frac_bits < 0 || frac_bits > kMaxFracBits)
-            return fail(BZ_ERR_SHAPE, "%s: frac_bits %d not in 0..%d", fn, frac_bits, kMaxFracBits);
-        if (rounding != BZ_TEXW_NEAREST && rounding != BZ_TEXW_TRUNCATE)
-            return fail(BZ_ERR_SHAPE, "%s: rounding %d", fn, rounding);
-        if (n_q == 0) return BZ_OK;
-        if (!grid || !T || !out) return fail(BZ_ERR_NULL, "%s: grid, T and out are required", fn);
-        if (!aligned(grid, 8) || !aligned(T, 4) || !aligned(out, 4))
-            return fail(BZ_ERR_ALIGN, "%s: grid needs 8-byte alignment", fn);
-        const hipStream_t s = as_stream(stream);
-        const int64_t per = int64_t(1) << 30;
-        for (int64_t q0 = 0; q0 < n_q; q0 += per) {
-            const uint32_t nq = static_cast<uint32_t>(std::min(per, n_q - q0));
-            const uint32_t ns = static_cast<uint32_t>(n_seg);
-            int rc;
-            switch (dim) {
-                case 1: rc = launch_chain_texemu<1>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
-                case 2: rc = launch_chain_texemu<2>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
-                case 3: rc = launch_chain_texemu<3>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
-                default: rc = launch_chain_texemu<4>(grid, ns, T + q0, nq, out + q0, n_q, frac_bits, rounding, s); break;
-            }
-            if (rc) return rc;
-        }
-        return BZ_OK;
+        return chain_texemu_entry<false>("bz_eval_piecewise_texemu", grid, n_seg, dim, T, n_q, frac_bits, rounding,
+                                         out, stream);
+    });
+}
+
+int bz_eval_piecewise_texemu_tiled(const float *tiles, int64_t n_seg, int dim, const float *T, int64_t n_q,
+                                   int frac_bits, int rounding, float *out, bz_stream stream) {
+    return guarded("bz_eval_piecewise_texemu_tiled", [&]() -> int {
+        return chain_texemu_entry<true>("bz_eval_piecewise_texemu_tiled", tiles, n_seg, dim, T, n_q, frac_bits,
+                                        rounding, out, stream);
     });
 }
 

@@ -141,6 +141,12 @@ def test_particles_probe_and_plan_errors(L):
     assert L.bz_hbm_probe(2, FAKE, FAKE, 6, 4, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(2, FAKE, FAKE, 16, 0, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(1, None, FAKE + 4, 16, 4, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_texemu_tiled(FAKE + 64, 16, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_texemu_tiled(FAKE, 16, 5, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_texemu_tiled(FAKE, 0, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_texemu_tiled(FAKE, 16, 3, FAKE, 8, 21, 0, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_texemu_tiled(None, 16, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_piecewise_texemu_tiled(None, 16, 3, None, 0, 8, 0, None, None) == bz.OK
     assert L.bz_gather_probe(FAKE, 64, 8, 5, FAKE, None) == bz.ERR_SHAPE
     assert L.bz_gather_probe(FAKE, 48, 8, 3, FAKE, None) == bz.ERR_SHAPE
     assert L.bz_gather_probe(FAKE, 0, 8, 3, FAKE, None) == bz.ERR_SHAPE

@@ -130,12 +130,20 @@ def test_errors():
                                            (777, 4, 4099)])
 @pytest.mark.parametrize("frac_bits,rounding", [(8, "nearest"), (8, "truncate"), (0, "nearest")])
 def test_chain_texemu_parity(orc, n_seg, dim, n_q, frac_bits, rounding):
+    """Grid and cache-line tiles: the oracle's emulated filter, and the two
+    placements bit-identical (same texels, same arithmetic)."""
     chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=n_q, seed=7 * n_seg + dim)
     grid = orc.piecewise_encode(chain).astype(np.float32)
+    T = np.concatenate([T, np.arange(n_seg + 1, dtype=np.float32), [np.nan, -1.0, n_seg + 3.0]]).astype(np.float32)
     got = host(bz.eval_piecewise_texemu(to_dev(grid), to_dev(T), frac_bits, rounding))
     ref = orc.chain_texemu_eval(grid, T, frac_bits, rounding)
+    ok = ~np.isnan(T)
     scale = max(float((chain.max(axis=0) - chain.min(axis=0)).max()), float(np.abs(grid).max()))
-    assert np.abs(got - ref).max() <= TOL_F32 * scale
+    assert np.abs(got[:, ok] - ref[:, ok]).max() <= TOL_F32 * scale
+    assert np.isnan(got[:, ~ok]).all()
+    tiles = bz.tile_piecewise(to_dev(grid))
+    got_t = host(bz.eval_piecewise_texemu_tiled(tiles, n_seg, dim, to_dev(T), frac_bits, rounding))
+    np.testing.assert_array_equal(got_t, got)
 
 
 def test_chain_texemu_edges(orc):
@@ -162,6 +170,8 @@ def test_chain_texemu_full_size(orc):
     ref = orc.chain_texemu_eval(gh, T)
     scale = max(float((chain.max(axis=0) - chain.min(axis=0)).max()), float(np.abs(gh).max()))
     assert np.abs(got - ref).max() / scale <= TOL_F32
+    tiles = bz.tile_piecewise(grid)
+    np.testing.assert_array_equal(host(bz.eval_piecewise_texemu_tiled(tiles, chain.shape[0] // 2, 3, to_dev(T))), got)
 
 
 # ------------------------------------------------------------ surfaces
