@@ -202,13 +202,18 @@ void plan_free(bz_plan_s *p) {
     delete p;
 }
 
+// Device copy of a host vector; waits for the copy, so the vector may be
+// freed when this returns (plan-time only).
 template <typename X>
 int dev_upload(X **dst, const std::vector<X> &src, hipStream_t s) {
     const size_t n = std::max<size_t>(src.size(), 1) * sizeof(X);
     hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), n);
     if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "bz_batch_plan_create: device allocation");
     BZ_CHECK_HIP(e);
-    if (!src.empty()) BZ_CHECK_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice, s));
+    if (!src.empty()) {
+        BZ_CHECK_HIP(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice, s));
+        BZ_CHECK_HIP(hipStreamSynchronize(s));
+    }
     return BZ_OK;
 }
 
@@ -409,7 +414,6 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             if (!build_nurbs_tables(seg_first, brk, nh, nt)) rc = fail(BZ_ERR_INTERNAL, "%s: NURBS span table", fn);
             if (!rc) rc = dev_upload(&p->nhead, nh, s);
             if (!rc) rc = dev_upload(&p->ntab, nt, s);
-            if (!rc) rc = hipStreamSynchronize(s) == hipSuccess ? BZ_OK : fail(BZ_ERR_HIP, "%s: sync", fn);
         }
         if (!rc) rc = build_tiles(p, 4, n_t % 4 == 0 ? 4 : 1, s);
         if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);
