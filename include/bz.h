@@ -362,27 +362,33 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                          int64_t n_t, int method, bz_stream stream, bz_plan *plan);
 int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
 /*
- * Autotuner: times the persistent launch on (t, out) for 2 lane mappings (one
- * query per lane, or -- when n_t is a multiple of 4 -- four consecutive
- * parameters of one object per lane) x 3 tile sizes (1, 2 or 4 sub-tiles of
- * 256 lanes per tile) x 2 schedules (atomic tile counter, static round
- * robin) x 4 grid sizes (4, 8, 12, 16 workgroups per CU) and keeps the
- * fastest in the plan.  Without autotuning a plan launches 8 workgroups per
- * CU, 4 sub-tiles per tile, the static schedule and four parameters per lane
- * when n_t is a multiple of 4.  Synchronises the stream.  best5 (nullable, host, 5 values):
- * workgroups, sub-tiles per tile, microseconds per launch, schedule (1
- * dynamic, 0 static), queries per lane.
+ * Autotuner: times the persistent launch on (t, out) for 4 tile orders
+ * (class-major, or window-major over blocks of 2^15, 2^17 or 2^18 consecutive
+ * objects with every class's tiles for a window together, heaviest class
+ * first: neighbouring objects' parameter rows and points, which share cache
+ * lines, are then read and written closer in time, and heavy and light
+ * classes alternate through the launch) x 2 lane mappings (one query per lane, or --
+ * when n_t is a multiple of 4 -- four consecutive parameters of one object per
+ * lane) x 3 tile sizes (1, 2 or 4 sub-tiles of 256 lanes per tile) x 2
+ * schedules (atomic tile counter, static round robin) x 4 grid sizes (4, 8,
+ * 12, 16 workgroups per CU) and keeps the fastest in the plan.  Without
+ * autotuning a plan launches 8 workgroups per CU, 4 sub-tiles per tile, the
+ * static schedule, windows of 2^17 objects and four parameters per lane when
+ * n_t is a multiple of 4.  Synchronises the stream.  best6 (nullable, host, 6
+ * values): workgroups, sub-tiles per tile, microseconds per launch, schedule
+ * (1 dynamic, 0 static), queries per lane, window (0: class-major).
  */
-int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best5);
+int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best6);
 /*
  * Set the launch configuration by hand (what the autotuner chooses among):
  * workgroups (1..2^20), sub_tiles (1, 2, 4), schedule (1 atomic counter, 0
  * static round robin), queries_per_lane (1, or 4 when n_t is a multiple of
- * 4).  Synchronises the stream.  BZ_ERR_UNSUPPORTED for 4 queries per lane
- * with n_t not a multiple of 4.
+ * 4), window (0 for class-major tile order, else the objects per window,
+ * below 2^31).  Synchronises the stream.  BZ_ERR_UNSUPPORTED for 4 queries
+ * per lane with n_t not a multiple of 4.
  */
 int bz_batch_plan_configure(bz_plan plan, int64_t workgroups, int sub_tiles, int schedule, int queries_per_lane,
-                            bz_stream stream);
+                            int64_t window, bz_stream stream);
 /* Plan statistics: n_classes, n_tiles, n_segments (NURBS), workgroups. */
 int bz_batch_plan_info(bz_plan plan, int64_t *info4);
 int bz_plan_destroy(bz_plan plan);

@@ -79,7 +79,7 @@ _SIGS = {
     "bz_batch_eval": (_I, [_P, _P, _P, _P]),
     "bz_batch_plan_autotune": (_I, [_P, _P, _P, _P, _P]),
     "bz_batch_plan_info": (_I, [_P, _P]),
-    "bz_batch_plan_configure": (_I, [_P, _I64, _I, _I, _I, _P]),
+    "bz_batch_plan_configure": (_I, [_P, _I64, _I, _I, _I, _I64, _P]),
     "bz_plan_destroy": (_I, [_P]),
     "bz_adjoint_bezier": (_I, [_P, _P, _I64, _I, _I, _P, _I64, _I, _P, _P, _P, _P, _P]),
     "bz_fit_adam_step": (_I, [_P, _P, _P, _I64, _I, _I, _I64, _P, _P, _P, _P, _I, _F, _F, _F, _F, _P, _P]),
@@ -423,14 +423,14 @@ class BatchPlan:
         return {"n_classes": buf[0], "n_tiles": buf[1], "n_segments": buf[2], "workgroups": buf[3]}
 
     def autotune(self, t, out):
-        buf = (ctypes.c_int64 * 5)()
+        buf = (ctypes.c_int64 * 6)()
         check(lib().bz_batch_plan_autotune(self._h, _ptr(t), _ptr(out), _stream(), ctypes.cast(buf, _P)))
         return {"workgroups": buf[0], "tile_multiple": buf[1], "us_per_launch": buf[2],
-                "schedule": "dynamic" if buf[3] else "static", "queries_per_lane": buf[4]}
+                "schedule": "dynamic" if buf[3] else "static", "queries_per_lane": buf[4], "window": buf[5]}
 
-    def configure(self, workgroups, sub_tiles=1, schedule="dynamic", queries_per_lane=1):
+    def configure(self, workgroups, sub_tiles=1, schedule="dynamic", queries_per_lane=1, window=0):
         check(lib().bz_batch_plan_configure(self._h, workgroups, sub_tiles, 1 if schedule == "dynamic" else 0,
-                                            queries_per_lane, _stream()))
+                                            queries_per_lane, window, _stream()))
 
     def __call__(self, t, out=None):
         assert t.shape == (self.n_obj, self.n_t)

@@ -160,6 +160,9 @@ bool build_nurbs_tables(const std::vector<int32_t> &seg_first, const std::vector
     return true;
 }
 
+// Objects per window of the default tile order (see build_tiles).
+constexpr uint32_t kDefaultWindow = 131072;
+
 int class_cost(int kind, int degree, int method, int dim) {
     const int ch = dim + (kind != 0 ? 1 : 0);
     if (kind == 2) return 60 + 4 * ch;
@@ -185,7 +188,8 @@ struct bz_plan_s {
     float *brk = nullptr, *seg = nullptr;
     unsigned int *counters = nullptr;
     std::vector<ClassInfo> classes;
-    uint32_t n_tiles = 0, qpt = 1, vq = 1;
+    std::vector<int32_t> perm_h;  // host copy of perm (window boundaries of the tile order)
+    uint32_t n_tiles = 0, qpt = 1, vq = 1, window = 0;
     int64_t n_segs = 0;
     uint32_t workgroups = 0, cus = 1;
     int dynamic = 1;
@@ -250,8 +254,13 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
 }
 
 // Rebuild the tile list for `qpt` sub-tiles of 256 lanes x `vq` queries per
-// tile (heaviest class first; NURBS tiles one query per lane).
-int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, hipStream_t s) {
+// tile (NURBS tiles one query per lane).  window = 0: class-major order,
+// heaviest class first.  window = W: window-major order over consecutive
+// blocks of W objects (in the caller's order), and within a window every
+// class, heaviest first, for that window's objects -- so the points and
+// parameter rows of neighbouring objects, which share cache lines, are
+// written and read close together in time.
+int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, uint32_t window, hipStream_t s) {
     const std::vector<ClassInfo> &cls = p->classes;
     std::vector<int> order(cls.size());
     std::iota(order.begin(), order.end(), 0);
@@ -260,11 +269,28 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, hipStream_t s) {
                class_cost(cls[y].kind, cls[y].degree, p->method, p->dim);
     });
     std::vector<Tile> tiles;
-    for (int c : order) {
-        // NURBS tiles always map one query per lane
+    auto emit = [&](int c, uint64_t a, uint64_t b) {  // queries [a, b) of class c
         const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 2 ? 1 : vq);
-        const uint64_t nq = static_cast<uint64_t>(cls[c].count) * p->n_t;
-        for (uint64_t q0 = 0; q0 < nq; q0 += span) tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), qpt});
+        for (uint64_t q0 = a; q0 < b; q0 += span)
+            tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), static_cast<uint32_t>(b), qpt, 0});
+    };
+    const uint64_t nt = static_cast<uint64_t>(p->n_t);
+    if (window == 0) {
+        for (int c : order) emit(c, 0, static_cast<uint64_t>(cls[c].count) * nt);
+    } else {
+        // a class's slots hold its objects in increasing caller order, so the
+        // objects of window w are one run of slots per class
+        std::vector<int64_t> cur(cls.size(), 0);
+        for (int64_t w0 = 0; w0 < p->n_obj; w0 += window) {
+            const int32_t w1 = static_cast<int32_t>(std::min<int64_t>(p->n_obj, w0 + window));
+            for (int c : order) {
+                const int32_t *first = p->perm_h.data() + cls[c].first;
+                const int64_t a = cur[c];
+                const int64_t b = std::lower_bound(first + a, first + cls[c].count, w1) - first;
+                if (b > a) emit(c, static_cast<uint64_t>(a) * nt, static_cast<uint64_t>(b) * nt);
+                cur[c] = b;
+            }
+        }
     }
     if (p->tiles) BZ_CHECK_HIP(hipStreamSynchronize(s));
     if (p->tiles) BZ_CHECK_HIP(hipFree(p->tiles));
@@ -274,6 +300,7 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, hipStream_t s) {
     p->n_tiles = static_cast<uint32_t>(tiles.size());
     p->qpt = qpt;
     p->vq = vq;
+    p->window = window;
     return BZ_OK;
 }
 
@@ -405,6 +432,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: device allocation of %zu bytes", fn, bytes);
             return e == hipSuccess ? BZ_OK : hip_fail(e, "hipMalloc");
         };
+        p->perm_h = perm;
         int rc = dev_upload(&p->perm, perm, s);
         if (!rc) rc = dev_upload(&p->seg_first, seg_first, s);
         if (!rc) rc = dev_upload(&p->brk, brk, s);
@@ -415,7 +443,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             if (!rc) rc = dev_upload(&p->nhead, nh, s);
             if (!rc) rc = dev_upload(&p->ntab, nt, s);
         }
-        if (!rc) rc = build_tiles(p, 4, n_t % 4 == 0 ? 4 : 1, s);
+        if (!rc) rc = build_tiles(p, 4, n_t % 4 == 0 ? 4 : 1, kDefaultWindow, s);
         if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);
         if (!rc) rc = dmalloc(&p->w_s, w_elems * es);
         if (!rc) rc = dmalloc(reinterpret_cast<void **>(&p->seg), std::max<int64_t>(p->n_segs, 1) * 4 * (dim + 1) * sizeof(float));
@@ -474,7 +502,8 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         if (!rc) {
             // default launch: the configuration the autotuner picks on MI355X for
             // mixed batches (static schedule, four sub-tiles per tile, four
-            // parameters per lane where n_t allows, eight workgroups per CU)
+            // parameters per lane where n_t allows, windows of 2^17 objects,
+            // eight workgroups per CU)
             int dev = 0, cus = 0;
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -503,7 +532,7 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream) {
     });
 }
 
-int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best5) {
+int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best6) {
     return guarded("bz_batch_plan_autotune", [&]() -> int {
         if (!plan) return fail(BZ_ERR_NULL, "bz_batch_plan_autotune: plan is required");
         if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
@@ -515,69 +544,79 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
         BZ_CHECK_HIP(hipEventCreate(&e1));
         const uint32_t cus = plan->cus;
         float best = 1e30f;
-        uint32_t best_wg = plan->workgroups, best_q = plan->qpt, best_vq = plan->vq;
+        uint32_t best_wg = plan->workgroups, best_q = plan->qpt, best_vq = plan->vq, best_win = plan->window;
         int best_dyn = plan->dynamic;
         const uint32_t qpts[] = {1, 2, 4};
         const uint32_t vqs[] = {1, 4};
         const uint32_t wg_per_cu[] = {4, 8, 12, 16};
-        int rc = BZ_OK;
-        for (uint32_t vq : vqs) {
-            if (vq == 4 && plan->n_t % 4 != 0) continue;  // four queries of one object per lane
-            for (uint32_t q : qpts) {
-                rc = build_tiles(plan, q, vq, s);
-                if (rc) break;
-                for (int dyn = 1; dyn >= 0 && !rc; --dyn)
-                    for (uint32_t f : wg_per_cu) {
-                        const uint32_t wg = f * cus;
-                        rc = launch_batch(plan, t, out, s, wg, dyn, vq);  // warm-up
-                        if (rc) break;
-                        // best of three rounds of 5 launches: one round is noisy enough
-                        // to rank close configurations wrongly
-                        float ms = 1e30f;
-                        for (int round = 0; round < 3 && !rc; ++round) {
-                            BZ_CHECK_HIP(hipEventRecord(e0, s));
-                            for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, dyn, vq);
-                            if (rc) break;
-                            BZ_CHECK_HIP(hipEventRecord(e1, s));
-                            BZ_CHECK_HIP(hipEventSynchronize(e1));
-                            float r_ms = 0;
-                            BZ_CHECK_HIP(hipEventElapsedTime(&r_ms, e0, e1));
-                            ms = std::min(ms, r_ms);
-                        }
-                        if (rc) break;
-                        if (ms < best) {
-                            best = ms;
-                            best_wg = wg;
-                            best_q = q;
-                            best_dyn = dyn;
-                            best_vq = vq;
-                        }
-                    }
-                if (rc) break;
+        const uint32_t windows[] = {0, 32768, 131072, 262144};
+        struct Layout {
+            uint32_t win, vq, q;
+        };
+        std::vector<Layout> layouts;
+        for (uint32_t win : windows) {
+            if (win != 0 && win >= plan->n_obj) continue;  // one window is the class-major order
+            for (uint32_t vq : vqs) {
+                if (vq == 4 && plan->n_t % 4 != 0) continue;  // four queries of one object per lane
+                for (uint32_t q : qpts) layouts.push_back(Layout{win, vq, q});
             }
+        }
+        int rc = BZ_OK;
+        for (const Layout &L : layouts) {
+            rc = build_tiles(plan, L.q, L.vq, L.win, s);
+            if (rc) break;
+            for (int dyn = 1; dyn >= 0 && !rc; --dyn)
+                for (uint32_t f : wg_per_cu) {
+                    const uint32_t wg = f * cus;
+                    rc = launch_batch(plan, t, out, s, wg, dyn, L.vq);  // warm-up
+                    if (rc) break;
+                    // best of three rounds of 5 launches: one round is noisy enough
+                    // to rank close configurations wrongly
+                    float ms = 1e30f;
+                    for (int round = 0; round < 3 && !rc; ++round) {
+                        BZ_CHECK_HIP(hipEventRecord(e0, s));
+                        for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, dyn, L.vq);
+                        if (rc) break;
+                        BZ_CHECK_HIP(hipEventRecord(e1, s));
+                        BZ_CHECK_HIP(hipEventSynchronize(e1));
+                        float r_ms = 0;
+                        BZ_CHECK_HIP(hipEventElapsedTime(&r_ms, e0, e1));
+                        ms = std::min(ms, r_ms);
+                    }
+                    if (rc) break;
+                    if (ms < best) {
+                        best = ms;
+                        best_wg = wg;
+                        best_q = L.q;
+                        best_dyn = dyn;
+                        best_vq = L.vq;
+                        best_win = L.win;
+                    }
+                }
             if (rc) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc) return rc;
-        rc = build_tiles(plan, best_q, best_vq, s);
+        rc = build_tiles(plan, best_q, best_vq, best_win, s);
         if (rc) return rc;
         plan->workgroups = best_wg;
         plan->dynamic = best_dyn;
         BZ_CHECK_HIP(hipStreamSynchronize(s));
-        if (best5) {
-            best5[0] = best_wg;
-            best5[1] = best_q;
-            best5[2] = static_cast<int64_t>(best * 1000.0f / 5.0f);  // microseconds per launch
-            best5[3] = best_dyn;
-            best5[4] = best_vq;
+        if (best6) {
+            best6[0] = best_wg;
+            best6[1] = best_q;
+            best6[2] = static_cast<int64_t>(best * 1000.0f / 5.0f);  // microseconds per launch
+            best6[3] = best_dyn;
+            best6[4] = best_vq;
+            best6[5] = best_win;
         }
         return BZ_OK;
     });
 }
 
 int bz_batch_plan_configure(bz_plan plan, int64_t workgroups, int sub_tiles, int schedule, int queries_per_lane,
-                            bz_stream stream) {
+                            int64_t window, bz_stream stream) {
     return guarded("bz_batch_plan_configure", [&]() -> int {
         const char *fn = "bz_batch_plan_configure";
         if (!plan) return fail(BZ_ERR_NULL, "%s: plan is required", fn);
@@ -587,8 +626,10 @@ int bz_batch_plan_configure(bz_plan plan, int64_t workgroups, int sub_tiles, int
         if (queries_per_lane != 1 && queries_per_lane != 4) return fail(BZ_ERR_SHAPE, "%s: queries_per_lane", fn);
         if (queries_per_lane == 4 && plan->n_t % 4 != 0)
             return fail(BZ_ERR_UNSUPPORTED, "%s: 4 queries per lane need n_t a multiple of 4", fn);
+        if (window < 0 || window > (int64_t(1) << 31) - 1) return fail(BZ_ERR_SHAPE, "%s: window", fn);
         const hipStream_t s = as_stream(stream);
-        const int rc = build_tiles(plan, static_cast<uint32_t>(sub_tiles), static_cast<uint32_t>(queries_per_lane), s);
+        const int rc = build_tiles(plan, static_cast<uint32_t>(sub_tiles), static_cast<uint32_t>(queries_per_lane),
+                                   static_cast<uint32_t>(window), s);
         if (rc) return rc;
         plan->workgroups = static_cast<uint32_t>(workgroups);
         plan->dynamic = schedule;

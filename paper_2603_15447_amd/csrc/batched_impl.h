@@ -21,8 +21,10 @@ struct ClassInfo {
 // A tile carries its class record, so a workgroup needs one scalar load per tile.
 struct Tile {
     ClassInfo ci;
-    uint32_t q0;  // first query of the tile within its class
-    uint32_t qpt; // sub-tiles of kBlock lanes in this tile (1..4)
+    uint32_t q0;   // first query of the tile within its class
+    uint32_t q1;   // end of the tile's queries (exclusive, a multiple of n_t)
+    uint32_t qpt;  // sub-tiles of kBlock lanes in this tile (1..4)
+    uint32_t pad;
 };
 
 // Span lookup of a NURBS query.  The parameter range [lo, hi] of NURBS r is cut
@@ -235,7 +237,7 @@ __device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile 
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
-        sq.ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
+        sq.ok[s] = s < static_cast<int>(tl.qpt) && qi < tl.q1;
         const uint32_t qc = min(qi, nq - 1);
         sq.slot[s] = fdiv(qc, a.div_nt);
         sq.j[s] = qc - sq.slot[s] * a.n_t;
@@ -276,7 +278,7 @@ __device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const uint32_t qi = tl.q0 + 4 * (s * kBlock + threadIdx.x);
-        ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
+        ok[s] = s < static_cast<int>(tl.qpt) && qi < tl.q1;
         const uint32_t qc = min(qi, nq - 4);
         slot[s] = fdiv(qc, a.div_nt);
         q[s] = qc - slot[s] * a.n_t;  // j for now
@@ -320,7 +322,7 @@ __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &t
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const uint32_t qi = tl.q0 + s * kBlock + threadIdx.x;
-        ok[s] = s < static_cast<int>(tl.qpt) && qi < nq;
+        ok[s] = s < static_cast<int>(tl.qpt) && qi < tl.q1;
         slot[s] = min(qi, nq - 1);
     }
     NurbsHead h[kMaxQpt];

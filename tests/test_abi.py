@@ -155,6 +155,6 @@ def test_particles_probe_and_plan_errors(L):
     assert L.bz_gather_probe(None, 64, 8, 3, FAKE, None) == bz.ERR_NULL
     assert L.bz_gather_probe(FAKE + 64, 64, 8, 3, FAKE, None) == bz.ERR_ALIGN
     assert L.bz_gather_probe(FAKE, 64, 0, 3, None, None) == bz.OK
-    assert L.bz_batch_plan_configure(None, 64, 1, 1, 1, None) == bz.ERR_NULL
+    assert L.bz_batch_plan_configure(None, 64, 1, 1, 1, 0, None) == bz.ERR_NULL
     assert L.bz_batch_plan_autotune(None, FAKE, FAKE, None, None) == bz.ERR_NULL
     assert L.bz_batch_eval(None, FAKE, FAKE, None) == bz.ERR_NULL

@@ -151,8 +151,10 @@ def test_low_precision_storage(orc, dtype):
 def test_every_launch_configuration(orc, n_t):
     """Both lane mappings (1 query per lane; 4 consecutive parameters of one
     object per lane), every tile size, both schedules, small and large
-    grids: within the tolerance of the oracle, and bit-identical across
-    schedules, tile sizes and grids of one mapping."""
+    grids, class-major and window-major tile orders (windows of one object,
+    and of 700 objects, which cut classes into partial tiles): within the
+    tolerance of the oracle, and bit-identical across schedules, tile sizes,
+    orders and grids of one mapping."""
     b = bz_synth.mixed_batch(n_bezier=3000, n_nurbs=300, n_t=n_t, deg_lo=1, seed=40 + n_t)
     plan, _ = _plan(b)
     t = to_dev(b.t)
@@ -162,11 +164,11 @@ def test_every_launch_configuration(orc, n_t):
         # two lane mappings contract their FMAs differently (1 ulp apart)
         for sub in (1, 2, 4):
             for sched in ("dynamic", "static"):
-                for wg in (7, 600):
-                    plan.configure(wg, sub, sched, vq)
+                for wg, window in ((7, 0), (600, 0), (600, 1), (7, 700), (600, 700)):
+                    plan.configure(wg, sub, sched, vq, window)
                     out = torch.full((3, b.n_obj * n_t), float("nan"), device=t.device)
                     got = host(plan(t, out=out))  # every query must be written
-                    assert _err(got, ref, _extents(b), n_t) <= TOL_F32, (vq, sub, sched, wg)
+                    assert _err(got, ref, _extents(b), n_t) <= TOL_F32, (vq, sub, sched, wg, window)
                     if first is None:
                         first = got
                     else:
@@ -185,6 +187,7 @@ def test_autotune_keeps_results(orc):
     out = torch.empty((3, b.n_obj * 16), device=t.device)
     best = plan.autotune(t, out)
     assert best["workgroups"] >= 1 and best["tile_multiple"] in (1, 2, 4) and best["queries_per_lane"] in (1, 4)
+    assert best["window"] == 0  # every window candidate covers the 22000 objects
     out.fill_(float("nan"))
     got = host(plan(t, out=out))
     assert _err(got, orc.batch_eval(b), _extents(b), 16) <= TOL_F32
