@@ -85,6 +85,13 @@ struct BatchArgs {
 
 namespace batch_dev {
 
+// FP32 value of 16-bit storage bits.
+template <typename T>
+__device__ __forceinline__ float bits_to_f32(uint16_t b) {
+    if constexpr (std::is_same<T, _Float16>::value) return static_cast<float>(__builtin_bit_cast(_Float16, b));
+    else return __uint_as_float(static_cast<uint32_t>(b) << 16);  // bf16
+}
+
 // Load n contiguous storage elements as FP32.
 template <typename T, int N>
 __device__ __forceinline__ void load_row(const T *__restrict__ p, float (&v)[N]) {
@@ -102,8 +109,31 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, float (&v)[N])
 #pragma unroll
         for (int i = 4 * V; i < N; ++i) v[i] = p[i];
     } else {
+        // 16-bit storage: the row in 16-, 8-, 4- and 2-byte pieces (rows are only
+        // 2-byte aligned), each element widened from its bits
+        typedef uint16_t u16x8 __attribute__((ext_vector_type(8), aligned(2)));
+        typedef uint16_t u16x4 __attribute__((ext_vector_type(4), aligned(2)));
+        typedef uint16_t u16x2 __attribute__((ext_vector_type(2), aligned(2)));
+        const uint16_t *__restrict__ q = reinterpret_cast<const uint16_t *>(p);
+        constexpr int N8 = N / 8 * 8, R = N - N8;
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = to_f32<T>(p[i]);
+        for (int i = 0; i < N8; i += 8) {
+            const u16x8 x = *reinterpret_cast<const u16x8 *>(q + i);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[i + e] = bits_to_f32<T>(x[e]);
+        }
+        constexpr int O4 = N8, O2 = N8 + (R & 4), O1 = O2 + (R & 2);
+        if constexpr ((R & 4) != 0) {
+            const u16x4 x = *reinterpret_cast<const u16x4 *>(q + O4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[O4 + e] = bits_to_f32<T>(x[e]);
+        }
+        if constexpr ((R & 2) != 0) {
+            const u16x2 x = *reinterpret_cast<const u16x2 *>(q + O2);
+            v[O2] = bits_to_f32<T>(x[0]);
+            v[O2 + 1] = bits_to_f32<T>(x[1]);
+        }
+        if constexpr ((R & 1) != 0) v[O1] = bits_to_f32<T>(q[O1]);
     }
 }
 
