@@ -155,7 +155,7 @@ def hbm_probe(torch, bz, mib=1024, iters=10):
     res = {"bytes": 4 * n}
     for mode in ("read", "write", "copy"):
         best = None
-        for bpc in (2, 4, 8, 16):
+        for bpc in (0, 2, 4, 8, 16):  # 0: one 16-byte vector per thread
             ms = timed(lambda: bz.hbm_probe(mode, src, dst, bpc), torch, iters=iters)
             gbs = (2 if mode == "copy" else 1) * 4 * n / (ms * 1e-3) / 1e9
             if best is None or gbs > best[0]:
@@ -254,6 +254,15 @@ def suite_plain(torch, bz, bz_synth, cpu):
     for m in ("decasteljau", "bernstein", "seiler"):
         ms = timed(lambda: bz.eval_bezier(c16, t_d, m, out=o16), torch)
         res[m + "_x16"] = {"kernel_ms": ms, "value": o16.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(n16, ms)}
+    # x64 curves: 805 MB of points, more than the 256 MB Infinity Cache can hold
+    # (the x16 outputs, 201 MB, may stay in it between launches)
+    c64 = torch.from_numpy(bz_synth.plain_curves(n_curves=1 << 18)[0]).cuda()
+    o64 = torch.empty((3, (1 << 18) * 256), device="cuda")
+    n64 = o64.numel() * 4 + c64.numel() * 4 + t.nbytes
+    for m in ("decasteljau", "bernstein", "seiler"):
+        ms = timed(lambda: bz.eval_bezier(c64, t_d, m, out=o64), torch)
+        res[m + "_x64"] = {"kernel_ms": ms, "value": o64.shape[1] / (ms * 1e-3) / 1e9, "roofline": hbm_roof(n64, ms)}
+    del c64, o64
     # random t per curve (t[n][256] ~ U[0,1), seed 1001): 4 bytes in and 12 out per point
     c16h, tr = bz_synth.random_curves(1 << 16, 3, 3, 256, seed=1001 + 16)
     c16r, tr_d = torch.from_numpy(c16h).cuda(), torch.from_numpy(tr).cuda()
@@ -268,7 +277,8 @@ def suite_plain(torch, bz, bz_synth, cpu):
             e["max_err_bbox"] = max_err_bbox(o16[:, :k * 256].cpu().numpy(), ref, extents(c16h[:k]), 256)
         res[m + "_x16_random_t"] = e
     return {"workload": "4096 cubic 3D Bezier curves x 256 shared t (1M points), FP32; *_x16: 65536 curves; "
-                        "*_x16_random_t: 65536 curves x 256 random t each", "unit": "G evals/s", **res}
+                        "*_x64: 262144 curves; *_x16_random_t: 65536 curves x 256 random t each",
+            "unit": "G evals/s", **res}
 
 
 def batch_bytes(b, es, n_segs, dim):

@@ -79,7 +79,8 @@ int bz_device_cu_count(void);
  * Measured HBM ceiling for the rooflines (the paper's performance section
  * compares against the memory system; MI355X publishes 8 TB/s): a streaming
  * kernel over n floats (n a multiple of 4, buffers 16-byte aligned) with a
- * persistent grid of blocks_per_cu x (CU count) workgroups of 256 threads.
+ * persistent grid of blocks_per_cu x (CU count) workgroups of 256 threads
+ * (blocks_per_cu 1..64), or with blocks_per_cu 0 one 16-byte vector per thread.
  * mode 0: read src (dst[0] is written only if a thread's partial sum equals
  * -1, which non-negative data never gives); 1: write dst; 2: copy src to dst.
  * Timing is the caller's (events around the call).

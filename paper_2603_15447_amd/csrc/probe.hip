@@ -112,13 +112,17 @@ extern "C" int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, i
         const char *fn = "bz_hbm_probe";
         if (mode < 0 || mode > 2) return fail(BZ_ERR_SHAPE, "%s: mode %d (0 read, 1 write, 2 copy)", fn, mode);
         if (n < 0 || n % 4 != 0) return fail(BZ_ERR_SHAPE, "%s: n %lld not a multiple of 4", fn, (long long)n);
-        if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(BZ_ERR_SHAPE, "%s: blocks_per_cu", fn);
+        if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(BZ_ERR_SHAPE, "%s: blocks_per_cu", fn);
         if (n == 0) return BZ_OK;
         if ((mode != 1 && !src) || !dst) return fail(BZ_ERR_NULL, "%s: buffers are required", fn);
         if (!aligned(src, 16) || !aligned(dst, 16)) return fail(BZ_ERR_ALIGN, "%s: 16-byte alignment", fn);
         const hipStream_t s = as_stream(stream);
-        const uint32_t blocks = static_cast<uint32_t>(bz_device_cu_count() * blocks_per_cu);
         const int64_t n4 = n / 4;
+        // blocks_per_cu 0: one 16-byte vector per thread (a grid as large as the data)
+        if (blocks_per_cu == 0 && (n4 + kBlock - 1) / kBlock > 0x7fffffffll)
+            return fail(BZ_ERR_SHAPE, "%s: n too large for one vector per thread", fn);
+        const uint32_t blocks = blocks_per_cu == 0 ? static_cast<uint32_t>((n4 + kBlock - 1) / kBlock)
+                                                   : static_cast<uint32_t>(bz_device_cu_count() * blocks_per_cu);
         if (mode == 0)
             hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(kBlock), 0, s, reinterpret_cast<const v4f *>(src),
                                n4, dst);

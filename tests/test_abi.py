@@ -139,7 +139,8 @@ def test_particles_probe_and_plan_errors(L):
     assert L.bz_particles_step(0, FAKE, 16, 64, FAKE, FAKE, ctypes.c_float(0.01), 0, 0, None, None, None) == bz.OK
     assert L.bz_hbm_probe(3, FAKE, FAKE, 16, 4, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(2, FAKE, FAKE, 6, 4, None) == bz.ERR_SHAPE
-    assert L.bz_hbm_probe(2, FAKE, FAKE, 16, 0, None) == bz.ERR_SHAPE
+    assert L.bz_hbm_probe(2, FAKE, FAKE, 16, -1, None) == bz.ERR_SHAPE
+    assert L.bz_hbm_probe(2, FAKE, FAKE, 16, 65, None) == bz.ERR_SHAPE
     assert L.bz_hbm_probe(1, None, FAKE + 4, 16, 4, None) == bz.ERR_ALIGN
     assert L.bz_eval_piecewise_texemu_tiled(FAKE + 64, 16, 3, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_ALIGN
     assert L.bz_eval_piecewise_texemu_tiled(FAKE, 16, 5, FAKE, 8, 8, 0, FAKE, None) == bz.ERR_SHAPE

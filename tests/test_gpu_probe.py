@@ -20,6 +20,14 @@ def test_probe_modes():
     bz.hbm_probe("read", src, dst, 8)  # non-negative data: dst untouched
     torch.cuda.synchronize()
     assert bool((dst == 1.0).all())
+    dst.zero_()
+    bz.hbm_probe("copy", src, dst, 0)  # one vector per thread
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    dst.zero_()
+    bz.hbm_probe("write", src, dst, 0)
+    torch.cuda.synchronize()
+    assert bool((dst == 1.0).all())
     with pytest.raises(bz.BzError) as e:
         bz.check(bz.lib().bz_hbm_probe(2, src.data_ptr(), dst.data_ptr(), 6, 4, None))
     assert e.value.code == bz.ERR_SHAPE
