@@ -352,7 +352,8 @@ int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw
  * its own device memory: none of the descriptor arrays, ctrl or w is used
  * after bz_batch_plan_create returns (changed control points need a new
  * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the knot
- * range) and out[dim][n_obj*n_t] are passed per evaluation.  method:
+ * range) and out[dim][n_obj*n_t] are passed per evaluation (out must not
+ * overlap t).  method:
  * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects are evaluated in FP32
  * (no FP64 recomputation: use bz_eval_rational for signed weights).
  * n_obj*n_t must stay below 2^32.

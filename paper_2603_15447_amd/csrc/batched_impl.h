@@ -283,7 +283,7 @@ __device__ __forceinline__ void prefetch_queries(const BatchArgs &a, const Tile 
 }
 
 template <int D, bool RAT, int F, typename T>
-__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &tl) {
+__device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     SubTileQueries sq;
     prefetch_queries(a, tl, sq);
 #pragma unroll
@@ -293,14 +293,14 @@ __device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &t
         const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(sq.slot[s]) * (D + 1) * a.dim;
         const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1)
                          : nullptr;
-        eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], a.out, a.plane, sq.q[s]);
+        eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], out, a.plane, sq.q[s]);
     }
 }
 
 // Lane l of sub-tile s takes the four queries starting at q0 + 4(s*256 + l);
 // n_t is a multiple of 4, so they belong to one object.
 template <int D, bool RAT, int F, typename T>
-__device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &tl) {
+__device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
     uint32_t slot[kMaxQpt];
     int64_t q[kMaxQpt];
@@ -329,7 +329,7 @@ __device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &
         const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(slot[s]) * (D + 1) * a.dim;
         const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(slot[s]) * (D + 1)
                          : nullptr;
-        eval_curve_query4<D, RAT, F, T>(P, W, a.dim, tv[s], a.out, a.plane, q[s]);
+        eval_curve_query4<D, RAT, F, T>(P, W, a.dim, tv[s], out, a.plane, q[s]);
     }
 }
 
@@ -344,7 +344,7 @@ typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
 template <int DIM>
-__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl) {
+__device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     constexpr int H = DIM + 1;  // homogeneous coordinates; a segment is 4*H floats = H vectors
     const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
     uint32_t slot[kMaxQpt];
@@ -421,52 +421,52 @@ __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &t
             for (int k = 0; k < H; ++k) acc[k] = __builtin_fmaf(B[i], S[s][i * H + k], acc[k]);
         const float rw = 1.0f / acc[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) st_stream(a.out + k * a.plane + q[s], acc[k] * rw);
+        for (int k = 0; k < DIM; ++k) st_stream(out + k * a.plane + q[s], acc[k] * rw);
     }
 }
 
-__device__ __forceinline__ void run_nurbs_tile_dim(const BatchArgs &a, const Tile &tl) {
+__device__ __forceinline__ void run_nurbs_tile_dim(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     switch (a.dim) {
-        case 1: run_nurbs_tile<1>(a, tl); break;
-        case 2: run_nurbs_tile<2>(a, tl); break;
-        case 3: run_nurbs_tile<3>(a, tl); break;
-        default: run_nurbs_tile<4>(a, tl); break;
+        case 1: run_nurbs_tile<1>(a, tl, out); break;
+        case 2: run_nurbs_tile<2>(a, tl, out); break;
+        case 3: run_nurbs_tile<3>(a, tl, out); break;
+        default: run_nurbs_tile<4>(a, tl, out); break;
     }
 }
 
 template <int D, bool RAT, int F, typename T, int VQ>
-__device__ __forceinline__ void run_curve_tile_vq(const BatchArgs &a, const Tile &tl) {
-    if constexpr (VQ == 4) run_curve_tile4<D, RAT, F, T>(a, tl);
-    else run_curve_tile<D, RAT, F, T>(a, tl);
+__device__ __forceinline__ void run_curve_tile_vq(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
+    if constexpr (VQ == 4) run_curve_tile4<D, RAT, F, T>(a, tl, out);
+    else run_curve_tile<D, RAT, F, T>(a, tl, out);
 }
 
 template <bool RAT, int F, typename T, int VQ>
-__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &tl) {
+__device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     switch (tl.ci.degree) {
-        case 1: run_curve_tile_vq<1, RAT, F, T, VQ>(a, tl); break;
-        case 2: run_curve_tile_vq<2, RAT, F, T, VQ>(a, tl); break;
-        case 3: run_curve_tile_vq<3, RAT, F, T, VQ>(a, tl); break;
-        case 4: run_curve_tile_vq<4, RAT, F, T, VQ>(a, tl); break;
-        case 5: run_curve_tile_vq<5, RAT, F, T, VQ>(a, tl); break;
-        case 6: run_curve_tile_vq<6, RAT, F, T, VQ>(a, tl); break;
-        case 7: run_curve_tile_vq<7, RAT, F, T, VQ>(a, tl); break;
-        case 8: run_curve_tile_vq<8, RAT, F, T, VQ>(a, tl); break;
-        case 9: run_curve_tile_vq<9, RAT, F, T, VQ>(a, tl); break;
-        case 10: run_curve_tile_vq<10, RAT, F, T, VQ>(a, tl); break;
-        case 11: run_curve_tile_vq<11, RAT, F, T, VQ>(a, tl); break;
-        case 12: run_curve_tile_vq<12, RAT, F, T, VQ>(a, tl); break;
-        case 13: run_curve_tile_vq<13, RAT, F, T, VQ>(a, tl); break;
-        case 14: run_curve_tile_vq<14, RAT, F, T, VQ>(a, tl); break;
-        default: run_curve_tile_vq<15, RAT, F, T, VQ>(a, tl); break;
+        case 1: run_curve_tile_vq<1, RAT, F, T, VQ>(a, tl, out); break;
+        case 2: run_curve_tile_vq<2, RAT, F, T, VQ>(a, tl, out); break;
+        case 3: run_curve_tile_vq<3, RAT, F, T, VQ>(a, tl, out); break;
+        case 4: run_curve_tile_vq<4, RAT, F, T, VQ>(a, tl, out); break;
+        case 5: run_curve_tile_vq<5, RAT, F, T, VQ>(a, tl, out); break;
+        case 6: run_curve_tile_vq<6, RAT, F, T, VQ>(a, tl, out); break;
+        case 7: run_curve_tile_vq<7, RAT, F, T, VQ>(a, tl, out); break;
+        case 8: run_curve_tile_vq<8, RAT, F, T, VQ>(a, tl, out); break;
+        case 9: run_curve_tile_vq<9, RAT, F, T, VQ>(a, tl, out); break;
+        case 10: run_curve_tile_vq<10, RAT, F, T, VQ>(a, tl, out); break;
+        case 11: run_curve_tile_vq<11, RAT, F, T, VQ>(a, tl, out); break;
+        case 12: run_curve_tile_vq<12, RAT, F, T, VQ>(a, tl, out); break;
+        case 13: run_curve_tile_vq<13, RAT, F, T, VQ>(a, tl, out); break;
+        case 14: run_curve_tile_vq<14, RAT, F, T, VQ>(a, tl, out); break;
+        default: run_curve_tile_vq<15, RAT, F, T, VQ>(a, tl, out); break;
     }
 }
 
 template <int F, typename T, int VQ>
-__device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) {
+__device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile, float *__restrict__ out) {
     const Tile tl = a.tiles[tile];
-    if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl);
-    else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl);
-    else run_nurbs_tile_dim(a, tl);
+    if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl, out);
+    else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl, out);
+    else run_nurbs_tile_dim(a, tl, out);
 }
 
 // Dynamic schedule: workgroups pull tiles from an atomic counter (the next
@@ -478,10 +478,13 @@ __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile) 
 // faster than three waves without spills); FP16/BF16 storage is faster at the
 // compiler's own choice.
 template <int F, typename T, int VQ>
+// out is also a parameter of its own, declared not to alias anything else the
+// kernel reads, so a lane's loads for its next coordinate or sub-tile need not
+// wait behind its stores.
 __global__ __launch_bounds__(kBlock, (VQ == 4 && std::is_same<T, float>::value) ? 4 : 1) void k_batch_persistent(
-    BatchArgs a) {
+    BatchArgs a, float *__restrict__ out) {
     if (!a.dynamic) {
-        for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T, VQ>(a, tile);
+        for (unsigned int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) run_tile<F, T, VQ>(a, tile, out);
         return;
     }
     __shared__ unsigned int s_tile;
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(kBlock, (VQ == 4 && std::is_same<T, float>::value) 
     __syncthreads();
     while (tile < a.n_tiles) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&a.counters[0], 1u);
-        run_tile<F, T, VQ>(a, tile);
+        run_tile<F, T, VQ>(a, tile, out);
         __syncthreads();
         tile = s_tile;
         __syncthreads();
@@ -513,9 +516,9 @@ __global__ __launch_bounds__(kBlock, (VQ == 4 && std::is_same<T, float>::value) 
 template <int F, typename T>
 int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) {
     if (a.vq == 4)
-        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 4>), dim3(workgroups), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 4>), dim3(workgroups), dim3(kBlock), 0, s, a, a.out);
     else
-        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 1>), dim3(workgroups), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 1>), dim3(workgroups), dim3(kBlock), 0, s, a, a.out);
     BZ_CHECK_LAUNCH("k_batch_persistent");
     return BZ_OK;
 }

@@ -125,6 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
         wz = D >= 6 ? tx_axis_weight(st * st, a.frac_bits, a.rounding) : wst;
     }
     const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.tex + static_cast<size_t>(cl) * DIM * NT);
+    // every coordinate is read before any result is stored (the stores could
+    // alias the texels for the compiler, which would then serialise the reads)
+    float res[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         float L[NT];
@@ -155,8 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_texemu(TexArgs a) {
                 for (int i = 0; i < M - lvl; ++i) lv[i] = lerp(lv[i], lv[i + 1], p);
             v = lv[0];
         }
-        st_stream(a.out + k * a.plane + qg, v);
+        res[k] = v;
     }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) st_stream(a.out + k * a.plane + qg, res[k]);
 }
 
 // TILED: the texels in the 128-byte cache-line tiles of bz_tile_piecewise
@@ -426,6 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_texemu_patch(TexPatchArgs a) {
         wv = tx_axis_weight(v, a.frac_bits, a.rounding);
     }
     const float4 *__restrict__ src = reinterpret_cast<const float4 *>(a.tex + static_cast<size_t>(ol) * DIM * NT);
+    float res[DIM];  // all coordinates read before any store
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         float L[NT];
@@ -460,8 +466,10 @@ __global__ __launch_bounds__(kBlock) void k_texemu_patch(TexPatchArgs a) {
             }
             val = __builtin_fmaf(sv, acc, r0);
         }
-        st_stream(a.out + c * a.plane + qg, val);
+        res[c] = val;
     }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) st_stream(a.out + c * a.plane + qg, res[c]);
 }
 
 template <int MODE>
