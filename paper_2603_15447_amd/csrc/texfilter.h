@@ -18,14 +18,14 @@ __device__ __forceinline__ float tx_round(float f, int F, int rnd) {
 }
 
 // Weight of a two-texel axis sampled at parameter p in [0,1].
+// Branch-free: clamping to [0, 1] before the rounding gives the edge weights
+// 0 and 1 exactly (the rounding keeps both), and NaN passes through.
 __device__ __forceinline__ float tx_axis_weight(float p, int F, int rnd) {
 #pragma clang fp contract(off)
     const float x = 0.25f + 0.5f * p;  // normalised coordinate
     const float xb = 2.0f * x - 0.5f;  // texel-space position, centres at 0 and 1
-    if (xb != xb) return xb;
-    if (xb <= 0.0f) return 0.0f;
-    if (xb >= 1.0f) return 1.0f;
-    return tx_round(xb, F, rnd);
+    const float c = tx_round(__builtin_fminf(__builtin_fmaxf(xb, 0.0f), 1.0f), F, rnd);
+    return xb != xb ? xb : c;
 }
 
 // Bilinear blend of a 2x2 layer L[row*2 + col]: x along a row, y across rows.
