@@ -360,15 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__r
     float loss = 0.0f;
     for (int step = 0; step < n_steps; ++step) {
         // current control points of this lane's curve, from the owning lanes
+        // (a lane-indexed permute through the LDS crossbar: one instruction per
+        // parameter for both curves of the wave, none of them VALU)
         const int pb = __builtin_bit_cast(int, p_own);
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
 #pragma unroll
-            for (int i = 0; i <= D; ++i) {
-                const float lo = __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, k * (D + 1) + i));
-                const float hi = CPW == 2 ? __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, L + k * (D + 1) + i)) : lo;
-                b[k][i] = base == 0 ? lo : hi;
-            }
+            for (int i = 0; i <= D; ++i)
+                b[k][i] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((base + k * (D + 1) + i) << 2, pb));
         const float2 bc = bias[step];
         float gb[DIM][D + 1] = {};
         loss = 0.0f;
