@@ -389,10 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__r
             float tn = adam_c(ts[s], dt, &mts[s], &vts[s], a, bc.x, bc.y);
             ts[s] = tn < 0.0f ? 0.0f : (tn > 1.0f ? 1.0f : tn);
         }
-        loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
         const float mine = reduce_grads<D, DIM, CPW>(gb, sub);
         if (sub < NP && live) p_own = adam_c(p_own, mine, &m_own, &v_own, a, bc.x, bc.y);
     }
+    // only the last step's loss is reported, so only it is summed over the lanes
+    loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
     if (a.loss_part && sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
     if (sub < NP && live) {
         a.ctrl[pidx] = p_own;
