@@ -358,6 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__r
     }
     float b[DIM][D + 1], wv[D + 1] = {};
     float loss = 0.0f;
+    const float two_inv_m = 2.0f * a.inv_m;
     for (int step = 0; step < n_steps; ++step) {
         // current control points of this lane's curve, from the owning lanes
         // (a lane-indexed permute through the LDS crossbar: one instruction per
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_fit_run(FitArgs a, const float2 *__r
             for (int k = 0; k < DIM; ++k) {
                 const float r = C[k] - ys[s][k];
                 loss = __builtin_fmaf(r, r, loss);
-                const float g = 2.0f * r * a.inv_m;
+                const float g = r * two_inv_m;  // = (2r) inv_m exactly: scaling by 2 commutes with rounding
                 dt = __builtin_fmaf(g, dC[k], dt);
 #pragma unroll
                 for (int i = 0; i <= D; ++i) gb[k][i] = __builtin_fmaf(g, B[i], gb[k][i]);
