@@ -528,6 +528,7 @@ def suite_texemu(torch, bz, bz_synth, cpu):
             ms_g = timed(lambda: bz.eval_piecewise_texemu(grid, T_d, 8, rounding, out=out), torch)
             r["grid_layout"] = {"kernel_ms": ms_g, "value": nq / (ms_g * 1e-3) / 1e9,
                                 "roofline": hbm_roof(chain_bytes(nseg, 3, nq), ms_g)}
+            r["gather_ceiling"] = gather_ceiling(torch, bz, tiles, nq, ms)
             bz.eval_piecewise_texemu_tiled(tiles, nseg, 3, T_d, 8, rounding, out=out)  # out: the tiled result again
         if cpu:
             got = out[:, :m].cpu().numpy().astype(np.float64)
