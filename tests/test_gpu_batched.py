@@ -144,7 +144,11 @@ def test_low_precision_storage(orc, dtype):
     rb = bz_synth.Batch(**{**b.__dict__})
     rb.ctrl = dev["ctrl"].float().cpu().numpy()
     rb.w = dev["w"].float().cpu().numpy()
-    assert _err(got, orc.batch_eval(rb), _extents(rb), 16) <= TOL_F32
+    ref = orc.batch_eval(rb)
+    assert _err(got, ref, _extents(rb), 16) <= TOL_F32
+    for vq, window in ((1, 0), (4, 300), (1, 300)):  # both lane mappings, window-major order
+        plan.configure(500, 2, "static", vq, window)
+        assert _err(host(plan(to_dev(b.t))), ref, _extents(rb), 16) <= TOL_F32, (vq, window)
 
 
 @pytest.mark.parametrize("n_t", [16, 8, 4, 12])
