@@ -218,9 +218,34 @@ def cpu_baseline_chain(chain, T, out_dev, budget_s=10.0):
     got = out_dev[:, :m].cpu().numpy().astype(np.float64)
     ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
     err = float(np.abs(got - ref).max() / ext)
+    # one thread beside the OpenMP figure: median of 3 runs over the first 2^20 queries
+    m1 = min(m, 1 << 20)
+    prev = oracle.set_threads(1)
+    try:
+        secs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.chain_eval(chain, T[:m1])
+            secs.append(time.perf_counter() - t0)
+    finally:
+        oracle.set_threads(prev)
+    single = {"value": m1 / sorted(secs)[1] / 1e9, "unit": "G evals/s", "cores": 1,
+              "sample": "median of 3 x %d random T" % m1}
     return {"value": m / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%d x %d random T of the same 2^20-segment chain (FP64 chain definition, OpenMP)"
-                      % (reps, m)}, err
+                      % (reps, m), "host": host_cpu(), "single_thread": single}, err
+
+
+def host_cpu():
+    """The host's CPU model name, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---------------------------------------------------------------- suite

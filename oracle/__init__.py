@@ -45,6 +45,8 @@ def lib():
         build(force=False)
         L = ctypes.CDLL(_LIB)
         L.bzo_max_threads.restype = ctypes.c_int
+        L.bzo_set_threads.restype = ctypes.c_int
+        L.bzo_set_threads.argtypes = [ctypes.c_int]
         L.bzo_fit_loss_grad.restype = ctypes.c_double
         _lib = L
     return _lib
@@ -60,6 +62,11 @@ def _ptr(a):
 
 def max_threads():
     return lib().bzo_max_threads()
+
+
+def set_threads(n):
+    """Thread count of the OpenMP loops from now on; returns the previous one."""
+    return lib().bzo_set_threads(int(n))
 
 
 def _curve_call(fn, ctrl, t, per_object):

@@ -39,6 +39,21 @@ int bzo_max_threads(void)
 #endif
 }
 
+/* Thread count for the parallel loops that follow (timing only: every result
+   is computed per object, so the outputs do not depend on it).  Returns the
+   previous count. */
+int bzo_set_threads(int n)
+{
+#ifdef _OPENMP
+    const int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Exact binomial coefficient (exact in double for n <= 63). */
 static double binom(int n, int k)
 {

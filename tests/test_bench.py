@@ -47,6 +47,31 @@ def test_recorded_traffic_is_bound_to_its_workload():
     assert bench.recorded_traffic("no_such_file.json", 1 << 20, 1 << 24) is None
 
 
+def test_cpu_baseline_leg_reports_both_thread_counts():
+    import torch
+    import oracle
+    chain, T = bz_synth.chain_walk(n_seg=1 << 10, dim=3, n_q=1 << 14, seed=3)
+    ref = oracle.chain_eval(chain, T)
+    before = oracle.max_threads()
+    cb, err = bench.cpu_baseline_chain(chain, T, torch.from_numpy(ref.astype(np.float32)), budget_s=0.2)
+    assert oracle.max_threads() == before  # the single-thread leg puts the thread count back
+    assert cb["kind"] == "oracle" and cb["cores"] == before and cb["value"] > 0
+    assert cb["single_thread"]["cores"] == 1 and cb["single_thread"]["value"] > 0
+    assert err < 1e-6  # FP32 rounding of the oracle's own values
+
+
+def test_oracle_thread_count_does_not_change_results():
+    import oracle
+    chain, T = bz_synth.chain_walk(n_seg=1 << 9, dim=2, n_q=1 << 12, seed=4)
+    a = oracle.chain_eval(chain, T)
+    prev = oracle.set_threads(1)
+    try:
+        b = oracle.chain_eval(chain, T)
+    finally:
+        oracle.set_threads(prev)
+    assert np.array_equal(a, b)
+
+
 def test_roofline_fraction():
     r = bench.hbm_roof(8e9, 1000.0)  # 8 GB in one second
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and abs(r["frac"] - 1e-3) < 1e-12
