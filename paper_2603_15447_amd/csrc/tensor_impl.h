@@ -7,7 +7,9 @@
 //                  block size is a multiple of nv every thread keeps one grid
 //                  column b, contracts the net with the v basis once
 //                  (isoline coefficients R_i(v_b)) and then needs only the u
-//                  basis and du+1 FMAs per coordinate for each of its points.
+//                  basis and du+1 FMAs per coordinate for each of its points;
+//                  the u basis of each row (nu <= block size) comes from a
+//                  table in LDS filled once per workgroup.
 //  k_tensor_points one object per wavefront, random (u,v[,w]) per query,
 //                  4 queries per lane, separable contraction w -> v -> u.
 #pragma once
@@ -50,6 +52,81 @@ __device__ __forceinline__ void basis_at(float x, float (&B)[D + 1]) {
 }
 
 // ------------------------------------------------------------------ VALU grid
+// Column-per-thread body of k_tensor_grid (nv divides the block size): each
+// thread keeps grid column b, contracts the net with the v basis once and
+// evaluates its points of that column with the u basis of their rows.  When nu <= block size the u
+// basis of every row is computed once per workgroup into the LDS table tab_u
+// (the divide and the basis cost more instructions than a row's FMAs and
+// stores).  NU, NV > 0 fix the grid size at compile time (the row loop unrolls,
+// the stores take immediate offsets, and with du = dv the column basis is a row
+// of the same table); 0 takes nu, nv at run time.  Every variant makes the same
+// basis calls on the same parameters, so all give identical values.
+template <int DU, int DV, int DIM, typename T, int BASIS, int NU, int NV>
+__device__ __forceinline__ void grid_columns(const T *__restrict__ P, int nu_rt, int nv_rt, float du_den, float dv_den,
+                                             float *__restrict__ ob, int64_t plane, float *tab_u) {
+    constexpr int NCP = (DU + 1) * (DV + 1);
+    const int nu = NU > 0 ? NU : nu_rt;
+    const int nv = NV > 0 ? NV : nv_rt;
+    const int b = threadIdx.x % nv;
+    const int a0 = threadIdx.x / nv;
+    const int astep = kBlock / nv;
+    const bool table = nu <= kBlock;
+    if (table) {
+        if (static_cast<int>(threadIdx.x) < nu) {
+            float Bu[DU + 1];
+            basis_at<DU, BASIS>(static_cast<float>(threadIdx.x) / du_den, Bu);
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) tab_u[threadIdx.x * (DU + 1) + i] = Bu[i];
+        }
+        __syncthreads();
+    }
+    float Bv[DV + 1];
+    if constexpr (NU > 0 && NU == NV && DU == DV) {
+#pragma unroll
+        for (int j = 0; j <= DV; ++j) Bv[j] = tab_u[b * (DU + 1) + j];
+    } else {
+        basis_at<DV, BASIS>(static_cast<float>(b) / dv_den, Bv);
+    }
+    float R[DIM][DU + 1];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int i = 0; i <= DU; ++i) {
+            float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
+#pragma unroll
+            for (int j = 1; j <= DV; ++j) acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
+            R[c][i] = acc;
+        }
+    float *__restrict__ oc = ob + a0 * nv + b;
+    if constexpr (NU > 0) {
+        static_assert(NU <= kBlock && NU % (kBlock / NV) == 0, "fixed grids fill whole row steps");
+#pragma unroll
+        for (int k = 0; k < NU / (kBlock / NV); ++k) {
+            const int a = a0 + k * (kBlock / NV);
+            float Bu[DU + 1];
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) Bu[i] = tab_u[a * (DU + 1) + i];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) st_stream(oc + c * plane + k * kBlock, dot_basis<DU>(Bu, R[c]));
+        }
+    } else if (table) {
+        for (int a = a0; a < nu; a += astep, oc += kBlock) {
+            float Bu[DU + 1];
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) Bu[i] = tab_u[a * (DU + 1) + i];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) st_stream(oc + c * plane, dot_basis<DU>(Bu, R[c]));
+        }
+    } else {
+        for (int a = a0; a < nu; a += astep, oc += kBlock) {
+            float Bu[DU + 1];
+            basis_at<DU, BASIS>(static_cast<float>(a) / du_den, Bu);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) st_stream(oc + c * plane, dot_basis<DU>(Bu, R[c]));
+        }
+    }
+}
+
 template <int DU, int DV, int DIM, typename T, int BASIS>
 __global__ __launch_bounds__(kBlock) void k_tensor_grid(const T *__restrict__ ctrl, int nu, int nv,
                                                         float *__restrict__ out, int64_t plane, int64_t o0) {
@@ -60,27 +137,10 @@ __global__ __launch_bounds__(kBlock) void k_tensor_grid(const T *__restrict__ ct
     float *__restrict__ ob = out + (o0 + o) * static_cast<int64_t>(npts);
     const float du_den = nu > 1 ? static_cast<float>(nu - 1) : 1.0f;
     const float dv_den = nv > 1 ? static_cast<float>(nv - 1) : 1.0f;
+    __shared__ __align__(16) float tab_u[kBlock * (DU + 1)];
     if (kBlock % nv == 0) {
-        const int b = threadIdx.x % nv;
-        const int astep = kBlock / nv;
-        float Bv[DV + 1];
-        basis_at<DV, BASIS>(static_cast<float>(b) / dv_den, Bv);
-        float R[DIM][DU + 1];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-#pragma unroll
-            for (int i = 0; i <= DU; ++i) {
-                float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
-#pragma unroll
-                for (int j = 1; j <= DV; ++j) acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
-                R[c][i] = acc;
-            }
-        for (int a = threadIdx.x / nv; a < nu; a += astep) {
-            float Bu[DU + 1];
-            basis_at<DU, BASIS>(static_cast<float>(a) / du_den, Bu);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) st_stream(ob + c * plane + a * nv + b, dot_basis<DU>(Bu, R[c]));
-        }
+        if (nu == 32 && nv == 32) grid_columns<DU, DV, DIM, T, BASIS, 32, 32>(P, nu, nv, du_den, dv_den, ob, plane, tab_u);
+        else grid_columns<DU, DV, DIM, T, BASIS, 0, 0>(P, nu, nv, du_den, dv_den, ob, plane, tab_u);
     } else {
         for (int p = threadIdx.x; p < npts; p += kBlock) {
             const int a = p / nv, b = p - (p / nv) * nv;

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("du,dv", [(1, 1), (2, 3), (3, 3), (4, 2), (4, 4), (1, 4)])
-@pytest.mark.parametrize("nu,nv", [(32, 32), (5, 16), (9, 7), (3, 33), (1, 1)])
+@pytest.mark.parametrize("nu,nv", [(32, 32), (5, 16), (9, 7), (3, 33), (1, 1), (300, 8), (129, 2)])
 def test_grid_valu(orc, du, dv, nu, nv):
     for dim in (3, 1, 4):
         P = bz_synth.patches(n_obj=19, du=du, dv=dv, dim=dim, seed=du * 10 + dv + dim)
