@@ -30,17 +30,21 @@ enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2, MF_F16X3 = 3 };
 
 // Bicubic patches on a 32 x 32 grid.  Rows of the contraction are the
 // (patch, coordinate) pairs, i.e. the control-point array read as
-// [n_obj*dim][16]; each wave owns 32 rows and sweeps the 32 grid rows a,
-// issuing per grid row the MFMA(s) of a 32 x 32 x 16 product and storing the
-// 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
+// [n_obj*dim][16]; each workgroup owns 32 rows and its four waves take the 32
+// grid rows a in turn (wave w: a = w, w + 4, ...), so the 4 KB output block of
+// a row is written front to back, four consecutive lines at a time, rather
+// than one line at a time over a single wave's lifetime.
+// Per grid row a wave issues the MFMA(s) of a 32 x 32 x 16 product and stores
+// the 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
 // Output-tile layout of the 32x32 MFMAs: lane l holds column l%32 and, in
 // accumulator register r, row 8*(r/4) + 4*(l/32) + r%4.
 template <int ENG>
 __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_rows, FastDiv div_dim,
                                                         float *__restrict__ out, int64_t plane, int64_t o0) {
     const int lane = threadIdx.x & 63;
-    const uint32_t row0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 32;
-    if (row0 >= n_rows) return;
+    constexpr int kWaves = kBlock / 64;
+    const int a_begin = threadIdx.x >> 6;  // grid rows a_begin, a_begin + kWaves, ...
+    const uint32_t row0 = blockIdx.x * 32;
     const int col = lane & 31, kh = lane >> 5;
     const uint32_t arow = min(row0 + col, n_rows - 1);
     float A[16];
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
 #pragma unroll
         for (int r = 0; r < 16; ++r) unscale[r] = __shfl(inv, 8 * (r / 4) + 4 * kh + (r % 4));
     }
-    for (int a = 0; a < 32; ++a) {
+    for (int a = a_begin; a < 32; a += kWaves) {
         float Bu[4];
         bernstein_basis<3>(static_cast<float>(a) / 31.0f, Bu);
         v16f acc = {};
@@ -188,7 +192,7 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                 const FastDiv dd = make_fastdiv(static_cast<uint32_t>(dim));
                 for (int64_t r0 = 0; r0 < rows; r0 += rows_per) {
                     const uint32_t nr = static_cast<uint32_t>(std::min(rows_per, rows - r0));
-                    const uint32_t blocks = (nr + 127) / 128;
+                    const uint32_t blocks = (nr + 31) / 32;
                     const float *c0 = static_cast<const float *>(ctrl) + r0 * 16;
                     const int64_t o0 = r0 / dim;
                     if (engine == BZ_TP_MFMA_F32)
