@@ -59,8 +59,8 @@ __device__ __forceinline__ void basis_at(float x, float (&B)[D + 1]) {
 // (the divide and the basis cost more instructions than a row's FMAs and
 // stores).  NU, NV > 0 fix the grid size at compile time (the row loop unrolls,
 // the stores take immediate offsets, and with du = dv the column basis is a row
-// of the same table); 0 takes nu, nv at run time.  Every variant makes the same
-// basis calls on the same parameters, so all give identical values.
+// of the same table); 0 takes nu, nv at run time.  Every variant evaluates the
+// same basis at the same parameters a/(nu-1), b/(nv-1).
 template <int DU, int DV, int DIM, typename T, int BASIS, int NU, int NV>
 __device__ __forceinline__ void grid_columns(const T *__restrict__ P, int nu_rt, int nv_rt, float du_den, float dv_den,
                                              float *__restrict__ ob, int64_t plane, float *tab_u) {
