@@ -57,6 +57,25 @@ def test_nan_and_extrapolation(orc):
         np.testing.assert_allclose(got[:, :, 1:], ref, rtol=0, atol=1e-5)
 
 
+@pytest.mark.parametrize("n_t", [64, 192, 256, 512, 768])
+@pytest.mark.parametrize("method", METHODS)
+def test_curves_wave_uniform_modes(orc, n_t, method):
+    """n_t a multiple of 64 (one curve per wavefront) or of 256 (256 queries of
+    one curve per wavefront, four per lane): degrees 1..15, dims 1..4, shared
+    and per-curve t, FP32 / FP16 / BF16 storage, a curve count that leaves the
+    last workgroup partly empty."""
+    cases = ((1, 3, False, None), (3, 1, True, None), (7, 2, False, torch.float16), (15, 4, True, None),
+             (3, 3, False, torch.bfloat16), (5, 3, True, torch.float16))
+    for degree, dim, per_object, dtype in cases:
+        ctrl, t = bz_synth.random_curves(21, degree, dim, n_t, seed=n_t + 16 * degree + dim, per_object=per_object)
+        dc = to_dev(ctrl) if dtype is None else to_dev(ctrl).to(dtype)
+        pts = dc.float().cpu().numpy()
+        got = host(bz.eval_bezier(dc, to_dev(t), method))
+        ref = orc.bezier_decasteljau(pts, t, per_object)
+        tol = TOL_F32 if (method != "seiler" or degree <= 12) else 4 * TOL_F32
+        assert bbox_err(got, ref, extents(pts), n_t) <= tol, (n_t, degree, dim, per_object, dtype, method)
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 def test_low_precision_storage(orc, dtype):
     """FP16/BF16 control points, FP32 arithmetic: exact-to-FP32 on the rounded
@@ -75,8 +94,9 @@ def test_low_precision_storage(orc, dtype):
 
 
 @pytest.mark.parametrize("degree", [2, 3, 5, 8, 15])
-def test_seiler_terms_and_eval(orc, degree):
-    ctrl, t = bz_synth.random_curves(70, degree, 3, 33, seed=10 + degree)
+@pytest.mark.parametrize("n_t", [33, 256])
+def test_seiler_terms_and_eval(orc, degree, n_t):
+    ctrl, t = bz_synth.random_curves(70, degree, 3, n_t, seed=10 + degree)
     sc = bz.bezier_to_seiler(to_dev(ctrl))
     ref_sc = orc.seiler_from_bezier(ctrl)
     scale = np.abs(ref_sc).max(axis=2, keepdims=True) + 1.0
@@ -84,7 +104,7 @@ def test_seiler_terms_and_eval(orc, degree):
     got = host(bz.eval_seiler(sc, to_dev(t)))
     ref = orc.bezier_decasteljau(ctrl, t, True)
     tol = TOL_F32 if degree <= 12 else 4 * TOL_F32
-    assert bbox_err(got, ref, extents(ctrl), 33) <= tol
+    assert bbox_err(got, ref, extents(ctrl), n_t) <= tol
 
 
 @pytest.mark.parametrize("degree", [1, 2, 3, 6, 11, 15])
