@@ -29,26 +29,32 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2, MF_F16X3 = 3 };
 
 // Bicubic patches on a 32 x 32 grid.  Rows of the contraction are the
-// (patch, coordinate) pairs, i.e. the control-point array read as
-// [n_obj*dim][16]; each workgroup owns 32 rows and its four waves take the 32
-// grid rows a in turn (wave w: a = w, w + 4, ...), so the 4 KB output block of
-// a row is written front to back, four consecutive lines at a time, rather
-// than one line at a time over a single wave's lifetime.
+// (patch, coordinate) pairs of the control-point array read as
+// [n_obj*dim][16]; each workgroup owns the 32 rows of one coordinate c of 32
+// consecutive patches, so its whole output is one contiguous 128 KB block of
+// plane c, addressed from a wave-uniform base with a 32-bit lane offset.  Its
+// four waves take the 32 grid rows a in turn (wave w: a = w, w + 4, ...), so
+// the block is written front to back, four consecutive lines per row at a
+// time.
 // Per grid row a wave issues the MFMA(s) of a 32 x 32 x 16 product and stores
 // the 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
 // Output-tile layout of the 32x32 MFMAs: lane l holds column l%32 and, in
 // accumulator register r, row 8*(r/4) + 4*(l/32) + r%4.
 template <int ENG>
-__global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_rows, FastDiv div_dim,
+__global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_patches, uint32_t dim,
                                                         float *__restrict__ out, int64_t plane, int64_t o0) {
     const int lane = threadIdx.x & 63;
     constexpr int kWaves = kBlock / 64;
     const int a_begin = threadIdx.x >> 6;  // grid rows a_begin, a_begin + kWaves, ...
-    const uint32_t row0 = blockIdx.x * 32;
+    const uint32_t g = blockIdx.x / dim;     // block of 32 patches
+    const uint32_t c = blockIdx.x - g * dim;  // coordinate
+    const uint32_t p0 = g * 32;
+    const uint32_t n_valid = min(32u, n_patches - p0);
     const int col = lane & 31, kh = lane >> 5;
-    const uint32_t arow = min(row0 + col, n_rows - 1);
+    const uint32_t prow = p0 + min(static_cast<uint32_t>(col), n_valid - 1);
     float A[16];
-    const float4 *__restrict__ a4 = reinterpret_cast<const float4 *>(ctrl + static_cast<size_t>(arow) * 16);
+    const float4 *__restrict__ a4 =
+        reinterpret_cast<const float4 *>(ctrl + (static_cast<size_t>(prow) * dim + c) * 16);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const float4 v = a4[e];
@@ -59,17 +65,10 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
     }
     float Bv[4];
     bernstein_basis<3>(static_cast<float>(col) / 31.0f, Bv);
-    // output addresses of this lane's 16 rows (clamped rows are never stored)
-    int64_t obase[16];
-    bool ok[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const uint32_t row = row0 + 8 * (r / 4) + 4 * kh + (r % 4);
-        ok[r] = row < n_rows;
-        const uint32_t o = fdiv(row, div_dim);
-        const uint32_t c = row - o * div_dim.d;
-        obase[r] = c * plane + (o0 + o) * 1024 + col;
-    }
+    // accumulator row r of this lane is patch p0 + 8*(r/4) + 4*kh + r%4; its
+    // points start (8*(r/4) + r%4) * 1024 floats after the lane's own base
+    float *__restrict__ wb = out + static_cast<int64_t>(c) * plane + (o0 + p0) * 1024;
+    const uint32_t lane_off = 4 * kh * 1024 + col;
     v8bf Ab;
     v8h Ah, Al;
     float unscale[16];
@@ -139,9 +138,16 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
             }
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, Bh, acc, 0, 0, 0);
         }
+        const uint32_t off = lane_off + a * 32;
+        if (n_valid == 32) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (ok[r]) st_stream(out + obase[r] + a * 32, acc[r]);
+            for (int r = 0; r < 16; ++r) st_stream(wb + off + (8 * (r / 4) + r % 4) * 1024, acc[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (8 * (r / 4) + 4 * kh + r % 4 < static_cast<int>(n_valid))
+                    st_stream(wb + off + (8 * (r / 4) + r % 4) * 1024, acc[r]);
+        }
     }
 }
 
@@ -187,22 +193,20 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                     BZ_CHECK_LAUNCH("k_tensor_grid");
                 }
             } else {
-                const int64_t rows_per = (int64_t(1) << 24) / dim * dim;  // whole patches per launch
-                const int64_t rows = n_obj * dim;
-                const FastDiv dd = make_fastdiv(static_cast<uint32_t>(dim));
-                for (int64_t r0 = 0; r0 < rows; r0 += rows_per) {
-                    const uint32_t nr = static_cast<uint32_t>(std::min(rows_per, rows - r0));
-                    const uint32_t blocks = (nr + 31) / 32;
-                    const float *c0 = static_cast<const float *>(ctrl) + r0 * 16;
-                    const int64_t o0 = r0 / dim;
+                const int64_t per = int64_t(1) << 22;  // patches per launch
+                const uint32_t ud = static_cast<uint32_t>(dim);
+                for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
+                    const uint32_t np = static_cast<uint32_t>(std::min(per, n_obj - o0));
+                    const uint32_t blocks = (np + 31) / 32 * ud;
+                    const float *c0 = static_cast<const float *>(ctrl) + o0 * dim * 16;
                     if (engine == BZ_TP_MFMA_F32)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
                     else if (engine == BZ_TP_MFMA_BF16)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
                     else if (engine == BZ_TP_MFMA_F16)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
                     else
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16X3>), dim3(blocks), dim3(kBlock), 0, s, c0, nr, dd, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16X3>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
                     BZ_CHECK_LAUNCH("k_tensor_mfma");
                 }
             }
