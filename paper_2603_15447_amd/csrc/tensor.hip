@@ -32,22 +32,37 @@ enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2, MF_F16X3 = 3 };
 // (patch, coordinate) pairs of the control-point array read as
 // [n_obj*dim][16]; each workgroup owns the 32 rows of one coordinate c of 32
 // consecutive patches, so its whole output is one contiguous 128 KB block of
-// plane c, addressed from a wave-uniform base with a 32-bit lane offset.  Its
-// four waves take the 32 grid rows a in turn (wave w: a = w, w + 4, ...), so
+// plane c, addressed from a wave-uniform base with a 32-bit lane offset.  The
+// 32 grid rows a go to kMfmaGridSplit<ENG> workgroups in equal ranges, whose
+// four waves take them in turn (wave w: a = first + w, first + w + 4, ...), so
 // the block is written front to back, four consecutive lines per row at a
-// time.
+// time.  The cubic basis at the 32 grid parameters comes from a 512-byte LDS
+// table filled once per workgroup.
 // Per grid row a wave issues the MFMA(s) of a 32 x 32 x 16 product and stores
 // the 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
 // Output-tile layout of the 32x32 MFMAs: lane l holds column l%32 and, in
 // accumulator register r, row 8*(r/4) + 4*(l/32) + r%4.
+// Workgroups per (32 patches, coordinate): the grid rows are split over
+// kMfmaGridSplit<ENG> workgroups.  The one-MFMA engines (BF16, FP16) run
+// faster with short waves; FP32 (eight MFMAs per grid row) and FP16x3 (three,
+// plus the operand splits) draw enough power that more parallel work only
+// lowers the sustained clock, so they keep all 32 rows in one workgroup.
+template <int ENG>
+constexpr int kMfmaGridSplit = (ENG == MF_BF16 || ENG == MF_F16) ? 4 : 1;
+
 template <int ENG>
 __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_patches, uint32_t dim,
                                                         float *__restrict__ out, int64_t plane, int64_t o0) {
     const int lane = threadIdx.x & 63;
     constexpr int kWaves = kBlock / 64;
-    const int a_begin = threadIdx.x >> 6;  // grid rows a_begin, a_begin + kWaves, ...
-    const uint32_t g = blockIdx.x / dim;     // block of 32 patches
-    const uint32_t c = blockIdx.x - g * dim;  // coordinate
+    constexpr int kSplit = kMfmaGridSplit<ENG>;
+    constexpr int kRowsPerBlock = 32 / kSplit;
+    const uint32_t part = blockIdx.x % kSplit;
+    const uint32_t bi = blockIdx.x / kSplit;
+    const int a_begin = part * kRowsPerBlock + (threadIdx.x >> 6);  // then + kWaves, ...
+    const int a_end = (part + 1) * kRowsPerBlock;
+    const uint32_t g = bi / dim;     // block of 32 patches
+    const uint32_t c = bi - g * dim;  // coordinate
     const uint32_t p0 = g * 32;
     const uint32_t n_valid = min(32u, n_patches - p0);
     const int col = lane & 31, kh = lane >> 5;
@@ -63,8 +78,22 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
         A[4 * e + 2] = v.z;
         A[4 * e + 3] = v.w;
     }
+    // cubic Bernstein basis at the 32 grid parameters j/31, once per workgroup
+    __shared__ __align__(16) float tab[32 * 4];
+    if (threadIdx.x < 32) {
+        float B[4];
+        bernstein_basis<3>(static_cast<float>(threadIdx.x) / 31.0f, B);
+        *reinterpret_cast<float4 *>(tab + 4 * threadIdx.x) = make_float4(B[0], B[1], B[2], B[3]);
+    }
+    __syncthreads();
     float Bv[4];
-    bernstein_basis<3>(static_cast<float>(col) / 31.0f, Bv);
+    {
+        const float4 v = *reinterpret_cast<const float4 *>(tab + 4 * col);
+        Bv[0] = v.x;
+        Bv[1] = v.y;
+        Bv[2] = v.z;
+        Bv[3] = v.w;
+    }
     // accumulator row r of this lane is patch p0 + 8*(r/4) + 4*kh + r%4; its
     // points start (8*(r/4) + r%4) * 1024 floats after the lane's own base
     float *__restrict__ wb = out + static_cast<int64_t>(c) * plane + (o0 + p0) * 1024;
@@ -96,9 +125,15 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
 #pragma unroll
         for (int r = 0; r < 16; ++r) unscale[r] = __shfl(inv, 8 * (r / 4) + 4 * kh + (r % 4));
     }
-    for (int a = a_begin; a < 32; a += kWaves) {
+    for (int a = a_begin; a < a_end; a += kWaves) {
         float Bu[4];
-        bernstein_basis<3>(static_cast<float>(a) / 31.0f, Bu);
+        {
+            const float4 v = *reinterpret_cast<const float4 *>(tab + 4 * a);
+            Bu[0] = v.x;
+            Bu[1] = v.y;
+            Bu[2] = v.z;
+            Bu[3] = v.w;
+        }
         v16f acc = {};
         if constexpr (ENG == MF_F32) {
 #pragma unroll
@@ -197,16 +232,20 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                 const uint32_t ud = static_cast<uint32_t>(dim);
                 for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
                     const uint32_t np = static_cast<uint32_t>(std::min(per, n_obj - o0));
-                    const uint32_t blocks = (np + 31) / 32 * ud;
+                    const uint32_t blocks = (np + 31) / 32 * ud;  // times the engine's grid split
                     const float *c0 = static_cast<const float *>(ctrl) + o0 * dim * 16;
                     if (engine == BZ_TP_MFMA_F32)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks * kMfmaGridSplit<MF_F32>), dim3(kBlock), 0, s,
+                                           c0, np, ud, out, plane, o0);
                     else if (engine == BZ_TP_MFMA_BF16)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_BF16>), dim3(blocks * kMfmaGridSplit<MF_BF16>), dim3(kBlock), 0,
+                                           s, c0, np, ud, out, plane, o0);
                     else if (engine == BZ_TP_MFMA_F16)
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16>), dim3(blocks * kMfmaGridSplit<MF_F16>), dim3(kBlock), 0, s,
+                                           c0, np, ud, out, plane, o0);
                     else
-                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16X3>), dim3(blocks), dim3(kBlock), 0, s, c0, np, ud, out, plane, o0);
+                        hipLaunchKernelGGL((k_tensor_mfma<MF_F16X3>), dim3(blocks * kMfmaGridSplit<MF_F16X3>), dim3(kBlock), 0,
+                                           s, c0, np, ud, out, plane, o0);
                     BZ_CHECK_LAUNCH("k_tensor_mfma");
                 }
             }
