@@ -57,8 +57,13 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
     constexpr int kWaves = kBlock / 64;
     constexpr int kSplit = kMfmaGridSplit<ENG>;
     constexpr int kRowsPerBlock = 32 / kSplit;
-    const uint32_t part = blockIdx.x % kSplit;
-    const uint32_t bi = blockIdx.x / kSplit;
+    // Workgroups are dealt to the 8 XCDs in turn; the kSplit parts of a row
+    // block are numbered 8 apart so that they run on one XCD and fetch the
+    // block's control points into one L2.  Numbers past the last block exit.
+    const uint32_t xcd = blockIdx.x % 8, rest = blockIdx.x / 8;
+    const uint32_t part = kSplit > 1 ? rest % kSplit : 0;
+    const uint32_t bi = kSplit > 1 ? (rest / kSplit) * 8 + xcd : blockIdx.x;
+    if (bi >= (n_patches + 31) / 32 * dim) return;
     const int a_begin = part * kRowsPerBlock + (threadIdx.x >> 6);  // then + kWaves, ...
     const int a_end = (part + 1) * kRowsPerBlock;
     const uint32_t g = bi / dim;     // block of 32 patches
@@ -232,7 +237,8 @@ extern "C" int bz_eval_tensor_patch(const void *ctrl, int dtype, int64_t n_obj, 
                 const uint32_t ud = static_cast<uint32_t>(dim);
                 for (int64_t o0 = 0; o0 < n_obj; o0 += per) {
                     const uint32_t np = static_cast<uint32_t>(std::min(per, n_obj - o0));
-                    const uint32_t blocks = (np + 31) / 32 * ud;  // times the engine's grid split
+                    // row blocks, rounded up to whole rounds of the 8 XCDs, times the engine's grid split
+                    const uint32_t blocks = ((np + 31) / 32 * ud + 7) / 8 * 8;
                     const float *c0 = static_cast<const float *>(ctrl) + o0 * dim * 16;
                     if (engine == BZ_TP_MFMA_F32)
                         hipLaunchKernelGGL((k_tensor_mfma<MF_F32>), dim3(blocks * kMfmaGridSplit<MF_F32>), dim3(kBlock), 0, s,
