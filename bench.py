@@ -52,6 +52,13 @@ def chain_bytes(n_seg, dim, n_q):
     return (n_seg + 1) * 2 * dim * 4 + n_q * 4 + n_q * dim * 4
 
 
+def particle_frame_bytes(n):
+    """Algorithmic HBM bytes of one particle frame: the phase T read and
+    written, the speed read, three coordinates and the shade written (the
+    16-segment ring itself stays in cache)."""
+    return n * (4 + 4 + 4 + 3 * 4 + 4)
+
+
 def recorded_traffic(name, n_seg, n_q):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source has changed since the counters were taken or
@@ -595,8 +602,8 @@ def suite_particles(torch, bz, bz_synth, cpu):
                 ms = graph_time_ms(lambda: bz.particles_step(m, rings[m], 16, T_d, s_d, 1 / 60, K, 64, pos, shade),
                                    torch)
                 row[m] = {"ms_per_frame": ms, "G particles/s": n / (ms * 1e-3) / 1e9}
-            # frame bytes: T read + written, speed read, 3 coordinates and the shade written
-            row["hbm_frac_polynomial"] = n * 24 / (row["polynomial"]["ms_per_frame"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+            row["hbm_frac_polynomial"] = (particle_frame_bytes(n) / (row["polynomial"]["ms_per_frame"] * 1e-3) / 1e9
+                                          / HBM_PEAK_GBS)
             # consumer: K FMAs = 2K flop per particle
             row["consumer_alu_frac_polynomial"] = (2 * K * n / (row["polynomial"]["ms_per_frame"] * 1e-3) / 1e12
                                                    / FP32_VALU_PEAK_TFLOPS)

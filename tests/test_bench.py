@@ -27,6 +27,11 @@ def test_chain_bytes():
     assert bench.chain_bytes(1, 1, 0) == 16
 
 
+def test_particle_frame_bytes():
+    # T in and out, speed in, x y z out, shade out: seven floats per particle
+    assert bench.particle_frame_bytes(10_000_000) == 10_000_000 * 7 * 4
+
+
 def test_batch_bytes_counts_each_part():
     b = bz_synth.mixed_batch(n_bezier=40, n_nurbs=6, n_t=5, seed=3)
     kind = b.kind_degree >> 8
