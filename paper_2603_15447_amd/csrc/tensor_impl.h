@@ -57,9 +57,10 @@ __device__ __forceinline__ void basis_at(float x, float (&B)[D + 1]) {
 // evaluates its points of that column with the u basis of their rows.  When nu <= block size the u
 // basis of every row is computed once per workgroup into the LDS table tab_u
 // (the divide and the basis cost more instructions than a row's FMAs and
-// stores).  NU, NV > 0 fix the grid size at compile time (the row loop unrolls,
-// the stores take immediate offsets, and with du = dv the column basis is a row
-// of the same table); 0 takes nu, nv at run time.  Every variant evaluates the
+// stores).  NU, NV > 0 fix the grid size at compile time: the row loop
+// unrolls, with du = dv the column basis is a row of the same table, and each
+// column is contracted once, by one thread, and shared with the other threads
+// of that column through LDS; 0 takes nu, nv at run time.  Every variant evaluates the
 // same basis at the same parameters a/(nu-1), b/(nv-1).
 template <int DU, int DV, int DIM, typename T, int BASIS, int NU, int NV>
 __device__ __forceinline__ void grid_columns(const T *__restrict__ P, int nu_rt, int nv_rt, float du_den, float dv_den,
@@ -80,26 +81,46 @@ __device__ __forceinline__ void grid_columns(const T *__restrict__ P, int nu_rt,
         }
         __syncthreads();
     }
-    float Bv[DV + 1];
-    if constexpr (NU > 0 && NU == NV && DU == DV) {
+    // isoline coefficients of column b: R[c][i] = sum_j Bv_j(b) P[c][i][j]
+    auto contract = [&](float (&R)[DIM][DU + 1]) {
+        float Bv[DV + 1];
+        if constexpr (NU > 0 && NU == NV && DU == DV) {
 #pragma unroll
-        for (int j = 0; j <= DV; ++j) Bv[j] = tab_u[b * (DU + 1) + j];
-    } else {
-        basis_at<DV, BASIS>(static_cast<float>(b) / dv_den, Bv);
-    }
-    float R[DIM][DU + 1];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-        for (int i = 0; i <= DU; ++i) {
-            float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
-#pragma unroll
-            for (int j = 1; j <= DV; ++j) acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
-            R[c][i] = acc;
+            for (int j = 0; j <= DV; ++j) Bv[j] = tab_u[b * (DU + 1) + j];
+        } else {
+            basis_at<DV, BASIS>(static_cast<float>(b) / dv_den, Bv);
         }
-    float *__restrict__ oc = ob + a0 * nv + b;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) {
+                float acc = Bv[0] * to_f32<T>(P[c * NCP + i * (DV + 1)]);
+#pragma unroll
+                for (int j = 1; j <= DV; ++j)
+                    acc = __builtin_fmaf(Bv[j], to_f32<T>(P[c * NCP + i * (DV + 1) + j]), acc);
+                R[c][i] = acc;
+            }
+    };
+    float R[DIM][DU + 1];
     if constexpr (NU > 0) {
         static_assert(NU <= kBlock && NU % (kBlock / NV) == 0, "fixed grids fill whole row steps");
+        // the first NV threads contract one column each; the kBlock / NV
+        // threads of a column share it through LDS
+        __shared__ __align__(16) float tab_r[NV * DIM * (DU + 1)];
+        if (static_cast<int>(threadIdx.x) < NV) {
+            float Rc[DIM][DU + 1];
+            contract(Rc);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int i = 0; i <= DU; ++i) tab_r[(b * DIM + c) * (DU + 1) + i] = Rc[c][i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int i = 0; i <= DU; ++i) R[c][i] = tab_r[(b * DIM + c) * (DU + 1) + i];
+        const uint32_t lo = static_cast<uint32_t>(a0 * NV + b);
 #pragma unroll
         for (int k = 0; k < NU / (kBlock / NV); ++k) {
             const int a = a0 + k * (kBlock / NV);
@@ -107,9 +128,13 @@ __device__ __forceinline__ void grid_columns(const T *__restrict__ P, int nu_rt,
 #pragma unroll
             for (int i = 0; i <= DU; ++i) Bu[i] = tab_u[a * (DU + 1) + i];
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) st_stream(oc + c * plane + k * kBlock, dot_basis<DU>(Bu, R[c]));
+            for (int c = 0; c < DIM; ++c) st_stream(ob + c * plane + (lo + k * kBlock), dot_basis<DU>(Bu, R[c]));
         }
-    } else if (table) {
+        return;
+    }
+    contract(R);
+    float *__restrict__ oc = ob + a0 * nv + b;
+    if (table) {
         for (int a = a0; a < nu; a += astep, oc += kBlock) {
             float Bu[DU + 1];
 #pragma unroll
