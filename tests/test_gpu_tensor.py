@@ -94,6 +94,32 @@ def test_grid_config_full_size_sampled(orc):
     del out
 
 
+def test_grid_across_launch_chunks(orc):
+    """2^22 + 40 bicubic patches: the grid engines launch at most 2^22 patches
+    at a time, so the last 40 (a partial block of 32 and 8) come in a second
+    launch with its own offsets into the control points and the 51.5 GB
+    output planes.  Patches on both sides of the boundary and at the ends are
+    checked for the VALU, FP32 and BF16 (four workgroups per block) engines."""
+    n = (1 << 22) + 40
+    P = bz_synth.patches(n_obj=n, seed=77)
+    Pd = to_dev(P)
+    pick = np.array([0, 1, 31, 32, (1 << 22) - 33, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, (1 << 22) + 31,
+                     (1 << 22) + 32, n - 1])
+    ref = orc.tensor_grid(P[pick], 3, 3, 32, 32).reshape(3, len(pick), 1024)
+    idx = torch.from_numpy(pick).to(Pd.device)
+    out = torch.empty((3, n * 1024), dtype=torch.float32, device=Pd.device)
+    for engine in ("valu", "mfma_f32", "mfma_bf16"):
+        out.fill_(float("nan"))
+        bz.eval_tensor_patch(Pd, 3, 3, nu=32, nv=32, engine=engine, out=out)
+        got = out.view(3, n, 1024)[:, idx].cpu().numpy().astype(np.float64)
+        if engine == "mfma_bf16":
+            assert np.abs(got - ref).max() <= MFMA_BOUNDS[engine] + 1e-5, engine
+        else:
+            assert bbox_err(got.reshape(3, -1), ref.reshape(3, -1), extents(P[pick]), 1024) <= TOL_F32, engine
+    del out, Pd
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("degs", [(3, 3, 0), (1, 1, 0), (2, 4, 0), (3, 3, 3), (1, 1, 1), (4, 2, 3), (2, 2, 2)])
 @pytest.mark.parametrize("n_per", [1, 100, 256, 300])
 def test_points(orc, degs, n_per):
