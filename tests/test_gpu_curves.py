@@ -76,6 +76,36 @@ def test_curves_wave_uniform_modes(orc, n_t, method):
         assert bbox_err(got, ref, extents(pts), n_t) <= tol, (n_t, degree, dim, per_object, dtype, method)
 
 
+def test_curves_across_launch_chunks(orc):
+    """2^18 + 5 cubic curves x 4096 t: more than 2^30 queries, so the call is
+    split into launches of whole curves and the last 5 curves come in a second
+    launch with its own control-point offset and global query offset (12.9 GB
+    of output; per-curve t indexed by the global query).  Curves on both sides
+    of the boundary and at the ends are checked, shared and per-curve t."""
+    n_t = 4096
+    per = (1 << 30) // n_t
+    n = per + 5
+    rng = np.random.default_rng(91)
+    ctrl = rng.uniform(-1, 1, size=(n, 3, 4)).astype(np.float32)
+    pick = np.array([0, 1, per - 1, per, per + 1, n - 1])
+    idx = torch.from_numpy(pick).cuda()
+    cd = to_dev(ctrl)
+    out = torch.empty((3, n * n_t), dtype=torch.float32, device=cd.device)
+    t_shared = rng.random(n_t, dtype=np.float32)
+    t_per = rng.random((n, n_t), dtype=np.float32)
+    for t, per_object in ((t_shared, False), (t_per, True)):
+        td = to_dev(t)
+        ref = orc.bezier_decasteljau(ctrl[pick], t[pick] if per_object else t, per_object)
+        for m in METHODS:
+            out.fill_(float("nan"))
+            bz.eval_bezier(cd, td, m, out=out)
+            got = out.view(3, n, n_t)[:, idx].reshape(3, -1).cpu().numpy()
+            assert bbox_err(got, ref, extents(ctrl[pick]), n_t) <= TOL_F32, (m, per_object)
+        del td
+    del out, cd
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 def test_low_precision_storage(orc, dtype):
     """FP16/BF16 control points, FP32 arithmetic: exact-to-FP32 on the rounded
