@@ -120,3 +120,42 @@ def test_tiled_full_chain_config(orc):
     got = host(bz.eval_piecewise_tiled(tiles, grid.shape[0] - 1, 3, to_dev(T)))
     ref = orc.chain_eval(chain, T)
     assert np.abs(got - ref).max() / _chain_extent(chain) <= TOL_F32
+
+
+def test_chains_across_launch_chunks(orc):
+    """2^30 + 777 queries in 2D: the chain evaluators launch at most 2^30
+    queries at a time, so the last 777 come in a second launch that reads T
+    and writes both output planes (stride n_q) at its own offset.  The
+    quadratic chain (grid and tiled layouts) and the two-layer cubic chain
+    (tiled) are checked at queries on both sides of the boundary and at the
+    ends.  T is drawn on the GPU from a seeded generator and the sampled
+    values are read back for the oracle."""
+    import torch
+    n_seg, dim = 1000, 2
+    n_q = (1 << 30) + 777
+    g = torch.Generator(device="cuda")
+    g.manual_seed(123)
+    T = torch.rand(n_q, generator=g, device="cuda", dtype=torch.float32) * n_seg
+    pick = np.array([0, 1, (1 << 30) - 2, (1 << 30) - 1, 1 << 30, (1 << 30) + 1, n_q - 1])
+    idx = torch.from_numpy(pick).cuda()
+    Tp = T[idx].cpu().numpy()
+    out = torch.empty((dim, n_q), dtype=torch.float32, device="cuda")
+    chain, _ = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=1, seed=5)
+    grid = bz.encode_piecewise(to_dev(chain))
+    tiles = bz.tile_piecewise(grid)
+    ref = orc.chain_eval(chain, Tp)
+    for name, run in (("grid", lambda: bz.eval_piecewise(grid, T, out=out)),
+                      ("tiled", lambda: bz.eval_piecewise_tiled(tiles, n_seg, dim, T, out=out))):
+        out.fill_(float("nan"))
+        run()
+        got = out[:, idx].cpu().numpy()
+        assert np.abs(got - ref).max() / _chain_extent(chain) <= TOL_F32, name
+    cchain, _ = bz_synth.cubic_chain_walk(n_seg=n_seg, dim=dim, n_q=1, seed=6)
+    ctiles = bz.tile_piecewise_cubic(bz.encode_piecewise_cubic(to_dev(cchain)))
+    out.fill_(float("nan"))
+    bz.eval_piecewise_cubic_tiled(ctiles, n_seg, dim, T, out=out)
+    got = out[:, idx].cpu().numpy()
+    cref = orc.cubic_chain_eval(cchain, Tp)
+    assert np.abs(got - cref).max() / _chain_extent(cchain) <= TOL_F32, "cubic"
+    del out, T
+    torch.cuda.empty_cache()
