@@ -126,8 +126,8 @@ def test_chains_across_launch_chunks(orc):
     """2^30 + 777 queries in 2D: the chain evaluators launch at most 2^30
     queries at a time, so the last 777 come in a second launch that reads T
     and writes both output planes (stride n_q) at its own offset.  The
-    quadratic chain (grid and tiled layouts) and the two-layer cubic chain
-    (tiled) are checked at queries on both sides of the boundary and at the
+    quadratic chain (grid and tiled layouts, and the tiles through the
+    emulated texture filter) and the two-layer cubic chain (tiled) are checked at queries on both sides of the boundary and at the
     ends.  T is drawn on the GPU from a seeded generator and the sampled
     values are read back for the oracle."""
     import torch
@@ -150,6 +150,14 @@ def test_chains_across_launch_chunks(orc):
         run()
         got = out[:, idx].cpu().numpy()
         assert np.abs(got - ref).max() / _chain_extent(chain) <= TOL_F32, name
+    # the same tiles read through the emulated 8-bit bilinear filter
+    gh = host(grid).astype(np.float32)
+    tref = orc.chain_texemu_eval(gh, Tp, 8, "nearest")
+    out.fill_(float("nan"))
+    bz.eval_piecewise_texemu_tiled(tiles, n_seg, dim, T, 8, "nearest", out=out)
+    got = out[:, idx].cpu().numpy()
+    scale = max(_chain_extent(chain), float(np.abs(gh).max()))
+    assert np.abs(got - tref).max() <= TOL_F32 * scale, "texture emulation"
     cchain, _ = bz_synth.cubic_chain_walk(n_seg=n_seg, dim=dim, n_q=1, seed=6)
     ctiles = bz.tile_piecewise_cubic(bz.encode_piecewise_cubic(to_dev(cchain)))
     out.fill_(float("nan"))
