@@ -120,6 +120,33 @@ def test_grid_across_launch_chunks(orc):
     torch.cuda.empty_cache()
 
 
+def test_points_across_launch_chunks(orc):
+    """2^22 + 5 objects: random-point evaluation launches at most 2^22 objects
+    at a time, so the last 5 come in a second launch with its own offsets into
+    the control points, the parameters and the output planes (stride n *
+    n_per).  Bicubic patches and tricubic volumes (Bernstein and per-axis
+    Seiler form), objects on both sides of the boundary and at the ends."""
+    n = (1 << 22) + 5
+    rng = np.random.default_rng(55)
+    pick = np.array([0, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, n - 1])
+    idx = torch.from_numpy(pick).cuda()
+    for du, dv, dw, n_per in ((3, 3, 0, 3), (3, 3, 3, 1)):
+        ncp = (du + 1) * (dv + 1) * (dw + 1)
+        P = rng.random((n, 3, ncp), dtype=np.float32) * 2.0 - 1.0
+        uvw = rng.random((n, n_per, 3 if dw else 2), dtype=np.float32)
+        ref = orc.tensor_points(P[pick], du, dv, dw, uvw[pick])
+        Pd, ud = to_dev(P), to_dev(uvw)
+        got = bz.eval_tensor_patch(Pd, du, dv, dw, uvw=ud).view(3, n, n_per)[:, idx].reshape(3, -1).cpu().numpy()
+        assert bbox_err(got, ref, extents(P[pick]), n_per) <= TOL_F32, (du, dv, dw)
+        if dw:
+            sc = bz.tensor_to_seiler(Pd, du, dv, dw)
+            got = bz.eval_tensor_seiler(sc, du, dv, dw, uvw=ud).view(3, n, n_per)[:, idx].reshape(3, -1).cpu().numpy()
+            assert bbox_err(got, ref, extents(P[pick]), n_per) <= 2 * TOL_F32, "seiler"
+            del sc
+        del Pd, ud, P
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("degs", [(3, 3, 0), (1, 1, 0), (2, 4, 0), (3, 3, 3), (1, 1, 1), (4, 2, 3), (2, 2, 2)])
 @pytest.mark.parametrize("n_per", [1, 100, 256, 300])
 def test_points(orc, degs, n_per):
