@@ -54,6 +54,39 @@ def test_eval_parity(orc, mode, d, frac_bits, rounding):
         assert bbox_err(got, ref, extents(ctrl), nt_obj) <= TOL_F32, (dim, nt_obj)
 
 
+def test_eval_across_launch_chunks(orc):
+    """2^18 + 5 cubic curve textures x 4096 t: more than 2^30 reads, so the
+    call is split into launches of whole curves; the last 5 curves come in a
+    second launch with its own texture and query offsets (12.9 GB of output).
+    Curves on both sides of the boundary and at the ends, shared and
+    per-curve t, de Casteljau and Seiler textures."""
+    import torch
+    n_t = 4096
+    per = (1 << 30) // n_t
+    n = per + 5
+    rng = np.random.default_rng(93)
+    ctrl = rng.random((n, 3, 4), dtype=np.float32) * 2.0 - 1.0
+    pick = np.array([0, per - 1, per, per + 1, n - 1])
+    idx = torch.from_numpy(pick).cuda()
+    out = torch.empty((3, n * n_t), dtype=torch.float32, device="cuda")
+    t_shared = rng.random(n_t, dtype=np.float32)
+    t_per = rng.random((n, n_t), dtype=np.float32)
+    for mode in ("decasteljau", "seiler"):
+        tex = bz.build_texture(to_dev(ctrl), mode)
+        tex_p = tex[idx].cpu().numpy()
+        for t, per_object in ((t_shared, False), (t_per, True)):
+            td = to_dev(t)
+            out.fill_(float("nan"))
+            bz.eval_texture(tex, 3, mode, td, 8, "nearest", out=out)
+            got = out.view(3, n, n_t)[:, idx].reshape(3, -1).cpu().numpy()
+            ref = orc.tex_eval(tex_p, 3, mode, t[pick] if per_object else t, per_object, 8, "nearest")
+            assert bbox_err(got, ref, extents(ctrl[pick]), n_t) <= TOL_F32, (mode, per_object)
+            del td
+        del tex
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_eval_edges(orc):
     """Clamp-to-edge outside [0,1], endpoints, ties of the weight rule, NaN."""
     ctrl = _curves(9, 3, 2, 530)
