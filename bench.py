@@ -1,29 +1,26 @@
 """Benchmark of the Bezier-family evaluators on one MI355X.
 
-Headline workload (the JSON line's `value`): random-access evaluation of a C0
-quadratic chain in the shared-diagonal (zig-zag) encoding.  A chain of 2^20
-quadratic segments (control points a random walk with U[-0.1,0.1]^3 steps) is
-encoded once into the 2 x (N+1) zig-zag texels, then one step evaluates it at
-2^24 uniform random global parameters T in [0, 2^20) (parameter decode,
-texel gather, bilinear diagonal read, store), inputs resident in HBM.
+Headline workload (the JSON line's `value`): plain FP32 evaluation of 4096
+independent cubic 3D Bezier curves (control points U[-1,1]^3) at 256 uniform
+t_j = j/255, by each of the three forms (de Casteljau lerps, the Bernstein
+polynomial, Seiler interpolation).  One step is one replay of a HIP graph that
+holds the three launches (3 x 2^20 evaluations); the inputs are resident in
+HBM.  The final JSON line also carries, for the metric's comparison, the mixed
+batch in one persistent launch (2^20 Bezier curves of degree 2..15, half
+rational, plus 2^16 cubic NURBS, 16 random t each) with FP32 and with FP16
+storage, each with its max error against the FP64 oracle, and the C0 quadratic
+chain (2^20 segments, 2^24 random T) as a secondary record.
 
-`suite` adds the other workloads, each with its own kernel time, roofline and
-a CPU-baseline leg (the FP64 oracle timed on a bounded sample, whose outputs
-also give the GPU's max error on that sample): plain cubic curves (three
-forms), the C0 cubic chain stored as two stacked zig-zag layers, the
-texture-filter emulation (Fig. 3's three read modes and the chain through an
-emulated bilinear filter, 8-bit weights), the mixed batch in one persistent
-launch (FP32 vs FP16 storage), bicubic patch tessellation (VALU vs
-FP32/BF16/FP16/FP16x3 MFMA), tricubic volumes at random points, the
-fitting loop (fused loss + adjoint + Adam, 200 steps in one register-resident
-launch), and the particle ring of the paper's performance section (frame
-time per position method as the consumer's arithmetic grows).
+`--suite` runs the other workloads as well (each with its own kernel time,
+roofline and CPU-baseline leg) and writes them to a JSON file (`--suite-out`);
+the final stdout line stays compact.
 
-Prints one JSON line.
+Prints one JSON line on stdout (progress goes to stderr).
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -59,19 +56,26 @@ def particle_frame_bytes(n):
     return n * (4 + 4 + 4 + 3 * 4 + 4)
 
 
-def recorded_traffic(name, n_seg, n_q):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source has changed since the counters were taken or
-    the workload is not the one they were taken on."""
+def recorded_traffic(name, workload, key=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when a kernel source it names has changed since the counters were
+    taken, or the workload differs from the one they were taken on.  `key`
+    picks one kernel of a summary that holds several."""
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
-        with open(os.path.join(ROOT, d["kernel_source"]), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-        same = sha == d["kernel_source_sha256"] and (d["n_seg"], d["n_q"]) == (n_seg, n_q)
-    except (OSError, KeyError, ValueError):
+        srcs = d.get("kernel_sources") or {d["kernel_source"]: d["kernel_source_sha256"]}
+        for path, want in srcs.items():
+            with open(os.path.join(ROOT, path), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+        wl = d.get("workload") or {"n_seg": d["n_seg"], "n_q": d["n_q"]}
+        if any(wl.get(k) != v for k, v in workload.items()):
+            return None
+        t = d["traffic_bytes_per_dispatch"]
+        return t.get(key) if key is not None else t
+    except (OSError, KeyError, ValueError, AttributeError):
         return None
-    return d["traffic_bytes_per_dispatch"] if same else None
 
 
 def event_time_ms(fn, iters, torch):
@@ -313,17 +317,20 @@ def suite_plain(torch, bz, bz_synth, cpu):
             "unit": "G evals/s", **res}
 
 
-def batch_bytes(b, es, n_segs, dim):
-    """Algorithmic bytes of one batched launch: control points (and weights of
-    rational objects) once, NURBS segments and breakpoints once, per-object
-    indices, and per query the parameter in and the point out."""
+def batch_bytes(b, es):
+    """Algorithmic bytes of one batched launch, as the caller's problem states
+    them: every control point (dim values) and the weight of every rational or
+    NURBS control point in the storage type (es bytes), every knot (FP32),
+    8 bytes of offsets per object and 8 more per NURBS (its knot offset), and
+    per query the parameter in and the point out (FP32).  The plan's own
+    derived data (class-sorted copies, extracted NURBS segments, tables) is
+    not counted: it is the implementation's choice, not the problem's."""
     kind = b.kind_degree >> 8
     ncp = np.diff(b.cp_offset)
-    bez = kind != 2
-    rd = int((ncp[bez] * dim * es).sum() + (ncp[kind == 1] * es).sum())
-    rd += n_segs * 4 * (dim + 1) * 4 + int((kind == 2).sum()) * 12 + n_segs * 4
-    rd += b.n_obj * 12
-    return rd + b.n_obj * b.n_t * (4 + 4 * dim)
+    nk = np.diff(b.knot_offset)
+    rd = int(ncp.sum()) * b.dim * es + int(ncp[kind != 0].sum()) * es + int(nk.sum()) * 4
+    rd += b.n_obj * 8 + int((kind == 2).sum()) * 8
+    return rd + b.n_obj * b.n_t * (4 + 4 * b.dim)
 
 
 def suite_batched(torch, bz, bz_synth, cpu):
@@ -358,7 +365,7 @@ def suite_batched(torch, bz, bz_synth, cpu):
         tune = plan.autotune(t, out)
         ms = timed(lambda: plan(t, out=out), torch)
         info = plan.info()
-        nbytes = batch_bytes(b, 4 if dt == torch.float32 else 2, info["n_segments"], 3)
+        nbytes = batch_bytes(b, 4 if dt == torch.float32 else 2)
         e = {"kernel_ms": ms, "value": n_q / (ms * 1e-3) / 1e9, "roofline": hbm_roof(nbytes, ms),
              "algorithmic_bytes": nbytes, "autotune": tune, "plan": info}
         if ref is not None:
@@ -671,19 +678,273 @@ def suite_fit(torch, bz, bz_synth, cpu):
                         "200 steps in one register-resident launch", "unit": "G sample-steps/s", **res}
 
 
+FORMS = ("decasteljau", "bernstein", "seiler")
+PLAIN_COUNTERS = "plain_curves_counters.json"
+# The final stdout line is kept below this size (the full suite goes to a file).
+RECORD_MAX_BYTES = 2048
+
+
+def plain_bytes(n_curves, degree, dim, n_t):
+    """Algorithmic bytes of one plain-curve launch with shared t: the points
+    out, the control points and the parameter vector once."""
+    return n_curves * n_t * dim * 4 + n_curves * dim * (degree + 1) * 4 + n_t * 4
+
+
+def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=256):
+    """The plain FP32 workload: n_curves cubic 3D curves x n_t shared t by the
+    three forms.  One step = one replay of a HIP graph holding the three
+    launches.  Returns the headline fields."""
+    log("headline: plain cubic curves, %d x %d t, three forms" % (n_curves, n_t))
+    ctrl, t = bz_synth.plain_curves(n_curves=n_curves, n_t=n_t)
+    c_d, t_d = torch.from_numpy(ctrl).cuda(), torch.from_numpy(t).cuda()
+    n_q = n_curves * n_t
+    outs = {m: torch.empty((3, n_q), device="cuda") for m in FORMS}
+
+    def step_eager():
+        for m in FORMS:
+            bz.eval_bezier(c_d, t_d, m, out=outs[m])
+
+    for _ in range(3):
+        step_eager()
+    torch.cuda.synchronize()
+    # eager steps (one Python call and one launch per form) for context
+    eager_ms = event_time_ms(step_eager, max(steps, 20), torch)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step_eager()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ea.record(s)
+    for _ in range(steps):
+        g.replay()
+    eb.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / steps
+    gpu_ms_per_step = ea.elapsed_time(eb) / steps
+    del g
+    # each form's kernel on its own: a HIP graph of 50 launches replayed,
+    # timed with HIP events on the launch stream (the kernels last a few us)
+    nbytes = plain_bytes(n_curves, 3, 3, n_t)
+    forms = {}
+    for m in FORMS:
+        ms = graph_time_ms(lambda: bz.eval_bezier(c_d, t_d, m, out=outs[m]), torch, launches=50, replays=10)
+        forms[m] = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"]}
+    dom = max(FORMS, key=lambda m: forms[m]["us"])
+    roof = hbm_roof(nbytes, forms[dom]["us"] * 1e-3)
+    roof["kernel"] = "k_curves<%s>" % dom
+    roof["bytes_per_launch"] = nbytes
+    roof["traffic"] = recorded_traffic(PLAIN_COUNTERS, {"n_curves": n_curves, "n_t": n_t}, dom)
+    rec = {"value": 3 * n_q / (ms_per_step * 1e-3) / 1e9, "ms_per_step": ms_per_step,
+           "gpu_ms_per_step": gpu_ms_per_step, "eager_ms_per_step": eager_ms, "forms": forms, "roofline": roof}
+    # 16x the curves (65536 x 256 = 2^24 points per form): past the launch-bound regime
+    c16 = torch.from_numpy(bz_synth.plain_curves(n_curves=16 * n_curves, n_t=n_t)[0]).cuda()
+    o16 = torch.empty((3, 16 * n_q), device="cuda")
+    n16 = plain_bytes(16 * n_curves, 3, 3, n_t)
+    x16 = {}
+    for m in FORMS:
+        ms = timed(lambda: bz.eval_bezier(c16, t_d, m, out=o16), torch, iters=20)
+        x16[m] = {"G/s": 16 * n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(n16, ms)["frac"]}
+    rec["x16"] = x16
+    del c16, o16
+    if cpu:
+        import oracle
+        log("headline: CPU baseline (oracle, three forms)")
+        ref = oracle.bezier_decasteljau(ctrl, t)
+        ext = extents(ctrl)
+        rec["max_err_bbox"] = {m: max_err_bbox(outs[m].cpu().numpy(), ref, ext, n_t) for m in FORMS}
+
+        def oracle_step():
+            oracle.bezier_decasteljau(ctrl, t)
+            oracle.bezier_bernstein(ctrl, t)
+            oracle.seiler_eval(oracle.seiler_from_bezier(ctrl), t)
+
+        _, sec, reps = oracle_timed(oracle_step, budget_s=10.0, max_reps=200)
+        rec["cpu_baseline"] = {"value": 3 * n_q / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
+                               "kind": "oracle",
+                               "sample": "the whole workload (3 forms x %d x %d, FP64), %d repetitions"
+                                         % (n_curves, n_t, reps), "host": host_cpu()}
+    return rec
+
+
+def batched_record(torch, bz, bz_synth, cpu, n_sample=16384):
+    """The mixed batch in one persistent launch, FP32 and FP16 storage.  Max
+    errors on a seeded random sample of objects spread over the whole batch
+    (with the first and last objects included); FP16 is measured against the
+    oracle on the FP32 inputs (its rounding included) and on the rounded
+    inputs."""
+    log("batched: generating 2^20 Bezier + 2^16 NURBS objects")
+    b = bz_synth.mixed_batch()
+    n_q = b.n_obj * b.n_t
+    kd = torch.from_numpy(b.kind_degree.astype(np.int16)).cuda()
+    cpo = torch.from_numpy(b.cp_offset).cuda()
+    ko = torch.from_numpy(b.knot_offset).cuda()
+    kn = torch.from_numpy(b.knots).cuda()
+    t = torch.from_numpy(b.t).cuda()
+    out = torch.empty((3, n_q), device="cuda")
+    idx = np.unique(np.concatenate([np.random.default_rng(7).choice(b.n_obj, n_sample - 2, replace=False),
+                                    [0, b.n_obj - 1]]))
+    sub = b.subset(idx)
+    idx_d = torch.from_numpy(idx).cuda()
+    ref = ext = None
+    res = {}
+    if cpu:
+        import oracle
+        ref, sec, reps = oracle_timed(lambda: oracle.batch_eval(sub), 5.0)
+        res["cpu_baseline"] = {"value": len(idx) * b.n_t / sec / 1e9, "unit": "G evals/s",
+                               "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": "%d random objects x 16 t, FP64" % len(idx)}
+        ext = np.empty(len(idx))
+        for i in range(len(idx)):
+            ext[i] = _box(sub.ctrl[sub.cp_offset[i] * 3:sub.cp_offset[i + 1] * 3].astype(np.float64).reshape(3, -1))
+    for dt, name in ((torch.float32, "fp32"), (torch.float16, "fp16")):
+        log("batched: %s plan + autotune" % name)
+        ctrl = torch.from_numpy(b.ctrl).cuda().to(dt)
+        w = torch.from_numpy(b.w).cuda().to(dt)
+        plan = bz.BatchPlan(kd, cpo, ctrl, w, 3, ko, kn, b.n_t, "bernstein")
+        tune = plan.autotune(t, out)
+        ms = timed(lambda: plan(t, out=out), torch, iters=20)
+        nbytes = batch_bytes(b, 4 if dt == torch.float32 else 2)
+        e = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"],
+             "bytes": nbytes, "config": [tune["workgroups"], tune["tile_multiple"], tune["schedule"],
+                                         tune["queries_per_lane"], tune["window"]]}
+        if ref is not None:
+            got = out.view(3, b.n_obj, b.n_t)[:, idx_d].reshape(3, -1).cpu().numpy()
+            e["max_err_bbox"] = max_err_bbox(got, ref, ext, b.n_t)
+            if name == "fp16":
+                import oracle
+                rsub = dataclasses.replace(sub)
+                rsub.ctrl = torch.from_numpy(sub.ctrl).to(dt).float().numpy()
+                rsub.w = torch.from_numpy(sub.w).to(dt).float().numpy()
+                e["max_err_bbox_vs_rounded_inputs"] = max_err_bbox(got, oracle.batch_eval(rsub), ext, b.n_t)
+        plan.close()
+        del ctrl, w
+        res[name] = e
+    res["fp16_speedup"] = res["fp32"]["us"] / res["fp16"]["us"]
+    return res
+
+
+def _box(P):
+    """Error normaliser of one object's control points P[dim][m]: the largest
+    side of their bounding box, floored by the largest |coordinate|."""
+    return max((P.max(axis=1) - P.min(axis=1)).max(), np.abs(P).max(), 1e-30)
+
+
+def chain_record(torch, bz, bz_synth, cpu, n_seg=1 << 20, n_q=1 << 24):
+    """The C0 quadratic chain (zig-zag texels in cache-line tiles), secondary."""
+    log("chain: generating %d segments, %d T" % (n_seg, n_q))
+    chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=3, n_q=n_q)
+    chain_d, T_d = torch.from_numpy(chain).cuda(), torch.from_numpy(T).cuda()
+    grid = bz.encode_piecewise(chain_d)
+    tiles = bz.tile_piecewise(grid)
+    out = torch.empty((3, n_q), device="cuda")
+    ms = timed(lambda: bz.eval_piecewise_tiled(tiles, n_seg, 3, T_d, out=out), torch, iters=20)
+    nbytes = chain_bytes(n_seg, 3, n_q)
+    rec = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"]}
+    traffic = recorded_traffic(COUNTER_FILES["tiled"], {"n_seg": n_seg, "n_q": n_q})
+    if traffic:
+        rec["traffic_over_algorithmic"] = traffic / nbytes
+        rec["traffic_frac"] = traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if cpu:
+        import oracle
+        m = 1 << 20
+        ref = oracle.chain_eval(chain, T[:m])
+        ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+        rec["max_err_bbox"] = float(np.abs(out[:, :m].cpu().numpy().astype(np.float64) - ref).max() / ext)
+    return rec
+
+
+def _round(x, nd=4):
+    """Floats to `nd` significant digits, recursively (keeps the line short)."""
+    if isinstance(x, float):
+        return float("%.*g" % (nd, x))
+    if isinstance(x, dict):
+        return {k: _round(v, nd) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_round(v, nd) for v in x]
+    return x
+
+
+def compact_record(head, batched, chain, steps, warmup, n_curves, n_t, suite_file=None, suite_summary=None):
+    """The final JSON line: the bench contract's keys with the plain FP32
+    headline, and the batched FP32 / FP16 and chain records beside it."""
+    rec = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "G evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain: %d cubic 3D Bezier curves x %d uniform t, FP32, by de Casteljau, Bernstein "
+                               "and Seiler" % (n_curves, n_t),
+                   "timing": "step = one HIP-graph replay of the 3 launches (3 x %d evals), wall clock"
+                             % (n_curves * n_t),
+                   "n_curves": n_curves, "n_t": n_t, "dim": 3, "degree": 3},
+        "roofline": head["roofline"],
+    }
+    for k in ("cpu_baseline", "max_err_bbox", "forms", "x16", "gpu_ms_per_step", "eager_ms_per_step"):
+        if k in head:
+            rec[k] = head[k]
+    if batched:
+        rec["batched"] = batched
+    if chain:
+        rec["chain"] = chain
+    if suite_summary:
+        rec["suite"] = suite_summary
+    if suite_file:
+        rec["suite_file"] = suite_file
+    rec = _round(rec)
+    for k in ("value", "ms_per_step"):
+        rec[k] = float("%.6g" % head[k])
+    return rec
+
+
+def suite_summary(suite):
+    """One [G/s, roofline fraction] pair per suite workload, for the final line."""
+    out = {}
+
+    def pick(name, e):
+        if isinstance(e, dict) and "value" in e and "roofline" in e:
+            out[name] = [e["value"], e["roofline"]["frac"]]
+
+    for w, rec in suite.items():
+        if not isinstance(rec, dict):
+            continue
+        pick(w, rec)
+        for k, e in rec.items():
+            if k in ("cpu_baseline",):
+                continue
+            pick(w + "." + k, e)
+    return _round(out, 3)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n-seg", type=int, default=1 << 20)
-    ap.add_argument("--n-q", type=int, default=1 << 24)
+    ap.add_argument("--n-curves", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
-    ap.add_argument("--no-suite", action="store_true", help="headline workload only")
-    ap.add_argument("--suite-only", choices=["plain", "chain_footprint", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit", "particles"], default=None,
+    ap.add_argument("--headline-only", action="store_true", help="plain headline only (no batch, no chain)")
+    ap.add_argument("--suite", action="store_true", help="also run every suite workload (written to --suite-out)")
+    ap.add_argument("--suite-out", default="bench_suite.json", help="file for the full suite record")
+    ap.add_argument("--suite-only", choices=["plain", "chain_footprint", "cubic_chain", "texemu", "batched", "patches",
+                                             "volumes", "fit", "particles", "chain"], default=None,
                     help="run one suite workload only (no headline) and print its record")
+    ap.add_argument("--n-seg", type=int, default=1 << 20, help="chain segments (--suite-only chain)")
+    ap.add_argument("--n-q", type=int, default=1 << 24, help="chain queries (--suite-only chain)")
     ap.add_argument("--layout", choices=["grid", "tiled"], default="tiled",
-                    help="placement of the zig-zag texels: column-major grid or 128-byte cache-line tiles")
+                    help="placement of the zig-zag texels for --suite-only chain")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -707,19 +968,57 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}), flush=True)
         return
-    suites = {"plain": suite_plain, "chain_footprint": suite_chain_footprint, "cubic_chain": suite_cubic_chain, "texemu": suite_texemu,
-              "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
+    suites = {"plain": suite_plain, "chain_footprint": suite_chain_footprint, "cubic_chain": suite_cubic_chain,
+              "texemu": suite_texemu, "batched": suite_batched, "patches": suite_patches, "volumes": suite_volumes,
               "fit": suite_fit, "particles": suite_particles}
-    if args.suite_only:
-        print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}), flush=True)
+    if args.suite_only == "chain":
+        print(json.dumps({"chain": suite_chain(torch, bz, bz_synth, args)}), flush=True)
         return
+    if args.suite_only:
+        print(json.dumps({args.suite_only: suites[args.suite_only](torch, bz, bz_synth, not args.no_cpu)}),
+              flush=True)
+        return
+    cpu = not args.no_cpu
+    head = headline_plain(torch, bz, bz_synth, args.steps, args.warmup, cpu, n_curves=args.n_curves)
+    log("headline: %.2f G evals/s (%.4f ms per step)" % (head["value"], head["ms_per_step"]))
+    torch.cuda.empty_cache()
+    batched = chain = None
+    if not args.headline_only:
+        batched = batched_record(torch, bz, bz_synth, cpu)
+        torch.cuda.empty_cache()
+        chain = chain_record(torch, bz, bz_synth, cpu)
+        torch.cuda.empty_cache()
+    summary = suite_file = None
+    if args.suite:
+        suite = {"chain": suite_chain(torch, bz, bz_synth, args)}
+        for name, fn in suites.items():
+            suite[name] = fn(torch, bz, bz_synth, cpu)
+            torch.cuda.empty_cache()
+        with open(args.suite_out, "w") as f:
+            json.dump(suite, f)
+        summary, suite_file = suite_summary(suite), args.suite_out
+    rec = compact_record(head, batched, chain, args.steps, args.warmup, args.n_curves, 256, suite_file, summary)
+    line = json.dumps(rec, separators=(",", ":"))
+    if len(line) > RECORD_MAX_BYTES:  # drop the least important parts rather than overflow
+        for k in ("suite", "x16", "forms"):
+            rec.pop(k, None)
+            line = json.dumps(rec, separators=(",", ":"))
+            if len(line) <= RECORD_MAX_BYTES:
+                break
+    print(line, flush=True)
+
+
+def suite_chain(torch, bz, bz_synth, args):
+    """The C0 quadratic chain in full (both texel layouts, encoder time, the
+    HBM probes, the random-line gather ceiling, counters-based traffic and the
+    CPU baseline)."""
     dim = 3
-    log("headline: generating the chain")
+    log("suite: quadratic chain (generating the chain)")
     chain, T = bz_synth.chain_walk(n_seg=args.n_seg, dim=dim, n_q=args.n_q)
-    chain_d = torch.from_numpy(chain).to(dev)
-    T_d = torch.from_numpy(T).to(dev)
-    grid = torch.empty((args.n_seg + 1, 2, dim), dtype=torch.float32, device=dev)
-    out = torch.empty((dim, args.n_q), dtype=torch.float32, device=dev)
+    chain_d = torch.from_numpy(chain).cuda()
+    T_d = torch.from_numpy(T).cuda()
+    grid = torch.empty((args.n_seg + 1, 2, dim), dtype=torch.float32, device="cuda")
+    out = torch.empty((dim, args.n_q), dtype=torch.float32, device="cuda")
     bz.encode_piecewise(chain_d, out=grid)
     torch.cuda.synchronize()
     enc_ms = event_time_ms(lambda: bz.encode_piecewise(chain_d, out=grid), 5, torch)
@@ -727,70 +1026,30 @@ def main():
     steps = {"grid": lambda: bz.eval_piecewise(grid, T_d, out=out),
              "tiled": lambda: bz.eval_piecewise_tiled(tiles, args.n_seg, dim, T_d, out=out)}
     other = "grid" if args.layout == "tiled" else "tiled"
-    for _ in range(3):
-        steps[other]()
-    other_ms = event_time_ms(steps[other], max(10, args.steps // 4), torch)
-    step = steps[args.layout]
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    kern_ms = event_time_ms(step, args.steps, torch)
-    log("headline: %.2f G evals/s" % (args.n_q / (ms_per_step * 1e-3) / 1e9))
-
+    other_ms = timed(steps[other], torch, iters=50)
+    kern_ms = timed(steps[args.layout], torch, iters=200, warmup=20)
     nbytes = chain_bytes(args.n_seg, dim, args.n_q)
     roof = hbm_roof(nbytes, kern_ms)
-    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout], args.n_seg, args.n_q)
-    rec = {
-        "metric": METRIC,
-        "value": args.n_q / (ms_per_step * 1e-3) / 1e9,
-        "unit": "G evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "C0 piecewise quadratic chain, zig-zag encoded (E=(B+C)/2), %d segments, "
-                               "%d uniform random global T, 3D, FP32" % (args.n_seg, args.n_q),
-                   "n_seg": args.n_seg, "n_q": args.n_q, "dim": dim, "layout": args.layout},
-        "roofline": roof,
-        "kernel": "k_piecewise_eval_tiled" if args.layout == "tiled" else "k_piecewise_eval",
-        "kernel_ms": kern_ms,
-        "algorithmic_bytes": nbytes,
-        "other_layout": {"layout": other, "kernel_ms": other_ms, "value": args.n_q / (other_ms * 1e-3) / 1e9},
-        "encode_ms": enc_ms,
-    }
+    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout], {"n_seg": args.n_seg, "n_q": args.n_q})
+    rec = {"workload": "C0 piecewise quadratic chain, zig-zag encoded (E=(B+C)/2), %d segments, %d uniform random "
+                       "global T, 3D, FP32" % (args.n_seg, args.n_q),
+           "layout": args.layout, "kernel_ms": kern_ms, "value": args.n_q / (kern_ms * 1e-3) / 1e9,
+           "roofline": roof, "algorithmic_bytes": nbytes,
+           "other_layout": {"layout": other, "kernel_ms": other_ms, "value": args.n_q / (other_ms * 1e-3) / 1e9},
+           "encode_ms": enc_ms}
     probe = hbm_probe(torch, bz)
-    probe["headline_frac_of_read"] = roof["achieved"] / probe["read_GB/s"]
+    probe["frac_of_read"] = roof["achieved"] / probe["read_GB/s"]
     rec["hbm_probe"] = probe
     if args.layout == "tiled":
         rec["gather_ceiling"] = gather_ceiling(torch, bz, tiles, args.n_q, kern_ms)
     if roof["traffic"]:
-        # the bytes the gather actually moves (one 128-byte line per query)
         rate = roof["traffic"] / (kern_ms * 1e-3) / 1e9
-        rec["actual_traffic"] = {"GB/s": rate, "frac_of_peak": rate / HBM_PEAK_GBS,
+        rec["actual_traffic"] = {"bytes_per_launch": roof["traffic"], "over_algorithmic": roof["traffic"] / nbytes,
+                                 "GB/s": rate, "frac_of_peak": rate / HBM_PEAK_GBS,
                                  "frac_of_read_probe": rate / probe["read_GB/s"]}
     if not args.no_cpu:
-        log("headline: CPU baseline")
         rec["cpu_baseline"], rec["max_err_bbox"] = cpu_baseline_chain(chain, T, out)
-    del out, grid, tiles, T_d, chain_d
-    torch.cuda.empty_cache()
-    if not args.no_suite:
-        suite = {}
-        for name, fn in suites.items():
-            suite[name] = fn(torch, bz, bz_synth, not args.no_cpu)
-            torch.cuda.empty_cache()
-        rec["suite"] = suite
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 if __name__ == "__main__":

@@ -122,6 +122,26 @@ class Batch:
     def n_obj(self):
         return int(self.kind_degree.shape[0])
 
+    def subset(self, idx):
+        """The objects idx (in that order) as a batch of their own: the same
+        control points, weights, knots and parameters, re-packed with new
+        offsets.  A layout gather only."""
+        idx = np.asarray(idx, dtype=np.int64)
+        ncp = (self.cp_offset[idx + 1] - self.cp_offset[idx])
+        nk = (self.knot_offset[idx + 1] - self.knot_offset[idx])
+        cp = np.zeros(len(idx) + 1, dtype=np.int64)
+        np.cumsum(ncp, out=cp[1:])
+        ko = np.zeros(len(idx) + 1, dtype=np.int64)
+        np.cumsum(nk, out=ko[1:])
+        def ranges(off, scale=1):
+            parts = [np.arange(off[o] * scale, off[o + 1] * scale) for o in idx]
+            return np.concatenate(parts) if parts else np.zeros(0, dtype=np.int64)
+        pts, crd, kts = ranges(self.cp_offset), ranges(self.cp_offset, self.dim), ranges(self.knot_offset)
+        return Batch(dim=self.dim, n_t=self.n_t, kind_degree=self.kind_degree[idx].copy(), cp_offset=cp,
+                     ctrl=np.ascontiguousarray(self.ctrl[crd]), w=np.ascontiguousarray(self.w[pts]),
+                     knot_offset=ko, knots=np.ascontiguousarray(self.knots[kts]),
+                     t=np.ascontiguousarray(self.t[idx]), meta=dict(self.meta))
+
 
 def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_hi=15,
                 knots_lo=8, knots_hi=64, seed=SEEDS["batched"]):

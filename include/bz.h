@@ -72,34 +72,6 @@ int bz_version(void);
 const char *bz_status_string(int code);
 const char *bz_last_error(void);
 
-/* Number of compute units of the current device (0 on failure). */
-int bz_device_cu_count(void);
-
-/*
- * Measured HBM ceiling for the rooflines (the paper's performance section
- * compares against the memory system; MI355X publishes 8 TB/s): a streaming
- * kernel over n floats (n a multiple of 4, buffers 16-byte aligned) with a
- * persistent grid of blocks_per_cu x (CU count) workgroups of 256 threads
- * (blocks_per_cu 1..64), or with blocks_per_cu 0 one 16-byte vector per thread.
- * mode 0: read src (dst[0] is written only if a thread's partial sum equals
- * -1, which non-negative data never gives); 1: write dst; 2: copy src to dst.
- * Timing is the caller's (events around the call).
- */
-int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, int blocks_per_cu, bz_stream stream);
-
-/*
- * Random-line gather ceiling, the access pattern of a chain query (Sec. 2.1:
- * one filtered read per query at an arbitrary position along the zig-zag
- * grid; with the grid in 128-byte tiles that is one line): n_reads reads, read r loading
- * vec16 (1..4) consecutive 16-byte vectors from the start of line
- * floor(h(r) * n_lines / 2^32) of src, h the lowbias32 hash of
- * r * 0x9e3779b9 + 12345 and n_lines = n / 32.  src: n floats (a multiple of
- * 32 below 2^37), 128-byte aligned, device.  sink: one device float, written
- * only if a thread's partial sum equals -1 (never for non-negative data).
- * n_reads 0..2^31-1; 0 launches nothing.  Timing is the caller's.
- */
-int bz_gather_probe(const float *src, int64_t n, int64_t n_reads, int vec16, float *sink, bz_stream stream);
-
 /*
  * Bezier curves (Sec. 2: de Casteljau recursive lerps; Sec. 3: Seiler
  * interpolation; Sec. 5: the Bernstein polynomial form).
@@ -354,9 +326,13 @@ int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw
  * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the knot
  * range) and out[dim][n_obj*n_t] are passed per evaluation (out must not
  * overlap t).  method:
- * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects are evaluated in FP32
- * (no FP64 recomputation: use bz_eval_rational for signed weights).
- * n_obj*n_t must stay below 2^32.
+ * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects whose weights are all
+ * positive are evaluated in FP32 (their conditioning number is 1).  Rational
+ * objects with a weight that is zero, negative or NaN form classes of their
+ * own whose every query takes the conditioning test of bz_eval_rational with
+ * kappa = 64: sum|w_i|B_i > 64 |sum w_i B_i| (or a zero weight sum) sends the
+ * point to FP64 de Casteljau on the homogeneous points.  NURBS weights must
+ * be positive (BZ_ERR_UNSUPPORTED otherwise).  n_obj*n_t must stay below 2^32.
  */
 typedef struct bz_plan_s *bz_plan;
 int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64_t *cp_offset, const void *ctrl,
@@ -433,6 +409,24 @@ int bz_adjoint_bezier(const float *ctrl, const float *w, int64_t n_curves, int d
                       float *grad_t, bz_stream stream);
 
 /*
+ * Gradient of the least-squares fitting loss without an optimiser step (the
+ * derivative of Sec. 2's curves with respect to their control points and
+ * parameters), for callers that run their own optimiser.  Integral curves,
+ * per-curve parameters:
+ *   L = (1/M) sum_q |C(t_q) - y_q|^2,  M = n_curves*n_t,
+ *   ctrl[n_curves][dim][degree+1], t[n_curves][n_t], target y[dim][n_curves*n_t].
+ * Writes (overwrites), each output nullable to skip it:
+ *   loss_part[n_curves]                   curve c's contribution to L (their sum is L)
+ *   grad_ctrl[n_curves][dim][degree+1]    dL/db_i = (2/M) sum_j (C(t_j) - y_j) B_i(t_j)
+ *   grad_t[n_curves][n_t]                 dL/dt_j = (2/M) (C(t_j) - y_j) . C'(t_j), C' the hodograph
+ * The per-curve sums are wave reductions: no atomics, deterministic.  Inputs
+ * are not modified.  Every array is FP32 with 4-byte alignment
+ * (BZ_ERR_ALIGN otherwise); ctrl, t and target are required (BZ_ERR_NULL).
+ */
+int bz_l2_fit_adjoint(const float *ctrl, int64_t n_curves, int degree, int dim, const float *t, int64_t n_t,
+                      const float *target, float *loss_part, float *grad_ctrl, float *grad_t, bz_stream stream);
+
+/*
  * One fused least-squares fitting step for integral curves with per-curve
  * parameters: loss L = (1/M) sum_q |C(t_q) - y_q|^2 (M = n_curves*n_t), its
  * gradients by the adjoint above, and an Adam update (bias-corrected, step
@@ -459,6 +453,37 @@ int bz_fit_adam_step(float *ctrl, float *t, const float *y, int64_t n_curves, in
 int bz_fit_adam_run(float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
                     float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, int first_step, int n_steps, float lr,
                     float beta1, float beta2, float eps, float *loss_part, bz_stream stream);
+
+/*
+ * Measurement utilities.  These are not part of the method: they measure the
+ * memory system the evaluators run on, so that each kernel's rate can be set
+ * against a ceiling measured on the same GPU (beside the published 8 TB/s of
+ * MI355X HBM).
+ *
+ * bz_device_cu_count: number of compute units of the current device (0 on
+ * failure).
+ *
+ * bz_hbm_probe: a streaming kernel over n floats (n a multiple of 4, buffers
+ * 16-byte aligned) with a persistent grid of blocks_per_cu x (CU count)
+ * workgroups of 256 threads (blocks_per_cu 1..64), or with blocks_per_cu 0
+ * one 16-byte vector per thread.  mode 0: read src (dst[0] is written only if
+ * a thread's partial sum equals -1, which non-negative data never gives); 1:
+ * write dst; 2: copy src to dst.  Timing is the caller's (events around the
+ * call).
+ *
+ * bz_gather_probe: the ceiling of a random one-line-per-query gather, the
+ * access pattern of a chain query in cache-line tiles (one window read per
+ * query at an arbitrary position along the chain): n_reads reads, read r
+ * loading vec16 (1..4) consecutive 16-byte vectors from the start of line
+ * floor(h(r) * n_lines / 2^32) of src, h the lowbias32 hash of
+ * r * 0x9e3779b9 + 12345 and n_lines = n / 32.  src: n floats (a multiple of
+ * 32 below 2^37), 128-byte aligned, device.  sink: one device float, written
+ * only if a thread's partial sum equals -1 (never for non-negative data).
+ * n_reads 0..2^31-1; 0 launches nothing.  Timing is the caller's.
+ */
+int bz_device_cu_count(void);
+int bz_hbm_probe(int mode, const float *src, float *dst, int64_t n, int blocks_per_cu, bz_stream stream);
+int bz_gather_probe(const float *src, int64_t n, int64_t n_reads, int vec16, float *sink, bz_stream stream);
 
 #ifdef __cplusplus
 }

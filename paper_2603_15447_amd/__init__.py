@@ -82,6 +82,7 @@ _SIGS = {
     "bz_batch_plan_configure": (_I, [_P, _I64, _I, _I, _I, _I64, _P]),
     "bz_plan_destroy": (_I, [_P]),
     "bz_adjoint_bezier": (_I, [_P, _P, _I64, _I, _I, _P, _I64, _I, _P, _P, _P, _P, _P]),
+    "bz_l2_fit_adjoint": (_I, [_P, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
     "bz_fit_adam_step": (_I, [_P, _P, _P, _I64, _I, _I, _I64, _P, _P, _P, _P, _I, _F, _F, _F, _F, _P, _P]),
     "bz_fit_adam_run": (_I, [_P, _P, _P, _I64, _I, _I, _I64, _P, _P, _P, _P, _I, _I, _F, _F, _F, _F, _P, _P]),
 }
@@ -140,7 +141,15 @@ def _dtype(x):
         raise BzError(ERR_DTYPE, "unsupported storage dtype %s" % x.dtype)
 
 
+def _f32_only(what, *xs):
+    """FP32 is the only type of parameters, gradients and adjoint inputs."""
+    for x in xs:
+        if x is not None and x.dtype != torch.float32:
+            raise BzError(ERR_DTYPE, "%s must be float32 (got %s)" % (what, x.dtype))
+
+
 def _tmode(t, n):
+    _f32_only("t", t)
     if t.dim() == 1:
         return T_SHARED, t.shape[0]
     assert t.dim() == 2 and t.shape[0] == n, "t must be [n_t] or [n_curves, n_t]"
@@ -205,6 +214,7 @@ def encode_piecewise(chain, out=None):
 
 def eval_piecewise(grid, T, out=None):
     """grid[N+1, 2, dim], T[n_q] -> out[dim, n_q]."""
+    _f32_only("grid and T", grid, T)
     nseg = grid.shape[0] - 1
     dim = grid.shape[2]
     nq = T.shape[0]
@@ -225,6 +235,7 @@ def encode_piecewise_cubic(chain, out=None):
 
 def eval_piecewise_cubic(grid, T, out=None):
     """grid[N+1, 2, 2, dim], T[n_q] -> out[dim, n_q]."""
+    _f32_only("grid and T", grid, T)
     nseg, dim = grid.shape[0] - 1, grid.shape[3]
     nq = T.shape[0]
     out = _f32_out((dim, nq), grid.device, out)
@@ -260,6 +271,7 @@ def build_texture(ctrl, mode, out=None):
 def eval_texture(tex, degree, mode, t, frac_bits=8, rounding="nearest", out=None):
     """Sample emulated curve textures tex[n, dim, texels] at t ([n_t] shared
     or [n, n_t]) through the emulated linear filter -> out[dim, n*n_t]."""
+    _f32_only("t", t)
     n, dim, _ = tex.shape
     per_object = t.dim() == 2
     nt = t.shape[-1]
@@ -318,6 +330,7 @@ def tile_piecewise_cubic(grid, out=None):
 
 
 def eval_piecewise_cubic_tiled(tiles, n_seg, dim, T, out=None):
+    _f32_only("tiles and T", tiles, T)
     nq = T.shape[0]
     out = _f32_out((dim, nq), tiles.device, out)
     check(lib().bz_eval_piecewise_cubic_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
@@ -362,6 +375,7 @@ def tile_piecewise(grid, out=None):
 
 
 def eval_piecewise_tiled(tiles, n_seg, dim, T, out=None):
+    _f32_only("tiles and T", tiles, T)
     nq = T.shape[0]
     out = _f32_out((dim, nq), tiles.device, out)
     check(lib().bz_eval_piecewise_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
@@ -370,6 +384,7 @@ def eval_piecewise_tiled(tiles, n_seg, dim, T, out=None):
 
 # ---------------------------------------------------------------- tensor
 def eval_tensor_patch(ctrl, du, dv, dw=0, uvw=None, nu=0, nv=0, engine="valu", out=None):
+    _f32_only("uvw", uvw)
     n, dim, _ = ctrl.shape
     if uvw is None:
         nq, n_per = n * nu * nv, 0
@@ -452,17 +467,38 @@ class BatchPlan:
 
 # ---------------------------------------------------------------- adjoint
 def adjoint_bezier(ctrl, t, grad_out, w=None, need_ctrl=True, need_w=None, need_t=True):
-    """Returns (grad_ctrl, grad_w, grad_t); entries not requested are None."""
+    """Returns (grad_ctrl, grad_w, grad_t), FP32; entries not requested are
+    None.  ctrl, w, t and grad_out must be FP32 (the adjoint's storage type)."""
+    _f32_only("adjoint inputs (ctrl, w, t, grad_out)", ctrl, w, t, grad_out)
     n, dim, dp1 = ctrl.shape
     mode, nt = _tmode(t, n)
     need_w = (w is not None) if need_w is None else need_w
     dev = ctrl.device
-    gc = torch.empty_like(ctrl) if need_ctrl else None
+    gc = torch.empty((n, dim, dp1), dtype=torch.float32, device=dev) if need_ctrl else None
     gw = torch.empty((n, dp1), dtype=torch.float32, device=dev) if need_w else None
     gt = torch.empty((n, nt), dtype=torch.float32, device=dev) if need_t else None
     check(lib().bz_adjoint_bezier(_ptr(ctrl), _ptr(w), n, dp1 - 1, dim, _ptr(t), nt, mode, _ptr(grad_out), _ptr(gc),
                                   _ptr(gw), _ptr(gt), _stream()))
     return gc, gw, gt
+
+
+def l2_fit_adjoint(ctrl, t, y, need_loss=True, need_ctrl=True, need_t=True):
+    """Least-squares loss L = sum |C(t) - y|^2 / (n*n_t) of integral curves
+    ctrl[n, dim, d+1] at per-curve t[n, n_t] against y[dim, n*n_t] (all FP32):
+    returns (loss_part[n], grad_ctrl, grad_t), each None when not requested.
+    No optimiser step; inputs are not modified."""
+    _f32_only("l2_fit_adjoint inputs", ctrl, t, y)
+    n, dim, dp1 = ctrl.shape
+    assert t.dim() == 2 and t.shape[0] == n, "t must be [n_curves, n_t]"
+    nt = t.shape[1]
+    assert tuple(y.shape) == (dim, n * nt)
+    dev = ctrl.device
+    lp = torch.empty(n, dtype=torch.float32, device=dev) if need_loss else None
+    gc = torch.empty((n, dim, dp1), dtype=torch.float32, device=dev) if need_ctrl else None
+    gt = torch.empty((n, nt), dtype=torch.float32, device=dev) if need_t else None
+    check(lib().bz_l2_fit_adjoint(_ptr(ctrl), n, dp1 - 1, dim, _ptr(t), nt, _ptr(y), _ptr(lp), _ptr(gc), _ptr(gt),
+                                  _stream()))
+    return lp, gc, gt
 
 
 def fit_adam_step(ctrl, t, y, m_ctrl, v_ctrl, m_t, v_t, step, lr=1e-2, betas=(0.9, 0.999), eps=1e-8,
@@ -501,8 +537,18 @@ class BezierCurve(torch.autograd.Function):
         need_t = ctx.needs_input_grad[1]
         if need_t and t.dim() != 2:
             raise BzError(ERR_UNSUPPORTED, "gradient w.r.t. a shared t is not provided; pass t as [n, n_t]")
-        gc, gw, gt = adjoint_bezier(ctrl, t, grad_out.contiguous(), w=w, need_ctrl=ctx.needs_input_grad[0],
+        # the adjoint runs in FP32: FP16/BF16 control points and weights are
+        # widened (exactly) for it, and their gradients rounded back to the
+        # storage type torch expects
+        c32 = ctrl.float().contiguous()
+        w32 = w.float().contiguous() if w is not None else None
+        gc, gw, gt = adjoint_bezier(c32, t, grad_out.float().contiguous(), w=w32,
+                                    need_ctrl=ctx.needs_input_grad[0],
                                     need_w=w is not None and ctx.needs_input_grad[2], need_t=need_t)
+        if gc is not None:
+            gc = gc.to(ctrl.dtype)
+        if gw is not None:
+            gw = gw.to(w.dtype)
         return gc, gt, gw, None
 
 

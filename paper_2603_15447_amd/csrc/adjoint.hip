@@ -323,6 +323,70 @@ __global__ __launch_bounds__(kBlock) void k_fit_step(FitArgs a) {
     }
 }
 
+// Gradient of the least-squares loss L = inv_m * sum |C(t) - y|^2 without an
+// optimiser step: per-curve loss contributions, dL/db (one sum per control
+// point, by the same reductions as the fused step) and dL/dt per query.  The
+// lane mapping is that of k_fit_step (two curves per wavefront when a curve
+// has at most 32 control-point coordinates); nothing is updated in place.
+struct L2Args {
+    const float *ctrl, *t, *y;
+    float *loss_part, *gctrl, *gt;
+    int64_t n_curves, n_t, plane;
+    float inv_m;
+};
+
+template <int D, int DIM>
+__global__ __launch_bounds__(kBlock) void k_l2_adjoint(L2Args a) {
+    constexpr int NP = DIM * (D + 1);
+    constexpr int CPW = NP <= 32 ? 2 : 1;
+    constexpr int L = 64 / CPW;
+    const int lane = threadIdx.x & 63, sub = lane % L;
+    const int64_t c0 = CPW * static_cast<int64_t>(__builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)));
+    if (c0 >= a.n_curves) return;
+    const bool has1 = CPW == 2 && c0 + 1 < a.n_curves;
+    const int64_t c = (lane < L || !has1) ? c0 : c0 + 1;
+    const bool live = lane < L || has1;
+    float b[DIM][D + 1], wv[D + 1] = {};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            const float v0 = a.ctrl[c0 * NP + k * (D + 1) + i];
+            const float v1 = a.ctrl[(has1 ? c0 + 1 : c0) * NP + k * (D + 1) + i];
+            b[k][i] = lane < L ? v0 : v1;
+        }
+    float gb[DIM][D + 1] = {};
+    float loss = 0.0f;
+    for (int64_t j = sub; live && j < a.n_t; j += L) {
+        const int64_t q = c * a.n_t + j;
+        const float t = a.t[q];
+        float yv[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) yv[k] = a.y[k * a.plane + q];
+        float B[D + 1], W, C[DIM], dC[DIM];
+        curve_and_derivative<D, DIM, false>(b, wv, t, B, W, C, dC);
+        float dt = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float r = C[k] - yv[k];
+            loss = __builtin_fmaf(r, r, loss);
+            const float g = 2.0f * r * a.inv_m;
+            dt = __builtin_fmaf(g, dC[k], dt);
+#pragma unroll
+            for (int i = 0; i <= D; ++i) gb[k][i] = __builtin_fmaf(g, B[i], gb[k][i]);
+        }
+        if (a.gt) a.gt[q] = dt;
+    }
+    if (a.loss_part) {
+        loss = CPW == 2 ? half_sum(loss) : wave_sum(loss);
+        if (sub == 0 && live) a.loss_part[c] = loss * a.inv_m;
+    }
+    if (a.gctrl) {
+        const float mine = reduce_grads<D, DIM, CPW>(gb, sub);
+        if (sub < NP && live) a.gctrl[c * NP + sub] = mine;
+    }
+}
+
 // Many fitting steps in one launch.  Curves are optimised independently, so
 // a wavefront can keep its curves' samples, parameters and Adam moments in
 // registers across all steps: HBM is read once and written once.  Each step
@@ -521,6 +585,40 @@ int launch_fit(int degree, int dim, const FitArgs &a, hipStream_t s) {
     }
 }
 
+template <int D>
+int launch_l2_d(int dim, const L2Args &a, hipStream_t s) {
+    const int cpw = dim * (D + 1) <= 32 ? 2 : 1;
+    const uint32_t blocks = static_cast<uint32_t>((a.n_curves + 4 * cpw - 1) / (4 * cpw));
+    switch (dim) {
+        case 1: hipLaunchKernelGGL((k_l2_adjoint<D, 1>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_l2_adjoint<D, 2>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_l2_adjoint<D, 3>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_l2_adjoint<D, 4>), dim3(blocks), dim3(kBlock), 0, s, a); break;
+    }
+    BZ_CHECK_LAUNCH("k_l2_adjoint");
+    return BZ_OK;
+}
+
+int launch_l2(int degree, int dim, const L2Args &a, hipStream_t s) {
+    switch (degree) {
+        case 1: return launch_l2_d<1>(dim, a, s);
+        case 2: return launch_l2_d<2>(dim, a, s);
+        case 3: return launch_l2_d<3>(dim, a, s);
+        case 4: return launch_l2_d<4>(dim, a, s);
+        case 5: return launch_l2_d<5>(dim, a, s);
+        case 6: return launch_l2_d<6>(dim, a, s);
+        case 7: return launch_l2_d<7>(dim, a, s);
+        case 8: return launch_l2_d<8>(dim, a, s);
+        case 9: return launch_l2_d<9>(dim, a, s);
+        case 10: return launch_l2_d<10>(dim, a, s);
+        case 11: return launch_l2_d<11>(dim, a, s);
+        case 12: return launch_l2_d<12>(dim, a, s);
+        case 13: return launch_l2_d<13>(dim, a, s);
+        case 14: return launch_l2_d<14>(dim, a, s);
+        default: return launch_l2_d<15>(dim, a, s);
+    }
+}
+
 int check_fit(const char *fn, float *ctrl, float *t, const float *y, int64_t n_curves, int degree, int dim, int64_t n_t,
               float *m_ctrl, float *v_ctrl, float *m_t, float *v_t, float lr, float beta1, float beta2, float eps) {
     if (degree < 1 || degree > kMaxDegree || dim < 1 || dim > kMaxDim)
@@ -585,6 +683,34 @@ int bz_adjoint_bezier(const float *ctrl, const float *w, int64_t n_curves, int d
         const uint32_t blocks = static_cast<uint32_t>((n_curves + 3) / 4);
         const hipStream_t s = as_stream(stream);
         return w ? launch_adj<true>(degree, dim, a, s, blocks) : launch_adj<false>(degree, dim, a, s, blocks);
+    });
+}
+
+int bz_l2_fit_adjoint(const float *ctrl, int64_t n_curves, int degree, int dim, const float *t, int64_t n_t,
+                      const float *target, float *loss_part, float *grad_ctrl, float *grad_t, bz_stream stream) {
+    return guarded("bz_l2_fit_adjoint", [&]() -> int {
+        const char *fn = "bz_l2_fit_adjoint";
+        if (degree < 1 || degree > kMaxDegree || dim < 1 || dim > kMaxDim)
+            return fail(BZ_ERR_SHAPE, "%s: degree %d / dim %d out of range", fn, degree, dim);
+        if (n_curves < 0 || n_t < 0) return fail(BZ_ERR_SHAPE, "%s: negative count", fn);
+        if (n_curves > (int64_t(1) << 31) - 1) return fail(BZ_ERR_SHAPE, "%s: too many curves", fn);
+        if (n_curves == 0 || n_t == 0) return BZ_OK;
+        if (!ctrl || !t || !target) return fail(BZ_ERR_NULL, "%s: ctrl, t and target are required", fn);
+        if (!aligned(ctrl, 4) || !aligned(t, 4) || !aligned(target, 4) || !aligned(loss_part, 4) ||
+            !aligned(grad_ctrl, 4) || !aligned(grad_t, 4))
+            return fail(BZ_ERR_ALIGN, "%s: FP32 arrays need 4-byte alignment", fn);
+        L2Args a;
+        a.ctrl = ctrl;
+        a.t = t;
+        a.y = target;
+        a.loss_part = loss_part;
+        a.gctrl = grad_ctrl;
+        a.gt = grad_t;
+        a.n_curves = n_curves;
+        a.n_t = n_t;
+        a.plane = n_curves * n_t;
+        a.inv_m = static_cast<float>(1.0 / static_cast<double>(n_curves * n_t));
+        return launch_l2(degree, dim, a, as_stream(stream));
     });
 }
 

@@ -49,8 +49,22 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n_sorted, cons
     const U *src = ctrl + cp_offset[o] * dim;
     U *dst = ctrl_s + ci.ctrl_base + slot * n;
     for (int e = 0; e < n; ++e) dst[e] = src[e];
-    if (ci.kind == 1)
+    if (ci.kind == 1 || ci.kind == 3)
         for (int e = 0; e <= ci.degree; ++e) w_s[ci.w_base + slot * (ci.degree + 1) + e] = w[cp_offset[o] + e];
+}
+
+// Plan-time weight check: flags[o] = 1 when a rational or NURBS object has a
+// weight that is not positive (zero, negative or NaN).  One thread per object.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_weight_flags(int64_t n_obj, const uint16_t *__restrict__ kind_degree,
+                                                         const int64_t *__restrict__ cp_offset, const T *__restrict__ w,
+                                                         uint8_t *__restrict__ flags) {
+    const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (o >= n_obj) return;
+    uint8_t f = 0;
+    if ((kind_degree[o] >> 8) != 0)
+        for (int64_t i = cp_offset[o]; i < cp_offset[o + 1]; ++i) f |= !(to_f32<T>(w[i]) > 0.0f);
+    flags[o] = f;
 }
 
 // Bezier extraction of one clamped cubic NURBS by knot insertion: every
@@ -166,6 +180,7 @@ constexpr uint32_t kDefaultWindow = 131072;
 int class_cost(int kind, int degree, int method, int dim) {
     const int ch = dim + (kind != 0 ? 1 : 0);
     if (kind == 2) return 60 + 4 * ch;
+    if (kind == 3) return 4 * degree + (degree + 1) * (ch + 2) + 8 + (method == BZ_DECASTELJAU ? degree * (degree + 1) / 2 * ch * 2 : 0);
     if (method == BZ_DECASTELJAU) return degree * (degree + 1) / 2 * ch * 2 + 8;
     return 3 * degree + (degree + 1) * ch + 8;
 }
@@ -189,7 +204,7 @@ struct bz_plan_s {
     unsigned int *counters = nullptr;
     std::vector<ClassInfo> classes;
     std::vector<int32_t> perm_h;  // host copy of perm (window boundaries of the tile order)
-    uint32_t n_tiles = 0, qpt = 1, vq = 1, window = 0;
+    uint32_t n_tiles = 0, n_signed = 0, qpt = 1, vq = 1, window = 0;
     int64_t n_segs = 0;
     uint32_t workgroups = 0, cus = 1;
     int dynamic = 1;
@@ -231,6 +246,7 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
     a.perm = p->perm;
     a.tiles = p->tiles;
     a.n_tiles = p->n_tiles;
+    a.n_signed = p->n_signed;
     a.nhead = p->nhead;
     a.ntab = p->ntab;
     a.brk = p->brk;
@@ -270,11 +286,17 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, uint32_t window, hipStr
     });
     std::vector<Tile> tiles;
     auto emit = [&](int c, uint64_t a, uint64_t b) {  // queries [a, b) of class c
-        const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 2 ? 1 : vq);
+        const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 0 || cls[c].kind == 1 ? vq : 1);
         for (uint64_t q0 = a; q0 < b; q0 += span)
             tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), static_cast<uint32_t>(b), qpt, 0});
     };
     const uint64_t nt = static_cast<uint64_t>(p->n_t);
+    // signed-weight rational classes (kind 3) go to a launch of their own:
+    // their tiles are appended after all others, in class order
+    std::vector<int> signed_cls;
+    for (int c : order)
+        if (cls[c].kind == 3) signed_cls.push_back(c);
+    order.erase(std::remove_if(order.begin(), order.end(), [&](int c) { return cls[c].kind == 3; }), order.end());
     if (window == 0) {
         for (int c : order) emit(c, 0, static_cast<uint64_t>(cls[c].count) * nt);
     } else {
@@ -292,12 +314,15 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, uint32_t window, hipStr
             }
         }
     }
+    const size_t n_main = tiles.size();
+    for (int c : signed_cls) emit(c, 0, static_cast<uint64_t>(cls[c].count) * nt);
     if (p->tiles) BZ_CHECK_HIP(hipStreamSynchronize(s));
     if (p->tiles) BZ_CHECK_HIP(hipFree(p->tiles));
     p->tiles = nullptr;
     int rc = dev_upload(&p->tiles, tiles, s);
     if (rc) return rc;
-    p->n_tiles = static_cast<uint32_t>(tiles.size());
+    p->n_tiles = static_cast<uint32_t>(n_main);
+    p->n_signed = static_cast<uint32_t>(tiles.size() - n_main);
     p->qpt = qpt;
     p->vq = vq;
     p->window = window;
@@ -331,8 +356,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
             BZ_CHECK_HIP(hipMemcpyAsync(cpo.data(), cp_offset, (n_obj + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
             BZ_CHECK_HIP(hipStreamSynchronize(s));
         }
-        // classes: kind 0/1 x degree 1..15, kind 2 (cubic NURBS)
-        std::vector<int64_t> count(32, 0);
+        // validate the objects
         bool need_w = false, any_nurbs = false;
         for (int64_t o = 0; o < n_obj; ++o) {
             const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
@@ -347,35 +371,73 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                 if (ncp != deg + 1) return fail(BZ_ERR_SHAPE, "%s: object %lld has %lld control points for degree %d", fn, (long long)o, (long long)ncp, deg);
             }
             if (kind != 0) need_w = true;
-            count[kind == 2 ? 30 : kind * 15 + deg - 1] += 1;
         }
         if (need_w && !w) return fail(BZ_ERR_NULL, "%s: weights are required (rational or NURBS objects)", fn);
         if (!aligned(ctrl, dtype_size(dtype)) || !aligned(w, dtype_size(dtype)))
             return fail(BZ_ERR_ALIGN, "%s: misaligned ctrl or w", fn);
-        // class list and permutation (stable counting sort by kind, degree)
+        // which weighted objects have a weight that is not positive
+        std::vector<uint8_t> wflag(n_obj, 0);
+        if (need_w) {
+            uint8_t *flags_d = nullptr;
+            hipError_t e = hipMalloc(reinterpret_cast<void **>(&flags_d), std::max<int64_t>(n_obj, 1));
+            if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: device allocation", fn);
+            BZ_CHECK_HIP(e);
+            const uint32_t blocks = static_cast<uint32_t>((n_obj + kBlock - 1) / kBlock);
+            if (dtype == BZ_F32)
+                hipLaunchKernelGGL((k_weight_flags<float>), dim3(blocks), dim3(kBlock), 0, s, n_obj, kind_degree,
+                                   cp_offset, static_cast<const float *>(w), flags_d);
+            else if (dtype == BZ_F16)
+                hipLaunchKernelGGL((k_weight_flags<_Float16>), dim3(blocks), dim3(kBlock), 0, s, n_obj, kind_degree,
+                                   cp_offset, static_cast<const _Float16 *>(w), flags_d);
+            else
+                hipLaunchKernelGGL((k_weight_flags<bf16_t>), dim3(blocks), dim3(kBlock), 0, s, n_obj, kind_degree,
+                                   cp_offset, static_cast<const bf16_t *>(w), flags_d);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipMemcpyAsync(wflag.data(), flags_d, n_obj, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            (void)hipFree(flags_d);
+            if (e != hipSuccess) return hip_fail(e, "k_weight_flags");
+        }
+        // classes, keyed: 0..14 integral Bezier of degree 1..15, 15..29
+        // rational with positive weights, 30..44 rational with a weight <= 0
+        // (conditioning test), 45 cubic NURBS (last, so the NURBS rank is its
+        // slot in the last class)
+        constexpr int kKeys = 46, kNurbsKey = 45;
+        auto key_of = [&](int64_t o) {
+            const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
+            if (kind == 2) return kNurbsKey;
+            if (kind == 1 && wflag[o]) return 30 + deg - 1;
+            return kind * 15 + deg - 1;
+        };
+        std::vector<int64_t> count(kKeys, 0);
+        for (int64_t o = 0; o < n_obj; ++o) {
+            if ((kd[o] >> 8) == 2 && wflag[o])
+                return fail(BZ_ERR_UNSUPPORTED, "%s: NURBS object %lld has a weight that is not positive", fn, (long long)o);
+            count[key_of(o)] += 1;
+        }
+        // class list and permutation (stable counting sort by key)
         std::vector<ClassInfo> cls;
-        std::vector<int32_t> cls_of_key(32, -1);
+        std::vector<int32_t> cls_of_key(kKeys, -1);
         int32_t first = 0;
         int64_t ctrl_elems = 0, w_elems = 0;
-        for (int key = 0; key < 31; ++key) {
+        for (int key = 0; key < kKeys; ++key) {
             if (count[key] == 0) continue;
             ClassInfo ci;
-            ci.kind = key == 30 ? 2 : key / 15;
-            ci.degree = key == 30 ? kNurbsP : key % 15 + 1;
+            ci.kind = key == kNurbsKey ? 2 : (key / 15 == 2 ? 3 : key / 15);
+            ci.degree = key == kNurbsKey ? kNurbsP : key % 15 + 1;
             ci.first = first;
             ci.count = static_cast<int32_t>(count[key]);
             ci.ctrl_base = ctrl_elems;
             ci.w_base = w_elems;
             if (ci.kind != 2) ctrl_elems += count[key] * (ci.degree + 1) * dim;
-            if (ci.kind == 1) w_elems += count[key] * (ci.degree + 1);
+            if (ci.kind == 1 || ci.kind == 3) w_elems += count[key] * (ci.degree + 1);
             cls_of_key[key] = static_cast<int32_t>(cls.size());
             cls.push_back(ci);
             first += ci.count;
         }
         std::vector<int32_t> perm(n_obj), fill(cls.size(), 0);
         for (int64_t o = 0; o < n_obj; ++o) {
-            const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
-            const int c = cls_of_key[kind == 2 ? 30 : kind * 15 + deg - 1];
+            const int c = cls_of_key[key_of(o)];
             perm[cls[c].first + fill[c]++] = static_cast<int32_t>(o);
         }
         // NURBS (in sorted order, so a NURBS's rank is its slot in the class):
@@ -641,7 +703,7 @@ int bz_batch_plan_configure(bz_plan plan, int64_t workgroups, int sub_tiles, int
 int bz_batch_plan_info(bz_plan plan, int64_t *info4) {
     if (!plan || !info4) return fail(BZ_ERR_NULL, "bz_batch_plan_info: plan and info are required");
     info4[0] = static_cast<int64_t>(plan->classes.size());
-    info4[1] = plan->n_tiles;
+    info4[1] = plan->n_tiles + plan->n_signed;
     info4[2] = plan->n_segs;
     info4[3] = plan->workgroups;
     return BZ_OK;

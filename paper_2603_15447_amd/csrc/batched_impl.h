@@ -10,7 +10,7 @@ namespace bzi {
 constexpr int kNurbsP = 3;
 
 struct ClassInfo {
-    int32_t kind;       // 0 Bezier, 1 rational, 2 NURBS
+    int32_t kind;       // 0 Bezier, 1 rational (all weights > 0), 2 NURBS, 3 rational with a weight <= 0
     int32_t degree;     // 1..15 (3 for NURBS)
     int32_t first;      // first slot of the class in perm
     int32_t count;      // objects in the class
@@ -67,7 +67,8 @@ struct BatchArgs {
     const void *w_s;           // weights of rational objects, class-sorted (plan copy)
     const int32_t *perm;       // sorted slot -> object
     const Tile *tiles;
-    uint32_t n_tiles;
+    uint32_t n_tiles;          // tiles of the persistent launch
+    uint32_t n_signed;         // tiles of signed-weight rationals, after those (a launch of their own)
     const NurbsHead *nhead;    // [n_nurbs], NURBS ranked in sorted order
     const NurbsTab *ntab;      // span lookup tables, 2*nseg+1 entries per NURBS
     const float *brk;          // breakpoints, nseg+1 per NURBS, from NurbsHead::brk0
@@ -250,6 +251,39 @@ __device__ __forceinline__ void eval_curve_query4(const T *__restrict__ P, const
     }
 }
 
+// Rational objects with a weight that is not positive: the denominator
+// sum w_i B_i can cancel, so each query gets the conditioning test of
+// bz_eval_rational, kappa = sum |w_i| B_i / |sum w_i B_i| computed from the
+// FP32 Bernstein basis, and a query with kappa above the threshold (or a zero
+// or non-finite weight sum) is evaluated again by FP64 de Casteljau on the
+// homogeneous points.  (With all weights positive kappa is 1, so those objects
+// form classes of their own that skip the test.)
+constexpr float kBatchKappa = 64.0f;
+
+template <int D, typename T>
+__device__ __attribute__((noinline)) void batch_rational_fp64(const T *__restrict__ P, const T *__restrict__ W, int dim,
+                                                              float t, float *__restrict__ out, int64_t plane,
+                                                              int64_t q) {
+    const double td = static_cast<double>(t);
+    double ww[D + 1], den[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) den[i] = ww[i] = static_cast<double>(to_f32<T>(W[i]));
+#pragma unroll
+    for (int lvl = 1; lvl <= D; ++lvl)
+#pragma unroll
+        for (int i = 0; i <= D - lvl; ++i) den[i] = lerp(den[i], den[i + 1], td);
+    for (int k = 0; k < dim; ++k) {
+        double H[D + 1];
+#pragma unroll
+        for (int i = 0; i <= D; ++i) H[i] = ww[i] * static_cast<double>(to_f32<T>(P[k * (D + 1) + i]));
+#pragma unroll
+        for (int lvl = 1; lvl <= D; ++lvl)
+#pragma unroll
+            for (int i = 0; i <= D - lvl; ++i) H[i] = lerp(H[i], H[i + 1], td);
+        st_stream(out + k * plane + q, static_cast<float>(H[0] / den[0]));
+    }
+}
+
 constexpr int kMaxQpt = 4;
 
 // Index, permutation and parameter loads of every sub-tile are issued before
@@ -294,6 +328,34 @@ __device__ __forceinline__ void run_curve_tile(const BatchArgs &a, const Tile &t
         const T *W = RAT ? static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1)
                          : nullptr;
         eval_curve_query<D, RAT, F, T>(P, W, a.dim, sq.t[s], out, a.plane, sq.q[s]);
+    }
+}
+
+// One query per lane; the conditioning test decides between the FP32 form
+// and the FP64 recomputation per query.
+template <int D, int F, typename T>
+__device__ __forceinline__ void run_signed_tile(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
+    SubTileQueries sq;
+    prefetch_queries(a, tl, sq);
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!sq.ok[s]) continue;
+        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(sq.slot[s]) * (D + 1) * a.dim;
+        const T *W = static_cast<const T *>(a.w_s) + tl.ci.w_base + static_cast<size_t>(sq.slot[s]) * (D + 1);
+        const float t = sq.t[s];
+        float wv[D + 1], B[D + 1];
+        load_row<T, D + 1>(W, wv);
+        bernstein_basis<D>(t, B);
+        float den = 0.0f, mag = 0.0f;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            den = __builtin_fmaf(wv[i], B[i], den);
+            mag = __builtin_fmaf(__builtin_fabsf(wv[i]), B[i], mag);
+        }
+        // NaN t: no recomputation, the FP32 form passes the NaN on
+        const bool fix = (t == t) && !(den != 0.0f && mag <= kBatchKappa * __builtin_fabsf(den));
+        if (fix) batch_rational_fp64<D, T>(P, W, a.dim, t, out, a.plane, sq.q[s]);
+        else eval_curve_query<D, true, F, T>(P, W, a.dim, t, out, a.plane, sq.q[s]);
     }
 }
 
@@ -461,6 +523,27 @@ __device__ __forceinline__ void dispatch_degree(const BatchArgs &a, const Tile &
     }
 }
 
+template <int F, typename T>
+__device__ __forceinline__ void dispatch_degree_signed(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
+    switch (tl.ci.degree) {
+        case 1: run_signed_tile<1, F, T>(a, tl, out); break;
+        case 2: run_signed_tile<2, F, T>(a, tl, out); break;
+        case 3: run_signed_tile<3, F, T>(a, tl, out); break;
+        case 4: run_signed_tile<4, F, T>(a, tl, out); break;
+        case 5: run_signed_tile<5, F, T>(a, tl, out); break;
+        case 6: run_signed_tile<6, F, T>(a, tl, out); break;
+        case 7: run_signed_tile<7, F, T>(a, tl, out); break;
+        case 8: run_signed_tile<8, F, T>(a, tl, out); break;
+        case 9: run_signed_tile<9, F, T>(a, tl, out); break;
+        case 10: run_signed_tile<10, F, T>(a, tl, out); break;
+        case 11: run_signed_tile<11, F, T>(a, tl, out); break;
+        case 12: run_signed_tile<12, F, T>(a, tl, out); break;
+        case 13: run_signed_tile<13, F, T>(a, tl, out); break;
+        case 14: run_signed_tile<14, F, T>(a, tl, out); break;
+        default: run_signed_tile<15, F, T>(a, tl, out); break;
+    }
+}
+
 template <int F, typename T, int VQ>
 __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile, float *__restrict__ out) {
     const Tile tl = a.tiles[tile];
@@ -510,6 +593,16 @@ __global__ __launch_bounds__(kBlock, (VQ == 4 && std::is_same<T, float>::value) 
     }
 }
 
+// The signed-weight rational tiles run in a launch of their own, one
+// workgroup per tile: their FP64 recomputation needs far more registers than
+// any path of the persistent kernel, whose occupancy would otherwise drop for
+// every batch.
+template <int F, typename T>
+__global__ __launch_bounds__(kBlock) void k_batch_signed(BatchArgs a, float *__restrict__ out) {
+    const Tile tl = a.tiles[a.n_tiles + blockIdx.x];
+    dispatch_degree_signed<F, T>(a, tl, out);
+}
+
 }  // namespace batch_dev
 
 // Launch of the persistent kernel (instantiated in batched_{dc,bern}_{f32,f16,bf16}.hip).
@@ -520,6 +613,10 @@ int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) 
     else
         hipLaunchKernelGGL((batch_dev::k_batch_persistent<F, T, 1>), dim3(workgroups), dim3(kBlock), 0, s, a, a.out);
     BZ_CHECK_LAUNCH("k_batch_persistent");
+    if (a.n_signed > 0) {
+        hipLaunchKernelGGL((batch_dev::k_batch_signed<F, T>), dim3(a.n_signed), dim3(kBlock), 0, s, a, a.out);
+        BZ_CHECK_LAUNCH("k_batch_signed");
+    }
     return BZ_OK;
 }
 

@@ -159,3 +159,40 @@ def test_particles_probe_and_plan_errors(L):
     assert L.bz_batch_plan_configure(None, 64, 1, 1, 1, 0, None) == bz.ERR_NULL
     assert L.bz_batch_plan_autotune(None, FAKE, FAKE, None, None) == bz.ERR_NULL
     assert L.bz_batch_eval(None, FAKE, FAKE, None) == bz.ERR_NULL
+
+
+def test_l2_fit_adjoint_errors(L):
+    f = L.bz_l2_fit_adjoint
+    assert f(FAKE, 4, 0, 3, FAKE, 8, FAKE, FAKE, FAKE, FAKE, None) == bz.ERR_SHAPE
+    assert f(FAKE, 4, 16, 3, FAKE, 8, FAKE, FAKE, FAKE, FAKE, None) == bz.ERR_SHAPE
+    assert f(FAKE, 4, 3, 5, FAKE, 8, FAKE, FAKE, FAKE, FAKE, None) == bz.ERR_SHAPE
+    assert f(FAKE, -1, 3, 3, FAKE, 8, FAKE, FAKE, FAKE, FAKE, None) == bz.ERR_SHAPE
+    assert f(None, 4, 3, 3, FAKE, 8, FAKE, FAKE, FAKE, FAKE, None) == bz.ERR_NULL
+    assert f(FAKE, 4, 3, 3, FAKE, 8, None, FAKE, FAKE, FAKE, None) == bz.ERR_NULL
+    assert f(FAKE, 4, 3, 3, FAKE, 8, FAKE, FAKE, ODD, FAKE, None) == bz.ERR_ALIGN
+    # nothing to do: no pointer is needed
+    assert f(None, 0, 3, 3, None, 8, None, None, None, None, None) == bz.OK
+    assert f(None, 4, 3, 3, None, 0, None, None, None, None, None) == bz.OK
+    assert "bz_l2_fit_adjoint" in (bz.last_error() or "bz_l2_fit_adjoint")
+
+
+def test_half_precision_inputs_are_refused_where_only_fp32_is_read():
+    # the adjoint reads FP32 only: half-precision control points, weights,
+    # parameters or incoming gradients are rejected before any pointer is
+    # passed on (the autograd backward widens them to FP32 first)
+    import torch
+    c32 = torch.zeros(2, 3, 4)
+    t32 = torch.zeros(2, 5)
+    g32 = torch.zeros(3, 10)
+    for bad in ({"ctrl": c32.half()}, {"t": t32.half()}, {"grad_out": g32.bfloat16()},
+                {"w": torch.ones(2, 4, dtype=torch.float16)}):
+        args = {"ctrl": c32, "t": t32, "grad_out": g32, **bad}
+        with pytest.raises(bz.BzError) as e:
+            bz.adjoint_bezier(args["ctrl"], args["t"], args["grad_out"], w=args.get("w"))
+        assert e.value.code == bz.ERR_DTYPE
+    with pytest.raises(bz.BzError) as e:
+        bz.eval_bezier(c32, t32.half())
+    assert e.value.code == bz.ERR_DTYPE
+    with pytest.raises(bz.BzError) as e:
+        bz.l2_fit_adjoint(c32, t32, g32.half())
+    assert e.value.code == bz.ERR_DTYPE

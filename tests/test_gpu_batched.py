@@ -6,21 +6,10 @@ import torch
 
 import bz_synth
 import paper_2603_15447_amd as bz
+from tests._batch import _extents, _lp_bound
 from tests._gpu import TOL_F32, host, to_dev
 
 pytestmark = pytest.mark.gpu
-
-
-def _extents(b, ctrl=None):
-    """Per-object normaliser (largest bounding-box side, floored by the
-    largest |coordinate|, as for single curves)."""
-    c = np.asarray(b.ctrl if ctrl is None else ctrl, np.float64)
-    ext = np.empty(b.n_obj)
-    for o in range(b.n_obj):
-        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
-        P = c[a0 * b.dim:a1 * b.dim].reshape(b.dim, a1 - a0)
-        ext[o] = max((P.max(axis=1) - P.min(axis=1)).max(), np.abs(P).max(), 1e-30)
-    return ext
 
 
 def _err(got, ref, ext, n_t):
@@ -215,19 +204,124 @@ def test_plan_errors():
 
 def test_config_batched_full_size_sampled(orc):
     """2^20 Bezier curves (degree 2..15, half rational) + 2^16 cubic NURBS,
-    16 random t each, FP32 and FP16 storage; the first 65536 objects checked."""
+    16 random t each, FP32 and FP16 storage, one persistent launch each:
+    65536 objects drawn at random from the whole batch (with the first and
+    last object and the last NURBS) checked against the oracle.  FP32: within
+    1e-5 of each object's box.  FP16: within FP32 rounding of the oracle on the
+    rounded inputs, and against the FP32 inputs within the rounding bound
+    (_lp_bound) plus 1e-5 of the box."""
     b = bz_synth.mixed_batch()
-    sub = _subbatch(b, 65536)
+    kinds = b.kind_degree >> 8
+    rng = np.random.default_rng(2024)
+    idx = np.unique(np.concatenate([rng.choice(b.n_obj, 65536, replace=False),
+                                    [0, b.n_obj - 1, np.nonzero(kinds == 2)[0][-1]]]))
+    sub = b.subset(idx)
     ref = orc.batch_eval(sub)
     ext = _extents(sub)
+    idx_d = torch.from_numpy(idx).cuda()
     for dtype in (torch.float32, torch.float16):
         plan, dev = _plan(b, dtype=dtype)
-        got = host(plan(to_dev(b.t))[:, :65536 * 16])
+        got = host(plan(to_dev(b.t)).view(3, b.n_obj, 16)[:, idx_d].reshape(3, -1))
         if dtype == torch.float32:
             assert _err(got, ref, ext, 16) <= TOL_F32
         else:
             rsub = bz_synth.Batch(**{**sub.__dict__})
-            rsub.ctrl = dev["ctrl"][:len(sub.ctrl)].float().cpu().numpy()
-            rsub.w = dev["w"][:len(sub.w)].float().cpu().numpy()
+            rsub.ctrl = torch.from_numpy(sub.ctrl).to(dtype).float().numpy()
+            rsub.w = torch.from_numpy(sub.w).to(dtype).float().numpy()
             assert _err(got, orc.batch_eval(rsub), _extents(rsub), 16) <= TOL_F32
+            d = np.abs(got - ref).max(axis=0).reshape(-1, 16).max(axis=1)
+            bound = _lp_bound(sub, rsub, ext) + TOL_F32 * ext
+            assert (d <= bound).all(), float((d / bound).max())
         plan.close()
+
+
+def _signed_batch(n_rat=600, n_t=16, seed=31):
+    """Rational curves of degree 2..9 with weights of both signs, parameters
+    placed next to the roots of the weight sum sum w_i B_i(t) (where the
+    conditioning number sum|w_i|B_i / |sum w_i B_i| is large) and at random;
+    plus integral curves and positive-weight rationals."""
+    b = bz_synth.mixed_batch(n_bezier=n_rat, n_nurbs=0, n_t=n_t, deg_lo=2, deg_hi=9, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    kinds = b.kind_degree >> 8
+    from math import comb
+    n_signed = 0
+    for o in range(b.n_obj):
+        if kinds[o] != 1 or o % 3 == 0:
+            continue
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        d = a1 - a0 - 1
+        w = rng.uniform(0.5, 2.0, d + 1)
+        w[1:d] *= -1.0  # inner weights negative: the sum changes sign inside (0, 1)
+        b.w[a0:a1] = w.astype(np.float32)
+        wf = b.w[a0:a1].astype(np.float64)
+        poly = np.zeros(d + 1)  # the weight sum in the power basis (numpy: highest power first)
+        for i in range(d + 1):
+            bi = np.zeros(d + 1)
+            for j in range(d - i + 1):  # C(d,i) t^i (1-t)^(d-i)
+                bi[d - (i + j)] += comb(d, i) * comb(d - i, j) * (-1) ** j
+            poly += wf[i] * bi
+        roots = [r.real for r in np.roots(poly) if abs(r.imag) < 1e-12 and 0.0 < r.real < 1.0]
+        ts = list(rng.random(n_t))
+        for k, r in enumerate(roots[:2]):
+            for j, off in enumerate((1e-4, -1e-4, 1e-6, -1e-6, 0.0)):
+                ts[5 * k + j] = r + off
+        b.t[o] = np.clip(np.asarray(ts[:n_t]), 0.0, 1.0).astype(np.float32)
+        n_signed += 1
+    return b, n_signed
+
+
+def _kappa(b):
+    """FP64 conditioning number of every query of the rational objects."""
+    from math import comb
+    kap = np.ones((b.n_obj, b.n_t))
+    for o in range(b.n_obj):
+        if (b.kind_degree[o] >> 8) != 1:
+            continue
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        d = a1 - a0 - 1
+        w = b.w[a0:a1].astype(np.float64)
+        t = b.t[o].astype(np.float64)[:, None]
+        B = np.array([comb(d, i) for i in range(d + 1)]) * t ** np.arange(d + 1) * (1 - t) ** (d - np.arange(d + 1))
+        kap[o] = (np.abs(w) * B).sum(1) / np.maximum(np.abs((w * B).sum(1)), 1e-300)
+    return kap
+
+
+@pytest.mark.parametrize("method", ["bernstein", "decasteljau"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_signed_weight_rationals(orc, method, dtype):
+    """Rational objects with weights of both signs get their own classes
+    with the conditioning test: points next to a root of the weight sum
+    (conditioning numbers far above 64) are recomputed in FP64, so every
+    point matches the oracle to 1e-5 of the larger of the object's box and
+    the point's own size (near a pole the point itself is huge, and its FP32
+    rounding alone is 2^-24 of it)."""
+    b, n_signed = _signed_batch()
+    kap = _kappa(b)
+    assert n_signed > 150 and (kap > 1e3).sum() > 300  # the test reaches the recomputation
+    plan, dev = _plan(b, dtype=dtype, method=method)
+    assert plan.info()["n_classes"] > len(set(b.kind_degree.tolist()))  # signed classes of their own
+    got = host(plan(to_dev(b.t)))
+    rb = bz_synth.Batch(**{**b.__dict__})
+    rb.ctrl = dev["ctrl"].float().cpu().numpy()
+    rb.w = dev["w"].float().cpu().numpy()
+    ref = orc.batch_eval(rb)
+    scale = np.maximum(np.repeat(_extents(rb), b.n_t)[None, :], np.abs(ref))
+    assert np.isfinite(got).all() or np.array_equal(np.isfinite(got), np.isfinite(ref))
+    assert (np.abs(got - ref) / scale).max() <= TOL_F32
+    # the same objects through bz_eval_rational (its own FP64 recomputation) agree
+    for o in np.nonzero(b.kind_degree >> 8 == 1)[0][:50]:
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        c = dev["ctrl"][a0 * 3:a1 * 3].reshape(1, 3, a1 - a0).contiguous()
+        w = dev["w"][a0:a1].reshape(1, a1 - a0).contiguous()
+        single = host(bz.eval_rational(c, w, to_dev(b.t[o:o + 1]), method=method))
+        sc = np.maximum(_extents(rb)[o], np.abs(ref[:, o * b.n_t:(o + 1) * b.n_t]))
+        assert (np.abs(single - ref[:, o * b.n_t:(o + 1) * b.n_t]) / sc).max() <= TOL_F32
+
+
+def test_signed_nurbs_weights_are_refused():
+    b = bz_synth.mixed_batch(n_bezier=20, n_nurbs=4, n_t=4, seed=32)
+    o = np.nonzero(b.kind_degree >> 8 == 2)[0][1]
+    b.w[b.cp_offset[o] + 2] = -0.5
+    with pytest.raises(bz.BzError) as e:
+        _plan(b)
+    assert e.value.code == bz.ERR_UNSUPPORTED

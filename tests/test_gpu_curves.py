@@ -22,9 +22,7 @@ def test_curves_all_degrees(orc, degree, method):
         got = host(bz.eval_bezier(to_dev(ctrl), to_dev(t), method))
         ref = orc.bezier_decasteljau(ctrl, t, per_object)
         err = bbox_err(got, ref, extents(ctrl), 67)
-        # Seiler terms grow like C(d, d/2); its FP32 error grows with degree
-        tol = TOL_F32 if (method != "seiler" or degree <= 12) else 4 * TOL_F32
-        assert err <= tol, (degree, dim, method, err)
+        assert err <= TOL_F32, (degree, dim, method, err)
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -72,8 +70,7 @@ def test_curves_wave_uniform_modes(orc, n_t, method):
         pts = dc.float().cpu().numpy()
         got = host(bz.eval_bezier(dc, to_dev(t), method))
         ref = orc.bezier_decasteljau(pts, t, per_object)
-        tol = TOL_F32 if (method != "seiler" or degree <= 12) else 4 * TOL_F32
-        assert bbox_err(got, ref, extents(pts), n_t) <= tol, (n_t, degree, dim, per_object, dtype, method)
+        assert bbox_err(got, ref, extents(pts), n_t) <= TOL_F32, (n_t, degree, dim, per_object, dtype, method)
 
 
 def test_curves_across_launch_chunks(orc):
@@ -133,8 +130,7 @@ def test_seiler_terms_and_eval(orc, degree, n_t):
     assert (np.abs(host(sc) - ref_sc) / scale).max() < 2e-6
     got = host(bz.eval_seiler(sc, to_dev(t)))
     ref = orc.bezier_decasteljau(ctrl, t, True)
-    tol = TOL_F32 if degree <= 12 else 4 * TOL_F32
-    assert bbox_err(got, ref, extents(ctrl), n_t) <= tol
+    assert bbox_err(got, ref, extents(ctrl), n_t) <= TOL_F32
 
 
 @pytest.mark.parametrize("degree", [1, 2, 3, 6, 11, 15])
@@ -144,8 +140,7 @@ def test_rational_parity(orc, degree, method):
     nf = torch.zeros(1, dtype=torch.int32, device=dev())
     got = host(bz.eval_rational(to_dev(ctrl), to_dev(w), to_dev(t), method, n_fixed=nf))
     ref = orc.rational_eval(ctrl, w, t, True)
-    tol = TOL_F32 if (method != "seiler" or degree <= 12) else 4 * TOL_F32
-    assert bbox_err(got, ref, extents(ctrl), 29) <= tol
+    assert bbox_err(got, ref, extents(ctrl), 29) <= TOL_F32
     assert int(nf.item()) == 0  # positive weights: conditioning 1, never recomputed
 
 

@@ -75,8 +75,9 @@ def test_grid_mfma_f16x3_row_scaling(orc, scale):
 
 
 def test_grid_config_full_size_sampled(orc):
-    """2^18 bicubic patches on 32x32 grids (2^28 points): VALU, FP32, BF16 and
-    FP16x3 MFMA outputs checked on 2048 sampled patches (every grid point)."""
+    """2^18 bicubic patches on 32x32 grids (2^28 points): VALU and every MFMA
+    engine (FP32, BF16, FP16, FP16x3) checked on 2048 sampled patches (every
+    grid point); BF16 and FP16 against their rounding bound."""
     n = 1 << 18
     P = bz_synth.patches(n_obj=n)
     Pd = to_dev(P)
@@ -84,11 +85,12 @@ def test_grid_config_full_size_sampled(orc):
     pick = np.sort(rng.choice(n, size=2048, replace=False))
     ref = orc.tensor_grid(P[pick], 3, 3, 32, 32).reshape(3, 2048, 1024)
     out = torch.empty((3, n * 1024), dtype=torch.float32, device=Pd.device)
-    for engine in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16x3"):
+    for engine in ("valu", "mfma_f32", "mfma_bf16", "mfma_f16", "mfma_f16x3"):
+        out.fill_(float("nan"))
         bz.eval_tensor_patch(Pd, 3, 3, nu=32, nv=32, engine=engine, out=out)
         got = out.view(3, n, 1024)[:, torch.from_numpy(pick).to(Pd.device)].cpu().numpy().astype(np.float64)
-        if engine == "mfma_bf16":
-            assert np.abs(got - ref).max() <= MFMA_BOUNDS[engine] + 1e-5
+        if engine in ("mfma_bf16", "mfma_f16"):
+            assert np.abs(got - ref).max() <= MFMA_BOUNDS[engine] * np.abs(P[pick]).max() + 1e-5, engine
         else:
             assert bbox_err(got.reshape(3, -1), ref.reshape(3, -1), extents(P[pick]), 1024) <= TOL_F32, engine
     del out
@@ -141,7 +143,7 @@ def test_points_across_launch_chunks(orc):
         if dw:
             sc = bz.tensor_to_seiler(Pd, du, dv, dw)
             got = bz.eval_tensor_seiler(sc, du, dv, dw, uvw=ud).view(3, n, n_per)[:, idx].reshape(3, -1).cpu().numpy()
-            assert bbox_err(got, ref, extents(P[pick]), n_per) <= 2 * TOL_F32, "seiler"
+            assert bbox_err(got, ref, extents(P[pick]), n_per) <= TOL_F32, "seiler"
             del sc
         del Pd, ud, P
     torch.cuda.empty_cache()
