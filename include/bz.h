@@ -126,6 +126,23 @@ int bz_eval_rational(const void *ctrl, const void *w, int dtype, int64_t n_curve
 int bz_encode_piecewise(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream);
 
 /*
+ * Allocation-free variant of bz_encode_piecewise, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same results bit for
+ * bit; it allocates nothing (no hipMalloc, hipMallocAsync or hipFree): the
+ * encoder's block partials live in a fixed 2 MiB device array of the library
+ * (a copy per device, held until the process ends), whose address is looked
+ * up once per device on the first call with that device current.  Limit: the
+ * partials of ceil((n_seg+1)/2048) blocks x dim coordinates must fit 2^18
+ * doubles, i.e. n_seg <= floor(2^18/dim)*2048 - 1 (536870911, 268435455,
+ * 178956287, 134217727 for dim 1..4); larger n_seg returns BZ_ERR_SHAPE.
+ * Every call on one device uses that device's one array: calls that overlap
+ * in time on one device (different streams or threads) race and must be
+ * serialised by the caller.  The array needs no clearing between calls.
+ */
+int bz_encode_piecewise_noalloc(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream);
+
+/*
  * Evaluate the chain at global parameters T[n_q]: T is clamped to
  * [0, n_seg], segment k = min(floor(T), n_seg-1), local t = T - k, and the
  * point is the bilinear read of the 2x2 window [A_k x_{k+1}; x_k A_{k+1}]

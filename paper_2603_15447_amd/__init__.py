@@ -52,6 +52,7 @@ _SIGS = {
     "bz_eval_seiler": (_I, [_P, _I64, _I, _I, _P, _I64, _I, _P, _P]),
     "bz_eval_rational": (_I, [_P, _P, _I, _I64, _I, _I, _P, _I64, _I, _I, _F, _P, _P, _P]),
     "bz_encode_piecewise": (_I, [_P, _I64, _I, _P, _P]),
+    "bz_encode_piecewise_noalloc": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
     "bz_encode_piecewise_cubic": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_cubic": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -209,6 +210,19 @@ def encode_piecewise(chain, out=None):
     assert m == 2 * nseg + 1
     out = _f32_out((nseg + 1, 2, dim), chain.device, out)
     check(lib().bz_encode_piecewise(_ptr(chain), nseg, dim, _ptr(out), _stream()))
+    return out
+
+
+def encode_piecewise_noalloc(chain, out):
+    """As encode_piecewise, through the allocation-free entry point (its
+    workspace is the library's fixed per-device array); out is required, so
+    nothing is allocated on this path either."""
+    m, dim = chain.shape
+    nseg = (m - 1) // 2
+    assert m == 2 * nseg + 1
+    _f32_only("chain and grid", chain, out)
+    assert tuple(out.shape) == (nseg + 1, 2, dim) and out.is_contiguous()
+    check(lib().bz_encode_piecewise_noalloc(_ptr(chain), nseg, dim, _ptr(out), _stream()))
     return out
 
 

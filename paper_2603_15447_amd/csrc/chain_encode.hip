@@ -5,6 +5,8 @@
 // block partials, write): every texel is one FP32 rounding of an FP64 prefix
 // sum, where an FP32 recurrence x_{k+1} = 2 M_k - x_k would let the rounding
 // error grow with k.
+#include <mutex>
+
 #include "common.h"
 
 namespace bzi {
@@ -125,14 +127,53 @@ __global__ __launch_bounds__(kBlock) void k_enc_write(EncSrc e, int nch, const d
 }
 
 }  // namespace
+
+// Workspace of the allocation-free encoder: the block partials (one double
+// per block of kEncPerBlock columns and channel) in a file-scope device array.
+// Each device holds its own copy until the process ends; host code reaches it
+// only through the device address looked up per device below (the array's
+// name in host code is a host-side stand-in, not a device address).
+constexpr int64_t kEncScratchDoubles = int64_t(1) << 18;  // 2 MiB
+static __device__ __align__(256) double scratch[kEncScratchDoubles];
+
+namespace {
+
+// Largest chain the workspace holds: nb * dim <= kEncScratchDoubles with
+// nb = ceil((n_seg + 1) / kEncPerBlock).
+int64_t noalloc_max_seg(int dim) { return (kEncScratchDoubles / dim) * kEncPerBlock - 1; }
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+int scratch_address(const char *fn, double **out) {
+    int dev = 0;
+    BZ_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchMaxDevices) return fail(BZ_ERR_UNSUPPORTED, "%s: device %d", fn, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return BZ_OK;
+}
+
+}  // namespace
 }  // namespace bzi
 
 using namespace bzi;
 
 extern "C" {
 
+// ws: caller-provided workspace of at least nb*nch doubles, or NULL for a
+// stream-ordered allocation freed after the launches.
 static int encode_chain(const char *fn, const float *chain, int64_t n_seg, int dim, int cubic, float *grid,
-                        bz_stream stream) {
+                        bz_stream stream, double *ws = nullptr) {
     if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
     if (n_seg < 0 || n_seg > (int64_t(1) << 40)) return fail(BZ_ERR_SHAPE, "%s: n_seg %lld", fn, (long long)n_seg);
     if (n_seg == 0) return BZ_OK;
@@ -141,19 +182,39 @@ static int encode_chain(const char *fn, const float *chain, int64_t n_seg, int d
     const hipStream_t s = as_stream(stream);
     const int nch = dim * (cubic ? 2 : 1);
     const int64_t nb = (n_seg + 1 + kEncPerBlock - 1) / kEncPerBlock;
-    double *partial = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * nb * nch, s);
-    if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: workspace", fn);
-    BZ_CHECK_HIP(e);
+    double *partial = ws;
+    if (!ws) {
+        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&partial), sizeof(double) * nb * nch, s);
+        if (e == hipErrorOutOfMemory) return fail(BZ_ERR_NOMEM, "%s: workspace", fn);
+        BZ_CHECK_HIP(e);
+    }
+    // every partial is written by k_enc_partials before it is read: the
+    // workspace needs no clearing
     const EncSrc src{chain, n_seg, dim, cubic};
     hipLaunchKernelGGL(k_enc_partials, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, src, nch, partial);
     hipLaunchKernelGGL(k_enc_offsets, dim3(1), dim3(kBlock), 0, s, src, nch, nb, partial);
     hipLaunchKernelGGL(k_enc_write, dim3(static_cast<uint32_t>(nb)), dim3(kBlock), 0, s, src, nch, partial, grid);
     const hipError_t le = hipGetLastError();
-    BZ_CHECK_HIP(hipFreeAsync(partial, s));
+    if (!ws) BZ_CHECK_HIP(hipFreeAsync(partial, s));
     if (le != hipSuccess) return hip_fail(le, fn);
     return BZ_OK;
 }
+
+int bz_encode_piecewise_noalloc(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream) {
+    return guarded("bz_encode_piecewise_noalloc", [&]() -> int {
+        const char *fn = "bz_encode_piecewise_noalloc";
+        if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
+        if (n_seg < 0 || n_seg > noalloc_max_seg(dim))
+            return fail(BZ_ERR_SHAPE, "%s: n_seg %lld outside 0..%lld, the workspace limit for dim %d", fn,
+                        (long long)n_seg, (long long)noalloc_max_seg(dim), dim);
+        if (n_seg == 0) return BZ_OK;
+        double *ws = nullptr;
+        const int rc = scratch_address(fn, &ws);
+        if (rc) return rc;
+        return encode_chain(fn, chain, n_seg, dim, 0, grid, stream, ws);
+    });
+}
+
 
 int bz_encode_piecewise(const float *chain, int64_t n_seg, int dim, float *grid, bz_stream stream) {
     return guarded("bz_encode_piecewise",
