@@ -322,7 +322,8 @@ def batch_bytes(b, es):
     them: every control point (dim values) and the weight of every rational or
     NURBS control point in the storage type (es bytes), every knot (FP32),
     8 bytes of offsets per object and 8 more per NURBS (its knot offset), and
-    per query the parameter in and the point out (FP32).  The plan's own
+    per query the parameter in (two for a surface patch) and the point out
+    (FP32).  The plan's own
     derived data (class-sorted copies, extracted NURBS segments, tables) is
     not counted: it is the implementation's choice, not the problem's."""
     kind = b.kind_degree >> 8
@@ -330,6 +331,7 @@ def batch_bytes(b, es):
     nk = np.diff(b.knot_offset)
     rd = int(ncp.sum()) * b.dim * es + int(ncp[kind != 0].sum()) * es + int(nk.sum()) * 4
     rd += b.n_obj * 8 + int((kind == 2).sum()) * 8
+    rd += int((kind == 3).sum()) * b.n_t * 4  # a surface patch's second parameter v
     return rd + b.n_obj * b.n_t * (4 + 4 * b.dim)
 
 
@@ -825,7 +827,41 @@ def batched_record(torch, bz, bz_synth, cpu, n_sample=16384):
         del ctrl, w
         res[name] = e
     res["fp16_speedup"] = res["fp32"]["us"] / res["fp16"]["us"]
+    del t, out, kd, cpo, ko, kn
+    torch.cuda.empty_cache()
+    res["fp32_with_patches"] = batched_patches_record(torch, bz, bz_synth, cpu)
     return res
+
+
+def batched_patches_record(torch, bz, bz_synth, cpu, n_sample=8192):
+    """The same mixed batch plus 2^16 bicubic surface patches at 16 random
+    (u, v) each, FP32, in the one persistent launch (u from t, v from a second
+    parameter array)."""
+    log("batched: with 2^16 bicubic patches")
+    b = bz_synth.mixed_batch(n_patches=1 << 16)
+    n_q = b.n_obj * b.n_t
+    ctrl = torch.from_numpy(b.ctrl).cuda()
+    plan = bz.BatchPlan(torch.from_numpy(b.kind_degree.astype(np.int16)).cuda(), torch.from_numpy(b.cp_offset).cuda(),
+                        ctrl, torch.from_numpy(b.w).cuda(), 3, torch.from_numpy(b.knot_offset).cuda(),
+                        torch.from_numpy(b.knots).cuda(), b.n_t, "bernstein")
+    t, v = torch.from_numpy(b.t).cuda(), torch.from_numpy(b.v).cuda()
+    out = torch.empty((3, n_q), device="cuda")
+    plan.autotune(t, out)
+    ms = timed(lambda: plan(t, out=out, v=v), torch, iters=20)
+    nbytes = batch_bytes(b, 4)
+    rec = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"]}
+    if cpu:
+        import oracle
+        kinds = b.kind_degree >> 8
+        idx = np.unique(np.concatenate([np.random.default_rng(8).choice(b.n_obj, n_sample, replace=False),
+                                        np.nonzero(kinds == 3)[0][:256]]))
+        sub = b.subset(idx)
+        got = out.view(3, b.n_obj, b.n_t)[:, torch.from_numpy(idx).cuda()].reshape(3, -1).cpu().numpy()
+        ext = np.array([_box(sub.ctrl[sub.cp_offset[i] * 3:sub.cp_offset[i + 1] * 3].astype(np.float64).reshape(3, -1))
+                        for i in range(len(idx))])
+        rec["max_err_bbox"] = max_err_bbox(got, oracle.batch_eval(sub), ext, b.n_t)
+    plan.close()
+    return rec
 
 
 def _box(P):

@@ -23,6 +23,7 @@ SEEDS = {"plain": 1001, "chain": 1002, "batched": 1003, "patch": 1004,
 KIND_BEZIER = 0
 KIND_RATIONAL = 1
 KIND_NURBS = 2
+KIND_PATCH = 3
 
 
 def _f32(a):
@@ -100,12 +101,16 @@ def cubic_chain_walk(n_seg=1 << 20, dim=3, n_q=1 << 24, step=0.1, seed=SEEDS["ch
 class Batch:
     """Mixed batch of curves in one flat description.
 
-    kind_degree[o] = kind << 8 | degree   (kind 0 Bezier, 1 rational, 2 NURBS)
+    kind_degree[o] = kind << 8 | degree   (kind 0 Bezier, 1 rational, 2 NURBS,
+                   3 tensor-product surface patch with degree du << 4 | dv)
     cp_offset[o]   first control point of object o; ctrl holds, for object o,
                    a [dim][ncp_o] block starting at float index cp_offset[o]*dim
+                   (a patch's (du+1)(dv+1) points indexed i*(dv+1)+j)
     w              one weight per control point (1.0 for integral objects)
     knot_offset[o] first knot of object o (NURBS only; empty range otherwise)
-    t              [n_obj][n_t] parameters in [0,1)
+    t              [n_obj][n_t] parameters in [0,1) (a patch's u)
+    v              [n_obj][n_t] second parameters (a patch's v), or None
+                   when the batch has no patch
     """
     dim: int
     n_t: int
@@ -117,6 +122,7 @@ class Batch:
     knots: np.ndarray
     t: np.ndarray
     meta: dict = field(default_factory=dict)
+    v: np.ndarray = None
 
     @property
     def n_obj(self):
@@ -140,34 +146,48 @@ class Batch:
         return Batch(dim=self.dim, n_t=self.n_t, kind_degree=self.kind_degree[idx].copy(), cp_offset=cp,
                      ctrl=np.ascontiguousarray(self.ctrl[crd]), w=np.ascontiguousarray(self.w[pts]),
                      knot_offset=ko, knots=np.ascontiguousarray(self.knots[kts]),
-                     t=np.ascontiguousarray(self.t[idx]), meta=dict(self.meta))
+                     t=np.ascontiguousarray(self.t[idx]), meta=dict(self.meta),
+                     v=None if self.v is None else np.ascontiguousarray(self.v[idx]))
 
 
 def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_hi=15,
-                knots_lo=8, knots_hi=64, seed=SEEDS["batched"]):
+                knots_lo=8, knots_hi=64, seed=SEEDS["batched"], n_patches=0, patch_deg_lo=3, patch_deg_hi=3):
     """Bezier curves of degree U{deg_lo..deg_hi} (half of them rational with
     log-uniform weights in [0.25,4]) plus cubic NURBS with a clamped knot
     vector of K ~ U{knots_lo..knots_hi} knots (interior knots sorted U(0,1)),
-    K-4 control points and log-uniform weights.  Objects are shuffled.
-    Control points are U[-1,1]^dim; n_t parameters U[0,1) per object."""
+    K-4 control points and log-uniform weights, plus n_patches tensor-product
+    surface patches of degrees du, dv ~ U{patch_deg_lo..patch_deg_hi} (default
+    bicubic).  Objects are shuffled.  Control points are U[-1,1]^dim; n_t
+    parameters U[0,1) per object, and for batches with patches a second
+    parameter array v, U[0,1) (drawn last, so batches without patches are
+    unchanged)."""
     rng = np.random.default_rng(seed)
-    n_obj = n_bezier + n_nurbs
+    n_obj = n_bezier + n_nurbs + n_patches
     deg = rng.integers(deg_lo, deg_hi + 1, size=n_bezier)
     rational = rng.random(n_bezier) < 0.5
     kinds = np.where(rational, KIND_RATIONAL, KIND_BEZIER)
     K = rng.integers(knots_lo, knots_hi + 1, size=n_nurbs)
+    if n_patches:
+        pdu = rng.integers(patch_deg_lo, patch_deg_hi + 1, size=n_patches)
+        pdv = rng.integers(patch_deg_lo, patch_deg_hi + 1, size=n_patches)
     perm = rng.permutation(n_obj)
     kind_degree = np.empty(n_obj, dtype=np.uint16)
     ncp = np.empty(n_obj, dtype=np.int64)
     nknot = np.zeros(n_obj, dtype=np.int64)
     is_b = perm < n_bezier
+    is_n = (perm >= n_bezier) & (perm < n_bezier + n_nurbs)
+    is_p = perm >= n_bezier + n_nurbs
     bidx = perm[is_b]
-    nidx = perm[~is_b] - n_bezier
+    nidx = perm[is_n] - n_bezier
     kind_degree[is_b] = (kinds[bidx] << 8 | deg[bidx]).astype(np.uint16)
     ncp[is_b] = deg[bidx] + 1
-    kind_degree[~is_b] = np.uint16(KIND_NURBS << 8 | 3)
-    ncp[~is_b] = K[nidx] - 4
-    nknot[~is_b] = K[nidx]
+    kind_degree[is_n] = np.uint16(KIND_NURBS << 8 | 3)
+    ncp[is_n] = K[nidx] - 4
+    nknot[is_n] = K[nidx]
+    if n_patches:
+        pidx = perm[is_p] - n_bezier - n_nurbs
+        kind_degree[is_p] = (KIND_PATCH << 8 | pdu[pidx] << 4 | pdv[pidx]).astype(np.uint16)
+        ncp[is_p] = (pdu[pidx] + 1) * (pdv[pidx] + 1)
     cp_offset = np.zeros(n_obj + 1, dtype=np.int64)
     np.cumsum(ncp, out=cp_offset[1:])
     knot_offset = np.zeros(n_obj + 1, dtype=np.int64)
@@ -178,7 +198,7 @@ def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_
     ctrl = _f32(rng.uniform(-1.0, 1.0, size=total_cp * dim))
     w = log_uniform_weights(rng, total_cp)
     kind = kind_degree >> 8
-    integral = np.repeat(kind == KIND_BEZIER, ncp)
+    integral = np.repeat((kind == KIND_BEZIER) | (kind == KIND_PATCH), ncp)
     w[integral] = 1.0
     w = _f32(w)
     # Clamped knot vectors: 4 zeros, K-8 sorted uniforms, 4 ones.
@@ -196,9 +216,10 @@ def mixed_batch(n_bezier=1 << 20, n_nurbs=1 << 16, dim=3, n_t=16, deg_lo=2, deg_
         knots[b - 4:b] = 1.0
     knots = _f32(knots)
     t = _f32(rng.random((n_obj, n_t)))
+    v = _f32(rng.random((n_obj, n_t))) if n_patches else None
     return Batch(dim=dim, n_t=n_t, kind_degree=kind_degree, cp_offset=cp_offset, ctrl=ctrl,
                  w=w, knot_offset=knot_offset, knots=knots, t=t,
-                 meta={"n_bezier": n_bezier, "n_nurbs": n_nurbs})
+                 meta={"n_bezier": n_bezier, "n_nurbs": n_nurbs, "n_patches": n_patches}, v=v)
 
 
 # ---------------------------------------------------------------- tensor

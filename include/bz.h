@@ -321,16 +321,18 @@ int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw
 
 /*
  * Mixed batches in one persistent launch: integral and rational Bezier
- * curves of degree 1..15 and cubic NURBS (Sec. 2.2: B-splines are converted
- * to rational Bezier segments by knot insertion).  All descriptor arrays are
- * device pointers:
+ * curves of degree 1..15, cubic NURBS (Sec. 2.2: B-splines are converted to
+ * rational Bezier segments by knot insertion) and tensor-product surface
+ * patches (Sec. 2.2).  All descriptor arrays are device pointers:
  *   kind_degree[n_obj]   kind << 8 | degree; kind 0 Bezier, 1 rational,
- *                        2 NURBS (degree must be 3)
+ *                        2 NURBS (degree must be 3), 3 surface patch with
+ *                        degree du << 4 | dv, du and dv in 1..3
  *   cp_offset[n_obj+1]   first control point of each object; object o's
  *                        points are ctrl[cp_offset[o]*dim ...] as [dim][ncp]
+ *                        (a patch's (du+1)(dv+1) points indexed i*(dv+1)+j)
  *   ctrl, w              in dtype; w aligned with control points (ignored
- *                        for kind 0; may be NULL if no object is rational
- *                        or NURBS)
+ *                        for kinds 0 and 3; may be NULL if no object is
+ *                        rational or NURBS)
  *   knot_offset[n_obj+1], knots (FP32): NURBS knot vectors, clamped, of
  *                        length ncp+4; may be NULL if there is no NURBS
  *   n_t                  parameters per object
@@ -341,8 +343,11 @@ int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw
  * its own device memory: none of the descriptor arrays, ctrl or w is used
  * after bz_batch_plan_create returns (changed control points need a new
  * plan).  Parameters t[n_obj][n_t] (NURBS parameters are clamped to the knot
- * range) and out[dim][n_obj*n_t] are passed per evaluation (out must not
- * overlap t).  method:
+ * range; a patch's u) and out[dim][n_obj*n_t] are passed per evaluation (out
+ * must not overlap t); a plan with patches is evaluated by bz_batch_eval_uv,
+ * whose v[n_obj][n_t] holds the patches' second parameters (only the rows of
+ * patch objects are read), and bz_batch_eval returns BZ_ERR_NULL for it.
+ * method:
  * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects whose weights are all
  * positive are evaluated in FP32 (their conditioning number is 1).  Rational
  * objects with a weight that is zero, negative or NaN form classes of their
@@ -356,6 +361,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                          const void *w, int dtype, int dim, const int64_t *knot_offset, const float *knots,
                          int64_t n_t, int method, bz_stream stream, bz_plan *plan);
 int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
+int bz_batch_eval_uv(bz_plan plan, const float *t, const float *v, float *out, bz_stream stream);
 /*
  * Autotuner: times the persistent launch on (t, out) for 4 tile orders
  * (class-major, or window-major over blocks of 2^15, 2^17 or 2^18 consecutive
@@ -366,7 +372,8 @@ int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream);
  * when n_t is a multiple of 4 -- four consecutive parameters of one object per
  * lane) x 3 tile sizes (1, 2 or 4 sub-tiles of 256 lanes per tile) x 2
  * schedules (atomic tile counter, static round robin) x 4 grid sizes (4, 8,
- * 12, 16 workgroups per CU) and keeps the fastest in the plan.  Without
+ * 12, 16 workgroups per CU) and keeps the fastest in the plan.
+ * (The timing launches of a plan with patches read the patches' v from t.)  Without
  * autotuning a plan launches 8 workgroups per CU, 4 sub-tiles per tile, the
  * static schedule, windows of 2^17 objects and four parameters per lane when
  * n_t is a multiple of 4.  Synchronises the stream.  best6 (nullable, host, 6

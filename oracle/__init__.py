@@ -191,10 +191,15 @@ def batch_eval(batch):
     cpo = np.ascontiguousarray(batch.cp_offset, dtype=np.int64)
     ko = np.ascontiguousarray(batch.knot_offset, dtype=np.int64)
     ctrl, w, knots, t = _d(batch.ctrl), _d(batch.w), _d(batch.knots), _d(batch.t)
+    v = getattr(batch, "v", None)
+    if v is None:
+        assert not ((kd >> 8) == 3).any(), "patches need the second parameters v"
+    else:
+        v = _d(v)
     n_obj = kd.shape[0]
     out = np.empty((batch.dim, n_obj * batch.n_t))
     lib().bzo_batch_eval(_I64(n_obj), _ptr(kd), _ptr(cpo), _ptr(ctrl), _ptr(w), _ptr(ko),
-                         _ptr(knots if knots.size else np.zeros(1)), ctypes.c_int(batch.dim), _ptr(t),
+                         _ptr(knots if knots.size else np.zeros(1)), ctypes.c_int(batch.dim), _ptr(t), _ptr(v),
                          _I64(batch.n_t), _ptr(out))
     return out
 

@@ -354,13 +354,18 @@ void bzo_nurbs_eval(const double *ctrl, const double *w, const double *knots, in
     }
 }
 
+static double tensor_point(const double *P, int du, int dv, int dw, double u, double v, double w);
+
 /* Mixed batch: kind_degree[o] = kind<<8 | degree (0 Bezier, 1 rational,
- * 2 NURBS).  Object o's control points are ctrl[cp_offset[o]*dim ...] laid
- * out [dim][ncp]; w is aligned with control points; NURBS knots at
- * knots[knot_offset[o] ...].  t[n_obj][nt], out[dim][n_obj*nt].           */
+ * 2 NURBS, 3 tensor-product surface patch with degree byte du<<4 | dv, Sec.
+ * 2.2).  Object o's control points are ctrl[cp_offset[o]*dim ...] laid out
+ * [dim][ncp] (a patch's ncp = (du+1)(dv+1) points indexed i*(dv+1)+j); w is
+ * aligned with control points; NURBS knots at knots[knot_offset[o] ...].
+ * t[n_obj][nt] (a patch's u), v[n_obj][nt] (a patch's v; read for patches
+ * only, may be NULL without them), out[dim][n_obj*nt].                     */
 void bzo_batch_eval(int64_t n_obj, const uint16_t *kind_degree, const int64_t *cp_offset,
                     const double *ctrl, const double *w, const int64_t *knot_offset,
-                    const double *knots, int dim, const double *t, int64_t nt, double *out)
+                    const double *knots, int dim, const double *t, const double *v, int64_t nt, double *out)
 {
     const int64_t nq = n_obj * nt;
 #pragma omp parallel for schedule(dynamic, 256)
@@ -376,8 +381,11 @@ void bzo_batch_eval(int64_t n_obj, const uint16_t *kind_degree, const int64_t *c
                 for (int k = 0; k < dim; ++k) res[k] = decasteljau(P + k * ncp, 1, deg, tt);
             } else if (kind == 1) {
                 rational_point(P, W, dim, deg, tt, res);
-            } else {
+            } else if (kind == 2) {
                 nurbs_point(P, ncp, W, knots + knot_offset[o], ncp, deg, dim, tt, res);
+            } else {
+                const int du = deg >> 4, dv = deg & 15;
+                for (int k = 0; k < dim; ++k) res[k] = tensor_point(P + k * ncp, du, dv, 0, tt, v[o * nt + j], 0.0);
             }
             for (int k = 0; k < dim; ++k) out[k * nq + o * nt + j] = res[k];
         }

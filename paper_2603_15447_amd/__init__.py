@@ -78,6 +78,7 @@ _SIGS = {
     "bz_eval_tensor_patch": (_I, [_P, _I, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
     "bz_batch_plan_create": (_I, [_I64, _P, _P, _P, _P, _I, _I, _P, _P, _I64, _I, _P, ctypes.POINTER(_P)]),
     "bz_batch_eval": (_I, [_P, _P, _P, _P]),
+    "bz_batch_eval_uv": (_I, [_P, _P, _P, _P, _P]),
     "bz_batch_plan_autotune": (_I, [_P, _P, _P, _P, _P]),
     "bz_batch_plan_info": (_I, [_P, _P]),
     "bz_batch_plan_configure": (_I, [_P, _I64, _I, _I, _I, _I64, _P]),
@@ -433,6 +434,10 @@ def eval_tensor_seiler(sc, du, dv, dw=0, uvw=None, nu=0, nv=0, out=None):
 
 
 # ---------------------------------------------------------------- batched
+SCHEDULES = {"static": 0, "dynamic": 1}
+SCHEDULES_BY_CODE = {v: k for k, v in SCHEDULES.items()}
+
+
 class BatchPlan:
     """Plan for a mixed batch (see bz_batch_plan_create)."""
 
@@ -455,16 +460,23 @@ class BatchPlan:
         buf = (ctypes.c_int64 * 6)()
         check(lib().bz_batch_plan_autotune(self._h, _ptr(t), _ptr(out), _stream(), ctypes.cast(buf, _P)))
         return {"workgroups": buf[0], "tile_multiple": buf[1], "us_per_launch": buf[2],
-                "schedule": "dynamic" if buf[3] else "static", "queries_per_lane": buf[4], "window": buf[5]}
+                "schedule": SCHEDULES_BY_CODE[buf[3]], "queries_per_lane": buf[4], "window": buf[5]}
 
     def configure(self, workgroups, sub_tiles=1, schedule="dynamic", queries_per_lane=1, window=0):
-        check(lib().bz_batch_plan_configure(self._h, workgroups, sub_tiles, 1 if schedule == "dynamic" else 0,
-                                            queries_per_lane, window, _stream()))
+        """schedule: "dynamic" (atomic tile counter) or "static" (round robin)."""
+        check(lib().bz_batch_plan_configure(self._h, workgroups, sub_tiles, SCHEDULES[schedule], queries_per_lane,
+                                            window, _stream()))
 
-    def __call__(self, t, out=None):
-        assert t.shape == (self.n_obj, self.n_t)
+    def __call__(self, t, out=None, v=None):
+        """t[n_obj, n_t] (a patch's u) and, for plans with surface patches,
+        v[n_obj, n_t] (a patch's v) -> out[dim, n_obj*n_t]."""
+        _f32_only("t and v", t, v)
+        assert t.shape == (self.n_obj, self.n_t) and (v is None or v.shape == t.shape)
         out = _f32_out((self.dim, self.n_obj * self.n_t), self.device, out)
-        check(lib().bz_batch_eval(self._h, _ptr(t), _ptr(out), _stream()))
+        if v is None:
+            check(lib().bz_batch_eval(self._h, _ptr(t), _ptr(out), _stream()))
+        else:
+            check(lib().bz_batch_eval_uv(self._h, _ptr(t), _ptr(v), _ptr(out), _stream()))
         return out
 
     def close(self):

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sorted(int64_t n_sorted, cons
     const ClassInfo ci = classes[c];
     if (ci.kind == 2) return;
     const int64_t slot = i - ci.first, o = perm[i];
-    const int n = (ci.degree + 1) * dim;
+    const int n = class_ncp(ci.kind, ci.degree) * dim;
     const U *src = ctrl + cp_offset[o] * dim;
     U *dst = ctrl_s + ci.ctrl_base + slot * n;
     for (int e = 0; e < n; ++e) dst[e] = src[e];
@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_weight_flags(int64_t n_obj, const ui
     const int64_t o = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (o >= n_obj) return;
     uint8_t f = 0;
-    if ((kind_degree[o] >> 8) != 0)
+    const int kind = kind_degree[o] >> 8;
+    if (kind == 1 || kind == 2)
         for (int64_t i = cp_offset[o]; i < cp_offset[o + 1]; ++i) f |= !(to_f32<T>(w[i]) > 0.0f);
     flags[o] = f;
 }
@@ -180,6 +181,11 @@ constexpr uint32_t kDefaultWindow = 131072;
 int class_cost(int kind, int degree, int method, int dim) {
     const int ch = dim + (kind != 0 ? 1 : 0);
     if (kind == 2) return 60 + 4 * ch;
+    if (kind == 4) {
+        const int du = degree >> 4, dv = degree & 15, ncp = (du + 1) * (dv + 1);
+        if (method == BZ_DECASTELJAU) return ((du + 1) * dv * (dv + 1) / 2 + du * (du + 1) / 2) * 2 * dim + 8;
+        return 3 * (du + dv) + ncp * dim + 8;
+    }
     if (kind == 3) return 4 * degree + (degree + 1) * (ch + 2) + 8 + (method == BZ_DECASTELJAU ? degree * (degree + 1) / 2 * ch * 2 : 0);
     if (method == BZ_DECASTELJAU) return degree * (degree + 1) / 2 * ch * 2 + 8;
     return 3 * degree + (degree + 1) * ch + 8;
@@ -205,6 +211,7 @@ struct bz_plan_s {
     std::vector<ClassInfo> classes;
     std::vector<int32_t> perm_h;  // host copy of perm (window boundaries of the tile order)
     uint32_t n_tiles = 0, n_signed = 0, qpt = 1, vq = 1, window = 0;
+    bool has_patches = false;
     int64_t n_segs = 0;
     uint32_t workgroups = 0, cus = 1;
     int dynamic = 1;
@@ -236,7 +243,7 @@ int dev_upload(X **dst, const std::vector<X> &src, hipStream_t s) {
     return BZ_OK;
 }
 
-int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, uint32_t workgroups,
+int launch_batch(const bz_plan_s *p, const float *t, const float *v, float *out, hipStream_t s, uint32_t workgroups,
                  int dynamic, uint32_t vq) {
     BatchArgs a;
     a.vq = static_cast<int>(vq);
@@ -252,6 +259,7 @@ int launch_batch(const bz_plan_s *p, const float *t, float *out, hipStream_t s, 
     a.brk = p->brk;
     a.seg = p->seg;
     a.t = t;
+    a.v = v;
     a.out = out;
     a.plane = p->n_obj * p->n_t;
     a.n_t = static_cast<uint32_t>(p->n_t);
@@ -286,7 +294,8 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, uint32_t window, hipStr
     });
     std::vector<Tile> tiles;
     auto emit = [&](int c, uint64_t a, uint64_t b) {  // queries [a, b) of class c
-        const uint64_t span = static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 0 || cls[c].kind == 1 ? vq : 1);
+        const uint64_t span =
+            static_cast<uint64_t>(kBlock) * qpt * (cls[c].kind == 0 || cls[c].kind == 1 || cls[c].kind == 4 ? vq : 1);
         for (uint64_t q0 = a; q0 < b; q0 += span)
             tiles.push_back(Tile{cls[c], static_cast<uint32_t>(q0), static_cast<uint32_t>(b), qpt, 0});
     };
@@ -361,8 +370,14 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         for (int64_t o = 0; o < n_obj; ++o) {
             const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
             const int64_t ncp = cpo[o + 1] - cpo[o];
-            if (kind > 2) return fail(BZ_ERR_SHAPE, "%s: object %lld has kind %d", fn, (long long)o, kind);
-            if (kind == 2) {
+            if (kind > 3) return fail(BZ_ERR_SHAPE, "%s: object %lld has kind %d", fn, (long long)o, kind);
+            if (kind == 3) {
+                const int du = deg >> 4, dv = deg & 15;
+                if (du < 1 || du > 3 || dv < 1 || dv > 3)
+                    return fail(BZ_ERR_UNSUPPORTED, "%s: patch object %lld has degree (%d, %d) (1..3 each)", fn, (long long)o, du, dv);
+                if (ncp != (du + 1) * (dv + 1))
+                    return fail(BZ_ERR_SHAPE, "%s: patch object %lld has %lld control points for degree (%d, %d)", fn, (long long)o, (long long)ncp, du, dv);
+            } else if (kind == 2) {
                 if (deg != kNurbsP) return fail(BZ_ERR_UNSUPPORTED, "%s: NURBS object %lld has degree %d (only cubic)", fn, (long long)o, deg);
                 if (ncp < 4) return fail(BZ_ERR_SHAPE, "%s: NURBS object %lld has %lld control points", fn, (long long)o, (long long)ncp);
                 any_nurbs = true;
@@ -370,7 +385,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
                 if (deg < 1 || deg > kMaxDegree) return fail(BZ_ERR_SHAPE, "%s: object %lld degree %d", fn, (long long)o, deg);
                 if (ncp != deg + 1) return fail(BZ_ERR_SHAPE, "%s: object %lld has %lld control points for degree %d", fn, (long long)o, (long long)ncp, deg);
             }
-            if (kind != 0) need_w = true;
+            if (kind == 1 || kind == 2) need_w = true;
         }
         if (need_w && !w) return fail(BZ_ERR_NULL, "%s: weights are required (rational or NURBS objects)", fn);
         if (!aligned(ctrl, dtype_size(dtype)) || !aligned(w, dtype_size(dtype)))
@@ -400,12 +415,13 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         }
         // classes, keyed: 0..14 integral Bezier of degree 1..15, 15..29
         // rational with positive weights, 30..44 rational with a weight <= 0
-        // (conditioning test), 45 cubic NURBS (last, so the NURBS rank is its
-        // slot in the last class)
-        constexpr int kKeys = 46, kNurbsKey = 45;
+        // (conditioning test), 45..53 patches of degree (du, dv) in 1..3, 54
+        // cubic NURBS (last, so the NURBS rank is its slot in the last class)
+        constexpr int kKeys = 55, kPatchKey = 45, kNurbsKey = 54;
         auto key_of = [&](int64_t o) {
             const int kind = kd[o] >> 8, deg = kd[o] & 0xff;
             if (kind == 2) return kNurbsKey;
+            if (kind == 3) return kPatchKey + ((deg >> 4) - 1) * 3 + (deg & 15) - 1;
             if (kind == 1 && wflag[o]) return 30 + deg - 1;
             return kind * 15 + deg - 1;
         };
@@ -423,13 +439,21 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         for (int key = 0; key < kKeys; ++key) {
             if (count[key] == 0) continue;
             ClassInfo ci;
-            ci.kind = key == kNurbsKey ? 2 : (key / 15 == 2 ? 3 : key / 15);
-            ci.degree = key == kNurbsKey ? kNurbsP : key % 15 + 1;
+            if (key == kNurbsKey) {
+                ci.kind = 2;
+                ci.degree = kNurbsP;
+            } else if (key >= kPatchKey) {
+                ci.kind = 4;
+                ci.degree = ((key - kPatchKey) / 3 + 1) << 4 | ((key - kPatchKey) % 3 + 1);
+            } else {
+                ci.kind = key / 15 == 2 ? 3 : key / 15;
+                ci.degree = key % 15 + 1;
+            }
             ci.first = first;
             ci.count = static_cast<int32_t>(count[key]);
             ci.ctrl_base = ctrl_elems;
             ci.w_base = w_elems;
-            if (ci.kind != 2) ctrl_elems += count[key] * (ci.degree + 1) * dim;
+            if (ci.kind != 2) ctrl_elems += count[key] * class_ncp(ci.kind, ci.degree) * dim;
             if (ci.kind == 1 || ci.kind == 3) w_elems += count[key] * (ci.degree + 1);
             cls_of_key[key] = static_cast<int32_t>(cls.size());
             cls.push_back(ci);
@@ -487,6 +511,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         p->dtype = dtype;
         p->method = method;
         p->classes = cls;
+        for (const ClassInfo &ci : cls) p->has_patches = p->has_patches || ci.kind == 4;
         p->n_segs = seg_first.back();
         const int es = dtype_size(dtype);
         auto dmalloc = [&](void **ptr, size_t bytes) -> int {
@@ -584,14 +609,23 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
     });
 }
 
+static int batch_eval(const char *fn, bz_plan plan, const float *t, const float *v, float *out, bz_stream stream) {
+    if (!plan) return fail(BZ_ERR_NULL, "%s: plan is required", fn);
+    if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
+    if (!t || !out) return fail(BZ_ERR_NULL, "%s: t and out are required", fn);
+    if (plan->has_patches && !v)
+        return fail(BZ_ERR_NULL, "%s: the plan has surface patches, which need v (bz_batch_eval_uv)", fn);
+    if (!aligned(t, 4) || !aligned(v, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "%s: misaligned", fn);
+    return launch_batch(plan, t, v, out, as_stream(stream), plan->workgroups, plan->dynamic, plan->vq);
+}
+
 int bz_batch_eval(bz_plan plan, const float *t, float *out, bz_stream stream) {
-    return guarded("bz_batch_eval", [&]() -> int {
-        if (!plan) return fail(BZ_ERR_NULL, "bz_batch_eval: plan is required");
-        if (plan->n_obj == 0 || plan->n_t == 0) return BZ_OK;
-        if (!t || !out) return fail(BZ_ERR_NULL, "bz_batch_eval: t and out are required");
-        if (!aligned(t, 4) || !aligned(out, 4)) return fail(BZ_ERR_ALIGN, "bz_batch_eval: misaligned");
-        return launch_batch(plan, t, out, as_stream(stream), plan->workgroups, plan->dynamic, plan->vq);
-    });
+    return guarded("bz_batch_eval", [&]() -> int { return batch_eval("bz_batch_eval", plan, t, nullptr, out, stream); });
+}
+
+int bz_batch_eval_uv(bz_plan plan, const float *t, const float *v, float *out, bz_stream stream) {
+    return guarded("bz_batch_eval_uv",
+                   [&]() -> int { return batch_eval("bz_batch_eval_uv", plan, t, v, out, stream); });
 }
 
 int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream stream, int64_t *best6) {
@@ -623,32 +657,37 @@ int bz_batch_plan_autotune(bz_plan plan, const float *t, float *out, bz_stream s
                 for (uint32_t q : qpts) layouts.push_back(Layout{win, vq, q});
             }
         }
+        // best of three rounds of 5 launches: one round is noisy enough to rank
+        // close configurations wrongly.  Patches read their v from t while
+        // timing (same size and layout).
+        auto time_cfg = [&](uint32_t wg, int dyn, uint32_t vq, float *ms_out) -> int {
+            int r0 = launch_batch(plan, t, t, out, s, wg, dyn, vq);  // warm-up
+            float ms = 1e30f;
+            for (int round = 0; round < 3 && !r0; ++round) {
+                BZ_CHECK_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 5 && !r0; ++r) r0 = launch_batch(plan, t, t, out, s, wg, dyn, vq);
+                if (r0) break;
+                BZ_CHECK_HIP(hipEventRecord(e1, s));
+                BZ_CHECK_HIP(hipEventSynchronize(e1));
+                float r_ms = 0;
+                BZ_CHECK_HIP(hipEventElapsedTime(&r_ms, e0, e1));
+                ms = std::min(ms, r_ms);
+            }
+            *ms_out = ms;
+            return r0;
+        };
         int rc = BZ_OK;
         for (const Layout &L : layouts) {
             rc = build_tiles(plan, L.q, L.vq, L.win, s);
             if (rc) break;
             for (int dyn = 1; dyn >= 0 && !rc; --dyn)
                 for (uint32_t f : wg_per_cu) {
-                    const uint32_t wg = f * cus;
-                    rc = launch_batch(plan, t, out, s, wg, dyn, L.vq);  // warm-up
-                    if (rc) break;
-                    // best of three rounds of 5 launches: one round is noisy enough
-                    // to rank close configurations wrongly
-                    float ms = 1e30f;
-                    for (int round = 0; round < 3 && !rc; ++round) {
-                        BZ_CHECK_HIP(hipEventRecord(e0, s));
-                        for (int r = 0; r < 5 && !rc; ++r) rc = launch_batch(plan, t, out, s, wg, dyn, L.vq);
-                        if (rc) break;
-                        BZ_CHECK_HIP(hipEventRecord(e1, s));
-                        BZ_CHECK_HIP(hipEventSynchronize(e1));
-                        float r_ms = 0;
-                        BZ_CHECK_HIP(hipEventElapsedTime(&r_ms, e0, e1));
-                        ms = std::min(ms, r_ms);
-                    }
+                    float ms = 0;
+                    rc = time_cfg(f * cus, dyn, L.vq, &ms);
                     if (rc) break;
                     if (ms < best) {
                         best = ms;
-                        best_wg = wg;
+                        best_wg = f * cus;
                         best_q = L.q;
                         best_dyn = dyn;
                         best_vq = L.vq;

@@ -10,8 +10,9 @@ namespace bzi {
 constexpr int kNurbsP = 3;
 
 struct ClassInfo {
-    int32_t kind;       // 0 Bezier, 1 rational (all weights > 0), 2 NURBS, 3 rational with a weight <= 0
-    int32_t degree;     // 1..15 (3 for NURBS)
+    int32_t kind;       // 0 Bezier, 1 rational (all weights > 0), 2 NURBS, 3 rational with a weight <= 0,
+                        // 4 tensor-product surface patch
+    int32_t degree;     // 1..15 (3 for NURBS; du << 4 | dv for patches)
     int32_t first;      // first slot of the class in perm
     int32_t count;      // objects in the class
     int64_t ctrl_base;  // first element of the class in the sorted control points
@@ -62,6 +63,11 @@ __host__ __device__ inline int nurbs_bucket(float u, float lo, float inv_h, int 
     return static_cast<int>(x);
 }
 
+// Control points per object of a class: degree+1, or (du+1)(dv+1) for a patch.
+__host__ __device__ inline int class_ncp(int kind, int degree) {
+    return kind == 4 ? ((degree >> 4) + 1) * ((degree & 15) + 1) : degree + 1;
+}
+
 struct BatchArgs {
     const void *ctrl_s;        // control points in class-sorted order (plan copy)
     const void *w_s;           // weights of rational objects, class-sorted (plan copy)
@@ -74,6 +80,7 @@ struct BatchArgs {
     const float *brk;          // breakpoints, nseg+1 per NURBS, from NurbsHead::brk0
     const float *seg;          // [n_segs][4][dim+1] homogeneous
     const float *t;
+    const float *v;            // second parameters (patches' v), [n_obj][n_t]; read for patches only
     float *out;
     int64_t plane;
     uint32_t n_t;
@@ -496,6 +503,104 @@ __device__ __forceinline__ void run_nurbs_tile_dim(const BatchArgs &a, const Til
     }
 }
 
+// Tensor-product surface patches (Sec. 2.2: the surface is the tensor product
+// of two curve bases): control points [dim][(DU+1)(DV+1)], index i*(DV+1)+j
+// (u major).  Bernstein form: both bases, then the double sum; de Casteljau
+// form: each u-row reduced in v, then the column in u.
+template <int DU, int DV, int F>
+__device__ __forceinline__ float patch_value(const float (&P)[(DU + 1) * (DV + 1)], const float (&Bu)[DU + 1],
+                                             const float (&Bv)[DV + 1], float u, float v) {
+    float col[DU + 1];
+#pragma unroll
+    for (int i = 0; i <= DU; ++i) {
+        float row[DV + 1];
+#pragma unroll
+        for (int j = 0; j <= DV; ++j) row[j] = P[i * (DV + 1) + j];
+        col[i] = F == FORM_BERN ? dot_basis<DV>(Bv, row) : eval_dc<DV>(row, v);
+    }
+    return F == FORM_BERN ? dot_basis<DU>(Bu, col) : eval_dc<DU>(col, u);
+}
+
+// VQ consecutive queries of one patch per lane (VQ = 4 needs n_t % 4 == 0):
+// the patch's net is loaded once for them, u and v come in VQ-wide loads and
+// each coordinate leaves in one VQ-wide store.
+template <int DU, int DV, int F, typename T, int VQ>
+__device__ __forceinline__ void run_patch_tile(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
+    constexpr int NCP = (DU + 1) * (DV + 1);
+    const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
+    uint32_t slot[kMaxQpt];
+    int64_t q[kMaxQpt];
+    bool ok[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        const uint32_t qi = tl.q0 + VQ * (s * kBlock + threadIdx.x);
+        ok[s] = s < static_cast<int>(tl.qpt) && qi < tl.q1;
+        const uint32_t qc = min(qi, nq - VQ);
+        slot[s] = fdiv(qc, a.div_nt);
+        q[s] = qc - slot[s] * a.n_t;  // j for now
+    }
+    int64_t o[kMaxQpt];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) o[s] = a.perm[tl.ci.first + slot[s]];
+    float uu[kMaxQpt][VQ], vv[kMaxQpt][VQ];
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        q[s] += o[s] * a.n_t;
+        if constexpr (VQ == 4) {
+            const f4u x = *reinterpret_cast<const f4u *>(a.t + q[s]);
+            const f4u y = *reinterpret_cast<const f4u *>(a.v + q[s]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) uu[s][e] = x[e], vv[s][e] = y[e];
+        } else {
+            uu[s][0] = a.t[q[s]];
+            vv[s][0] = a.v[q[s]];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kMaxQpt; ++s) {
+        if (!ok[s]) continue;
+        const T *P = static_cast<const T *>(a.ctrl_s) + tl.ci.ctrl_base + static_cast<size_t>(slot[s]) * NCP * a.dim;
+        float Bu[VQ][DU + 1], Bv[VQ][DV + 1];
+        if constexpr (F == FORM_BERN) {
+#pragma unroll
+            for (int e = 0; e < VQ; ++e) {
+                bernstein_basis<DU>(uu[s][e], Bu[e]);
+                bernstein_basis<DV>(vv[s][e], Bv[e]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+            if (k < a.dim) {
+                float p[NCP];
+                load_row<T, NCP>(P + k * NCP, p);
+                if constexpr (VQ == 4) {
+                    f4u r;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) r[e] = patch_value<DU, DV, F>(p, Bu[e], Bv[e], uu[s][e], vv[s][e]);
+                    __builtin_nontemporal_store(r, reinterpret_cast<f4u *>(out + k * a.plane + q[s]));
+                } else {
+                    st_stream(out + k * a.plane + q[s], patch_value<DU, DV, F>(p, Bu[0], Bv[0], uu[s][0], vv[s][0]));
+                }
+            }
+        }
+    }
+}
+
+template <int F, typename T, int VQ>
+__device__ __forceinline__ void dispatch_patch(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
+    switch (tl.ci.degree) {
+        case 0x11: run_patch_tile<1, 1, F, T, VQ>(a, tl, out); break;
+        case 0x12: run_patch_tile<1, 2, F, T, VQ>(a, tl, out); break;
+        case 0x13: run_patch_tile<1, 3, F, T, VQ>(a, tl, out); break;
+        case 0x21: run_patch_tile<2, 1, F, T, VQ>(a, tl, out); break;
+        case 0x22: run_patch_tile<2, 2, F, T, VQ>(a, tl, out); break;
+        case 0x23: run_patch_tile<2, 3, F, T, VQ>(a, tl, out); break;
+        case 0x31: run_patch_tile<3, 1, F, T, VQ>(a, tl, out); break;
+        case 0x32: run_patch_tile<3, 2, F, T, VQ>(a, tl, out); break;
+        default: run_patch_tile<3, 3, F, T, VQ>(a, tl, out); break;
+    }
+}
+
 template <int D, bool RAT, int F, typename T, int VQ>
 __device__ __forceinline__ void run_curve_tile_vq(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     if constexpr (VQ == 4) run_curve_tile4<D, RAT, F, T>(a, tl, out);
@@ -549,6 +654,7 @@ __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile, 
     const Tile tl = a.tiles[tile];
     if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl, out);
     else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl, out);
+    else if (tl.ci.kind == 4) dispatch_patch<F, T, VQ>(a, tl, out);
     else run_nurbs_tile_dim(a, tl, out);
 }
 
@@ -605,7 +711,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_signed(BatchArgs a, float *__r
 
 }  // namespace batch_dev
 
-// Launch of the persistent kernel (instantiated in batched_{dc,bern}_{f32,f16,bf16}.hip).
+// Launch of the persistent kernel (instantiated in batched_{dc,bern}_{f32,f16,bf16}.hip),
+// then the signed-weight rationals' own launch.
 template <int F, typename T>
 int launch_batch_kernel(uint32_t workgroups, const BatchArgs &a, hipStream_t s) {
     if (a.vq == 4)

@@ -308,6 +308,11 @@ def test_signed_weight_rationals(orc, method, dtype):
     scale = np.maximum(np.repeat(_extents(rb), b.n_t)[None, :], np.abs(ref))
     assert np.isfinite(got).all() or np.array_equal(np.isfinite(got), np.isfinite(ref))
     assert (np.abs(got - ref) / scale).max() <= TOL_F32
+    # the signed classes' launch follows the persistent one in every configuration
+    for cfg in ((64, 1, "dynamic", 1, 0), (512, 4, "static", 4, 300)):
+        plan.configure(*cfg)
+        got = host(plan(to_dev(b.t)))
+        assert (np.abs(got - ref) / scale).max() <= TOL_F32, cfg
     # the same objects through bz_eval_rational (its own FP64 recomputation) agree
     for o in np.nonzero(b.kind_degree >> 8 == 1)[0][:50]:
         a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
@@ -325,3 +330,72 @@ def test_signed_nurbs_weights_are_refused():
     with pytest.raises(bz.BzError) as e:
         _plan(b)
     assert e.value.code == bz.ERR_UNSUPPORTED
+
+
+def _plan_uv(b, dtype=torch.float32, method="bernstein"):
+    plan, dev = _plan(b, dtype=dtype, method=method)
+    return plan, dev, to_dev(b.t), to_dev(b.v)
+
+
+@pytest.mark.parametrize("method", ["bernstein", "decasteljau"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+@pytest.mark.parametrize("n_t", [16, 5])
+def test_batch_with_patches(orc, method, dtype, n_t):
+    """Surface patches of degree (1..3, 1..3) in the same persistent launch as
+    curves, rational curves and NURBS (Sec. 2.2): every point against the
+    oracle (on the rounded inputs for FP16 storage), for both lane mappings,
+    both schedules and the window-major order."""
+    b = bz_synth.mixed_batch(n_bezier=2000, n_nurbs=200, n_patches=900, n_t=n_t, patch_deg_lo=1, patch_deg_hi=3,
+                             seed=60 + n_t)
+    plan, dev, t, v = _plan_uv(b, dtype, method)
+    rb = bz_synth.Batch(**{**b.__dict__})
+    rb.ctrl = dev["ctrl"].float().cpu().numpy()
+    rb.w = dev["w"].float().cpu().numpy()
+    ref = orc.batch_eval(rb)
+    ext = _extents(rb)
+    assert plan.info()["n_classes"] == len(set(b.kind_degree.tolist()))
+    assert _err(host(plan(t, v=v)), ref, ext, n_t) <= TOL_F32
+    configs = [(300, 1, "static", 1, 0), (64, 2, "dynamic", 1, 500), (512, 4, "static", 1, 400)]
+    if n_t % 4 == 0:
+        configs += [(300, 4, "static", 4, 0), (512, 1, "dynamic", 4, 700)]
+    for cfg in configs:
+        plan.configure(*cfg)
+        out = torch.full((3, b.n_obj * n_t), float("nan"), device=t.device)
+        assert _err(host(plan(t, out=out, v=v)), ref, ext, n_t) <= TOL_F32, cfg
+
+
+def test_batch_patches_need_v_and_degrees():
+    b = bz_synth.mixed_batch(n_bezier=20, n_nurbs=2, n_patches=5, n_t=4, seed=61)
+    plan, dev, t, v = _plan_uv(b)
+    with pytest.raises(bz.BzError) as e:
+        plan(t)  # no v for the patches
+    assert e.value.code == bz.ERR_NULL
+    plan(t, v=v)
+    kd = b.kind_degree.copy()
+    kd[np.nonzero(kd >> 8 == 3)[0][0]] = (3 << 8) | (4 << 4) | 1  # du = 4
+    with pytest.raises(bz.BzError) as e:
+        _plan(bz_synth.Batch(**{**b.__dict__, "kind_degree": kd}))
+    assert e.value.code == bz.ERR_UNSUPPORTED
+
+
+def test_autotune_with_patches(orc):
+    b = bz_synth.mixed_batch(n_bezier=20000, n_nurbs=2000, n_patches=4000, n_t=16, seed=62)
+    plan, dev, t, v = _plan_uv(b)
+    out = torch.empty((3, b.n_obj * 16), device=t.device)
+    plan.autotune(t, out)
+    out.fill_(float("nan"))
+    assert _err(host(plan(t, out=out, v=v)), orc.batch_eval(b), _extents(b), 16) <= TOL_F32
+
+
+def test_config_batched_with_patches_sampled(orc):
+    """The mixed workload plus 2^16 bicubic patches at 16 random (u, v) each,
+    in one launch: a random sample of 16384 objects against the oracle."""
+    b = bz_synth.mixed_batch(n_patches=1 << 16)
+    kinds = b.kind_degree >> 8
+    rng = np.random.default_rng(63)
+    idx = np.unique(np.concatenate([rng.choice(b.n_obj, 16384, replace=False), [0, b.n_obj - 1],
+                                    np.nonzero(kinds == 3)[0][[0, -1]]]))
+    sub = b.subset(idx)
+    plan, dev, t, v = _plan_uv(b)
+    got = host(plan(t, v=v).view(3, b.n_obj, 16)[:, torch.from_numpy(idx).cuda()].reshape(3, -1))
+    assert _err(got, orc.batch_eval(sub), _extents(sub), 16) <= TOL_F32

@@ -244,3 +244,46 @@ def test_volume_corners_exact(orc):
     for o in range(3):
         for idx, (i, j, k) in enumerate(corners.astype(int)):
             np.testing.assert_array_equal(got[:, o, idx], ctrl[o, :, (i * 3 * 4 + j * 3) * 4 + k * 3])
+
+
+def test_batch_patches_exact_brute_force(orc):
+    """Surface patches inside a mixed batch (kind 3, degree byte du<<4 | dv,
+    Sec. 2.2): every point equals the exact tensor-product Bernstein double
+    sum of its net at its (u, v), for bilinear to bicubic patches and mixed
+    degrees, with curves and NURBS around them."""
+    from tests._exact import F, tensor
+    b = bz_synth.mixed_batch(n_bezier=30, n_nurbs=6, n_patches=40, n_t=3, patch_deg_lo=1, patch_deg_hi=3, seed=21)
+    out = orc.batch_eval(b)
+    kinds = b.kind_degree >> 8
+    assert (kinds == 3).sum() == 40 and len(set((b.kind_degree[kinds == 3] & 0xff).tolist())) > 4
+    for o in np.nonzero(kinds == 3)[0]:
+        du, dv = int(b.kind_degree[o] & 0xff) >> 4, int(b.kind_degree[o] & 15)
+        a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
+        assert a1 - a0 == (du + 1) * (dv + 1)
+        P = b.ctrl[a0 * 3:a1 * 3].reshape(3, -1)
+        for j in range(3):
+            u, v = F(b.t[o, j]), F(b.v[o, j])
+            for k in range(3):
+                want = tensor([F(x) for x in P[k]], du, dv, 0, u, v, 0)
+                assert abs(out[k, o * 3 + j] - float(want)) <= 1e-15 * max(1.0, abs(float(want)))
+
+
+def test_batch_bilinear_patch_closed_form(orc):
+    """A (1,1) patch in a batch is the bilinear interpolation of its corners,
+    (1-u)(1-v)P00 + (1-u)v P01 + u(1-v)P10 + uv P11."""
+    b = bz_synth.mixed_batch(n_bezier=0, n_nurbs=0, n_patches=25, n_t=7, patch_deg_lo=1, patch_deg_hi=1, seed=22)
+    out = orc.batch_eval(b).reshape(3, 25, 7)
+    for o in range(25):
+        P = b.ctrl[b.cp_offset[o] * 3:b.cp_offset[o + 1] * 3].reshape(3, 2, 2).astype(np.float64)
+        u, v = b.t[o].astype(np.float64), b.v[o].astype(np.float64)
+        want = ((1 - u) * (1 - v))[None] * P[:, 0, 0, None] + ((1 - u) * v)[None] * P[:, 0, 1, None] + \
+            (u * (1 - v))[None] * P[:, 1, 0, None] + (u * v)[None] * P[:, 1, 1, None]
+        np.testing.assert_allclose(out[:, o], want, rtol=0, atol=1e-15)
+
+
+def test_batch_without_patches_is_unchanged_by_the_second_parameters(orc):
+    """Curves and NURBS do not read v."""
+    b = bz_synth.mixed_batch(n_bezier=50, n_nurbs=8, n_t=4, seed=23)
+    ref = orc.batch_eval(b)
+    b.v = np.full_like(b.t, np.nan)
+    np.testing.assert_array_equal(orc.batch_eval(b), ref)
