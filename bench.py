@@ -150,10 +150,17 @@ def max_err_bbox(got, ref, ext, per_obj):
     return float((d.max(axis=0).reshape(-1, per_obj).max(axis=1) / ext).max())
 
 
+# a box side below this fraction of the object's largest |coordinate| cannot
+# be resolved to 1e-5 by FP32 results (two roundings, 2 * 2^-24, exceed it)
+FP32_RESOLVABLE = 2.0 ** -23 / 1e-5
+
+
 def extents(ctrl):
+    """Per-object error normaliser: the largest side of the control-point box,
+    floored at FP32_RESOLVABLE of the largest |coordinate|."""
     c = np.asarray(ctrl, np.float64)
     side = (c.max(axis=2) - c.min(axis=2)).max(axis=1)
-    return np.maximum(np.maximum(side, np.abs(c).max(axis=(1, 2))), 1e-30)
+    return np.maximum(np.maximum(side, FP32_RESOLVABLE * np.abs(c).max(axis=(1, 2))), 1e-30)
 
 
 def hbm_probe(torch, bz, mib=1024, iters=10):
@@ -866,8 +873,9 @@ def batched_patches_record(torch, bz, bz_synth, cpu, n_sample=8192):
 
 def _box(P):
     """Error normaliser of one object's control points P[dim][m]: the largest
-    side of their bounding box, floored by the largest |coordinate|."""
-    return max((P.max(axis=1) - P.min(axis=1)).max(), np.abs(P).max(), 1e-30)
+    side of their bounding box, floored at FP32_RESOLVABLE of the largest
+    |coordinate|."""
+    return max((P.max(axis=1) - P.min(axis=1)).max(), FP32_RESOLVABLE * np.abs(P).max(), 1e-30)
 
 
 def chain_record(torch, bz, bz_synth, cpu, n_seg=1 << 20, n_q=1 << 24):

@@ -407,16 +407,26 @@ int bz_plan_destroy(bz_plan plan);
  *     2 Seiler texture: ring = Seiler textures [n_seg][3][4]
  *       (bz_build_texture, BZ_TEX_SEILER) read through the emulated filter
  *       with 8-bit nearest weights at (t, st);
- *     3 sampled table: ring = [3][n_seg*samples] curve samples at segment
- *       j / samples, local (j mod samples)/samples (bz_eval_bezier with
- *       t_j = j/samples); x = T*samples, i = min(floor x, n_seg*samples-1),
- *       lerp of samples i and i+1 (wrapping to sample 0) with x - i;
+ *     3 sampled table: ring = [3][n_seg*samples] curve samples, entry
+ *       k*samples + j the point of segment k at t = j/samples
+ *       (bz_particle_ring_table); x = T*samples, i = min(floor x,
+ *       n_seg*samples-1), lerp of samples i and i+1 (wrapping to sample 0)
+ *       with x - i;
  *   then shade[p] = v_K of v_0 = 0, v_{i+1} = fma(23/32, v_i, x/4 - y/8 + z/16)
  *   (iters = K >= 0), a stand-in for the shader's other work.
  * ring 16-byte aligned; T is updated in place.
  */
 int bz_particles_step(int method, const float *ring, int64_t n_seg, int samples, float *T, const float *speed,
                       float dt, int64_t n_particles, int iters, float *pos, float *shade, bz_stream stream);
+
+/*
+ * The sampled table of the particle ring (method 3 above; the memory-lookup
+ * end of Sec. 5's comparison): ring control points [n_seg][3][4] (FP32) ->
+ * table[3][n_seg*samples], entry k*samples + j the point of segment k at
+ * t = j/samples (FP32 division), evaluated by de Casteljau.  n_seg 1..2^20,
+ * n_seg*samples at most 2^24.
+ */
+int bz_particle_ring_table(const float *ring, int64_t n_seg, int samples, float *table, bz_stream stream);
 
 /*
  * Adjoint of curve evaluation (the derivative of Sec. 2's curves): given

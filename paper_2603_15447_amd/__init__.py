@@ -72,6 +72,7 @@ _SIGS = {
     "bz_build_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _P]),
     "bz_eval_texture_patch": (_I, [_P, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _P, _P]),
     "bz_particles_step": (_I, [_I, _P, _I64, _I, _P, _P, _F, _I64, _I, _P, _P, _P]),
+    "bz_particle_ring_table": (_I, [_P, _I64, _I, _P, _P]),
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
@@ -363,8 +364,17 @@ def particle_ring_data(seg, method, samples=64):
         return bezier_to_seiler(seg)
     if method == "seiler_texture":
         return build_texture(seg, "seiler")
-    t = torch.arange(samples, device=seg.device, dtype=torch.float32) / samples
-    return eval_bezier(seg, t)  # [3][N*samples]
+    return particle_ring_table(seg, samples)
+
+
+def particle_ring_table(seg, samples=64, out=None):
+    """Sampled table [3, N*samples] of the ring seg[N, 3, 4] (FP32) at t = j/samples."""
+    _f32_only("seg", seg)
+    n = seg.shape[0]
+    assert tuple(seg.shape) == (n, 3, 4)
+    out = _f32_out((3, n * samples), seg.device, out)
+    check(lib().bz_particle_ring_table(_ptr(seg), n, samples, _ptr(out), _stream()))
+    return out
 
 
 def particles_step(method, ring, n_seg, T, speed, dt, iters, samples=64, pos=None, shade=None):

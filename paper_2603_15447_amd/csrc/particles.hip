@@ -9,8 +9,9 @@
 //   1 Seiler terms [N][3][4] (bz_bezier_to_seiler): three lerps;
 //   2 Seiler textures [N][3][4] (bz_build_texture, Seiler): the emulated
 //     8-bit filter read at (t, st);
-//   3 sampled table [3][N*S] (bz_eval_bezier at t = j/S): one lerp between
-//     neighbouring samples.
+//   3 sampled table [3][N*S] (bz_particle_ring_table: segment k at t = j/S,
+//     de Casteljau): one lerp between neighbouring samples.
+#include "curves_impl.h"
 #include "texfilter.h"
 
 namespace bzi {
@@ -96,10 +97,43 @@ __global__ __launch_bounds__(kBlock) void k_particles(ParticleArgs a) {
     st_stream(a.shade + p, v);
 }
 
+// Table of the ring for method 3: one thread per (segment, sample).
+__global__ __launch_bounds__(kBlock) void k_ring_table(const float *__restrict__ ring, uint32_t n_seg,
+                                                       uint32_t samples, float *__restrict__ table) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t n = n_seg * samples;
+    if (i >= n) return;
+    const uint32_t k = i / samples, j = i - k * samples;
+    const float t = static_cast<float>(j) / static_cast<float>(samples);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b[e] = ring[(static_cast<size_t>(k) * 3 + c) * 4 + e];
+        table[static_cast<size_t>(c) * n + i] = eval_dc<3>(b, t);
+    }
+}
+
 }  // namespace
 }  // namespace bzi
 
 using namespace bzi;
+
+extern "C" int bz_particle_ring_table(const float *ring, int64_t n_seg, int samples, float *table, bz_stream stream) {
+    return guarded("bz_particle_ring_table", [&]() -> int {
+        const char *fn = "bz_particle_ring_table";
+        if (n_seg < 1 || n_seg > (int64_t(1) << 20)) return fail(BZ_ERR_SHAPE, "%s: n_seg not in 1..2^20", fn);
+        if (samples < 1 || n_seg * samples > (int64_t(1) << 24))
+            return fail(BZ_ERR_SHAPE, "%s: samples (n_seg*samples at most 2^24)", fn);
+        if (!ring || !table) return fail(BZ_ERR_NULL, "%s: ring and table are required", fn);
+        if (!aligned(ring, 4) || !aligned(table, 4)) return fail(BZ_ERR_ALIGN, "%s: misaligned", fn);
+        const uint32_t n = static_cast<uint32_t>(n_seg * samples);
+        hipLaunchKernelGGL(bzi::k_ring_table, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, as_stream(stream), ring,
+                           static_cast<uint32_t>(n_seg), static_cast<uint32_t>(samples), table);
+        BZ_CHECK_LAUNCH("k_ring_table");
+        return BZ_OK;
+    });
+}
 
 extern "C" int bz_particles_step(int method, const float *ring, int64_t n_seg, int samples, float *T,
                                  const float *speed, float dt, int64_t n_particles, int iters, float *pos,

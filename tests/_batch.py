@@ -4,14 +4,15 @@ import numpy as np
 
 
 def _extents(b, ctrl=None):
-    """Per-object normaliser (largest bounding-box side, floored by the
-    largest |coordinate|, as for single curves)."""
+    """Per-object normaliser: the largest bounding-box side, floored at
+    FP32_RESOLVABLE of the largest |coordinate|, as for single curves."""
+    from tests._gpu import FP32_RESOLVABLE
     c = np.asarray(b.ctrl if ctrl is None else ctrl, np.float64)
     ext = np.empty(b.n_obj)
     for o in range(b.n_obj):
         a0, a1 = b.cp_offset[o], b.cp_offset[o + 1]
         P = c[a0 * b.dim:a1 * b.dim].reshape(b.dim, a1 - a0)
-        ext[o] = max((P.max(axis=1) - P.min(axis=1)).max(), np.abs(P).max(), 1e-30)
+        ext[o] = max((P.max(axis=1) - P.min(axis=1)).max(), FP32_RESOLVABLE * np.abs(P).max(), 1e-30)
     return ext
 
 

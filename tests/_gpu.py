@@ -19,16 +19,21 @@ def host(x):
     return x.detach().cpu().numpy().astype(np.float64)
 
 
+# Below this fraction of an object's largest |coordinate| a box side cannot
+# be resolved to TOL_F32 by FP32 results at all: two roundings of a result of
+# that size (2u, u = 2^-24) already exceed TOL_F32 of such a box.
+FP32_RESOLVABLE = 2.0 ** -23 / TOL_F32  # about 1.2%
+
+
 def extents(ctrl):
     """Per-object error normaliser of ctrl[n][dim][m]: the largest side of the
-    control-point bounding box, floored by the largest |coordinate| so that a
-    box that is tiny compared with its distance from the origin (where FP32
-    rounding of the result alone exceeds 1e-5 of the box) is measured on the
-    scale FP32 resolves."""
+    control-point bounding box, floored at FP32_RESOLVABLE of the object's
+    largest |coordinate| (only a box smaller than about 1.2% of its distance
+    from the origin reaches the floor)."""
     c = np.asarray(ctrl, dtype=np.float64)
     side = (c.max(axis=2) - c.min(axis=2)).max(axis=1)
     mag = np.abs(c).max(axis=(1, 2))
-    return np.maximum(np.maximum(side, mag), 1e-30)
+    return np.maximum(np.maximum(side, FP32_RESOLVABLE * mag), 1e-30)
 
 
 def bbox_err(got, ref, ext, per_obj):

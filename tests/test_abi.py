@@ -196,3 +196,12 @@ def test_half_precision_inputs_are_refused_where_only_fp32_is_read():
     with pytest.raises(bz.BzError) as e:
         bz.l2_fit_adjoint(c32, t32, g32.half())
     assert e.value.code == bz.ERR_DTYPE
+
+
+def test_particle_ring_table_errors(L):
+    f = L.bz_particle_ring_table
+    assert f(FAKE, 0, 64, FAKE, None) == bz.ERR_SHAPE
+    assert f(FAKE, 16, 0, FAKE, None) == bz.ERR_SHAPE
+    assert f(FAKE, 1 << 20, 64, FAKE, None) == bz.ERR_SHAPE  # more than 2^24 samples
+    assert f(None, 16, 64, FAKE, None) == bz.ERR_NULL
+    assert f(FAKE, 16, 64, ODD, None) == bz.ERR_ALIGN

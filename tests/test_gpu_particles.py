@@ -71,3 +71,19 @@ def test_errors():
         bz.check(bz.lib().bz_particles_step(3, ring.data_ptr(), 16, 0, T_d.data_ptr(), s_d.data_ptr(), 0.01, 10, 0,
                                             pos.data_ptr(), shade.data_ptr(), None))
     assert e.value.code == bz.ERR_SHAPE
+
+
+def test_ring_table_matches_curve_evaluation(orc):
+    """The table entry point holds segment k at t = j/samples: against the
+    oracle within 1e-5 of the ring's box, and within two FP32 ulps of the
+    curve evaluator at the same parameters."""
+    seg, _, _ = bz_synth.particle_ring(n_particles=16)
+    ext = float((seg.max(axis=(0, 2)) - seg.min(axis=(0, 2))).max())
+    for samples in (1, 7, 64):
+        sd = to_dev(seg)
+        got = host(bz.particle_ring_table(sd, samples))
+        t = (np.arange(samples, dtype=np.float32) / np.float32(samples)).astype(np.float32)
+        ref = orc.bezier_decasteljau(seg, t)
+        assert np.abs(got - ref).max() <= 1e-5 * ext
+        gpu = host(bz.eval_bezier(sd, to_dev(t)))
+        np.testing.assert_allclose(got, gpu, rtol=0, atol=2 * 2.0 ** -23 * np.abs(gpu).max())
