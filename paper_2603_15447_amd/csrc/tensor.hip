@@ -38,17 +38,18 @@ enum { MF_F32 = 0, MF_BF16 = 1, MF_F16 = 2, MF_F16X3 = 3 };
 // the block is written front to back, four consecutive lines per row at a
 // time.  The cubic basis at the 32 grid parameters comes from a 512-byte LDS
 // table filled once per workgroup.
-// Per grid row a wave issues the MFMA(s) of a 32 x 32 x 16 product and stores
-// the 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
+// Per grid row a wave issues the MFMA(s) of a 32 x 32 x 16 product (FP32: the
+// u contraction on the vector ALU, then a 32 x 32 x 4 product) and stores the
+// 32 x 32 result tile (each half-wave writes 128 contiguous bytes).
 // Output-tile layout of the 32x32 MFMAs: lane l holds column l%32 and, in
 // accumulator register r, row 8*(r/4) + 4*(l/32) + r%4.
 // Workgroups per (32 patches, coordinate): the grid rows are split over
-// kMfmaGridSplit<ENG> workgroups.  The one-MFMA engines (BF16, FP16) run
-// faster with short waves; FP32 (eight MFMAs per grid row) and FP16x3 (three,
-// plus the operand splits) draw enough power that more parallel work only
-// lowers the sustained clock, so they keep all 32 rows in one workgroup.
+// kMfmaGridSplit workgroups of short waves (measured faster for every engine
+// once the FP32 engine contracts u on the vector ALU; with the 16-term
+// Kronecker basis, eight FP32 MFMAs per grid row drew enough power that more
+// parallel work only lowered the sustained clock).
 template <int ENG>
-constexpr int kMfmaGridSplit = (ENG == MF_BF16 || ENG == MF_F16) ? 4 : 1;
+constexpr int kMfmaGridSplit = 4;
 
 template <int ENG>
 __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict__ ctrl, uint32_t n_patches, uint32_t dim,
@@ -141,10 +142,16 @@ __global__ __launch_bounds__(kBlock) void k_tensor_mfma(const float *__restrict_
         }
         v16f acc = {};
         if constexpr (ENG == MF_F32) {
+            // contract u on the vector ALU first: Q[p][j] = sum_i P[p][4i+j] Bu[a][i]
+            // (lane: row p = col, j = 2s + kh), then the K = 4 product with the
+            // v basis on the matrix cores -- two MFMAs per grid row, where the
+            // Kronecker basis of u and v would take eight
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int k = 2 * s + kh;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[k], Bu[k >> 2] * Bv[k & 3], acc, 0, 0, 0);
+            for (int s = 0; s < 2; ++s) {
+                const int j = 2 * s + kh;
+                const float qa = __builtin_fmaf(A[12 + j], Bu[3], __builtin_fmaf(A[8 + j], Bu[2],
+                                                __builtin_fmaf(A[4 + j], Bu[1], A[j] * Bu[0])));
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(qa, Bv[j], acc, 0, 0, 0);
             }
         } else if constexpr (ENG == MF_BF16) {
             v8bf Bb;
