@@ -229,3 +229,27 @@ def test_l2_fit_adjoint_matches_the_fused_step(orc):
     g = host(gc)
     c_ref = c0.astype(np.float32).astype(np.float64) - 1e-2 * g / (np.abs(g) + 1e-8)
     assert np.abs(host(s["ctrl"]) - c_ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_autograd_half_precision_control_points(orc, dtype):
+    """FP16/BF16 control points (and weights) with requires_grad: the forward
+    reads the half-precision storage, the backward widens it to FP32 for the
+    adjoint and returns gradients in the storage type, equal to the FP32
+    adjoint of the rounded inputs rounded once."""
+    rng = np.random.default_rng(3)
+    n, d, nt = 6, 3, 24
+    ctrl = rng.uniform(-1, 1, size=(n, 3, d + 1)).astype(np.float32)
+    w = rng.uniform(0.5, 2, size=(n, d + 1)).astype(np.float32)
+    t = rng.uniform(0.05, 0.95, size=(n, nt)).astype(np.float32)
+    G = rng.normal(size=(3, n * nt)).astype(np.float32)
+    c_d = to_dev(ctrl).to(dtype).requires_grad_(True)
+    w_d = to_dev(w).to(dtype).requires_grad_(True)
+    t_d = to_dev(t).requires_grad_(True)
+    (bz.bezier_curve(c_d, t_d, w_d) * to_dev(G)).sum().backward()
+    assert c_d.grad.dtype == dtype and w_d.grad.dtype == dtype and t_d.grad.dtype == torch.float32
+    rc, rw, rt = orc.bezier_adjoint(c_d.detach().float().cpu().numpy(), t, G, w=w_d.detach().float().cpu().numpy())
+    u = 2.0 ** -8 if dtype == torch.bfloat16 else 2.0 ** -11  # one rounding to the storage type
+    assert _rel(host(c_d.grad.float()), rc) <= u + 2e-5  # numpy has no bfloat16: widened (exactly) first
+    assert _rel(host(w_d.grad.float()), rw) <= u + 2e-5
+    assert _rel(host(t_d.grad), rt) <= 1e-4
