@@ -44,9 +44,10 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def chain_bytes(n_seg, dim, n_q):
-    """Algorithmic HBM bytes of one evaluation launch: the texels once, T in, points out."""
-    return (n_seg + 1) * 2 * dim * 4 + n_q * 4 + n_q * dim * 4
+def chain_bytes(n_seg, dim, n_q, es=4):
+    """Algorithmic HBM bytes of one evaluation launch: the texels once (es
+    bytes each), T in, points out (FP32)."""
+    return (n_seg + 1) * 2 * dim * es + n_q * 4 + n_q * dim * 4
 
 
 def particle_frame_bytes(n):
@@ -748,8 +749,15 @@ def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=2
     roof["kernel"] = "k_curves<%s>" % dom
     roof["bytes_per_launch"] = nbytes
     roof["traffic"] = recorded_traffic(PLAIN_COUNTERS, {"n_curves": n_curves, "n_t": n_t}, dom)
+    # what a launch of this size costs at best: a write-only kernel storing the
+    # same output bytes (one 16-byte vector per thread), timed the same way
+    wbuf = torch.empty(3 * n_q, device="cuda")
+    floor_ms = graph_time_ms(lambda: bz.hbm_probe("write", wbuf, wbuf, blocks_per_cu=0), torch, launches=50, replays=10)
+    del wbuf
+    floor = {"us": floor_ms * 1e3, "bytes": 12 * n_q, "of_dominant": floor_ms * 1e3 / forms[dom]["us"]}
     rec = {"value": 3 * n_q / (ms_per_step * 1e-3) / 1e9, "ms_per_step": ms_per_step,
-           "gpu_ms_per_step": gpu_ms_per_step, "eager_ms_per_step": eager_ms, "forms": forms, "roofline": roof}
+           "gpu_ms_per_step": gpu_ms_per_step, "eager_ms_per_step": eager_ms, "forms": forms, "roofline": roof,
+           "launch_floor": floor}
     # 16x the curves (65536 x 256 = 2^24 points per form): past the launch-bound regime
     c16 = torch.from_numpy(bz_synth.plain_curves(n_curves=16 * n_curves, n_t=n_t)[0]).cuda()
     o16 = torch.empty((3, 16 * n_q), device="cuda")
@@ -893,12 +901,20 @@ def chain_record(torch, bz, bz_synth, cpu, n_seg=1 << 20, n_q=1 << 24):
     if traffic:
         rec["traffic_over_algorithmic"] = traffic / nbytes
         rec["traffic_frac"] = traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the same tiles with FP16 texels (2.2x fewer bytes; error: the texel rounding)
+    tiles16 = bz.tile_piecewise16(grid, torch.float16)
+    out16 = torch.empty((3, n_q), device="cuda")
+    ms16 = timed(lambda: bz.eval_piecewise_tiled16(tiles16, n_seg, 3, T_d, out=out16), torch, iters=20)
+    nb16 = chain_bytes(n_seg, 3, n_q, es=2)
+    ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+    rec["fp16"] = {"us": ms16 * 1e3, "G/s": n_q / (ms16 * 1e-3) / 1e9, "frac": hbm_roof(nb16, ms16)["frac"],
+                   "max_diff_vs_fp32_bbox": float((out16 - out).abs().max().item()) / ext}
     if cpu:
         import oracle
         m = 1 << 20
         ref = oracle.chain_eval(chain, T[:m])
-        ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
         rec["max_err_bbox"] = float(np.abs(out[:, :m].cpu().numpy().astype(np.float64) - ref).max() / ext)
+        rec["fp16"]["max_err_bbox"] = float(np.abs(out16[:, :m].cpu().numpy().astype(np.float64) - ref).max() / ext)
     return rec
 
 
@@ -936,7 +952,7 @@ def compact_record(head, batched, chain, steps, warmup, n_curves, n_t, suite_fil
                    "n_curves": n_curves, "n_t": n_t, "dim": 3, "degree": 3},
         "roofline": head["roofline"],
     }
-    for k in ("cpu_baseline", "max_err_bbox", "forms", "x16", "gpu_ms_per_step", "eager_ms_per_step"):
+    for k in ("cpu_baseline", "max_err_bbox", "forms", "launch_floor", "x16", "gpu_ms_per_step", "eager_ms_per_step"):
         if k in head:
             rec[k] = head[k]
     if batched:

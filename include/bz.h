@@ -201,6 +201,30 @@ int bz_eval_piecewise_tiled(const float *tiles, int64_t n_seg, int dim, const fl
                             bz_stream stream);
 
 /*
+ * The same tiles with 16-bit texels (dtype BZ_F16 or BZ_BF16; a storage
+ * choice, not the paper's): 128-byte tiles of C = 32/dim columns (32, 16, 10,
+ * 8 for dim 1..4), tile j holding segments [j*(C-1), (j+1)*(C-1)), unused
+ * bytes zero, so the tiled chain takes about 2.2x fewer bytes and every query
+ * still reads one line.  bz_piecewise_tiled16_halfs: buffer size in 16-bit
+ * elements (0 for invalid arguments; host function).  bz_tile_piecewise16:
+ * grid (FP32, as bz_encode_piecewise writes it) -> tiles, each texel rounded
+ * to nearest even once (NaN stays NaN); tiles 128-byte aligned, device.
+ * bz_eval_piecewise_tiled16: as bz_eval_piecewise (same parameter decode, FP32
+ * arithmetic on the widened texels).  Error: the bilinear read weighs the four
+ * texels of a window by (1-t)^2, t(1-t), t(1-t), t^2 (sum 1), so a result
+ * differs from the FP32 tiles' by at most the largest texel rounding, 2^-11
+ * (F16) or 2^-8 (BF16) of the largest |texel| of its window, plus FP32
+ * rounding; the zig-zag's free texels drift like the chain's alternating sums
+ * (Eq. 2), so for long chains far from the origin this can be large against a
+ * segment's own size.  BZ_ERR_DTYPE for another dtype; otherwise the errors of
+ * the FP32 functions.
+ */
+int64_t bz_piecewise_tiled16_halfs(int64_t n_seg, int dim);
+int bz_tile_piecewise16(const float *grid, int64_t n_seg, int dim, int dtype, void *tiles, bz_stream stream);
+int bz_eval_piecewise_tiled16(const void *tiles, int dtype, int64_t n_seg, int dim, const float *T, int64_t n_q,
+                              float *out, bz_stream stream);
+
+/*
  * Texture-filter emulation (Sec. 2: texel values at texel centres, 2x2 and
  * 2x2x2 textures holding de Casteljau levels; Sec. 2.3: filter weights in
  * fixed point with 8 fractional bits; Sec. 4 with Table 1: Seiler textures;

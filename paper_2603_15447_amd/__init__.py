@@ -76,6 +76,9 @@ _SIGS = {
     "bz_piecewise_tiled_floats": (_I64, [_I64, _I]),
     "bz_tile_piecewise": (_I, [_P, _I64, _I, _P, _P]),
     "bz_eval_piecewise_tiled": (_I, [_P, _I64, _I, _P, _I64, _P, _P]),
+    "bz_piecewise_tiled16_halfs": (_I64, [_I64, _I]),
+    "bz_tile_piecewise16": (_I, [_P, _I64, _I, _I, _P, _P]),
+    "bz_eval_piecewise_tiled16": (_I, [_P, _I, _I64, _I, _P, _I64, _P, _P]),
     "bz_eval_tensor_patch": (_I, [_P, _I, _I64, _I, _I, _I, _I, _P, _I64, _I, _I, _I, _P, _P]),
     "bz_batch_plan_create": (_I, [_I64, _P, _P, _P, _P, _I, _I, _P, _P, _I64, _I, _P, ctypes.POINTER(_P)]),
     "bz_batch_eval": (_I, [_P, _P, _P, _P]),
@@ -404,6 +407,28 @@ def eval_piecewise_tiled(tiles, n_seg, dim, T, out=None):
     nq = T.shape[0]
     out = _f32_out((dim, nq), tiles.device, out)
     check(lib().bz_eval_piecewise_tiled(_ptr(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
+    return out
+
+
+def tile_piecewise16(grid, dtype=torch.float16, out=None):
+    """Zig-zag grid[N+1, 2, dim] (float32) -> cache-line tiles with 16-bit
+    texels (dtype float16 or bfloat16; flat, 128-byte aligned)."""
+    _f32_only("grid", grid)
+    nseg = grid.shape[0] - 1
+    dim = grid.shape[2]
+    n = lib().bz_piecewise_tiled16_halfs(nseg, dim)
+    if out is None:
+        out = torch.empty(n, dtype=dtype, device=grid.device)
+    assert out.numel() == n and out.data_ptr() % 128 == 0
+    check(lib().bz_tile_piecewise16(_ptr(grid), nseg, dim, _dtype(out), _ptr(out), _stream()))
+    return out
+
+
+def eval_piecewise_tiled16(tiles, n_seg, dim, T, out=None):
+    _f32_only("T", T)
+    nq = T.shape[0]
+    out = _f32_out((dim, nq), tiles.device, out)
+    check(lib().bz_eval_piecewise_tiled16(_ptr(tiles), _dtype(tiles), n_seg, dim, _ptr(T), nq, _ptr(out), _stream()))
     return out
 
 

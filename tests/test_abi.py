@@ -101,6 +101,27 @@ def test_cubic_chain_errors(L):
     assert L.bz_piecewise_tiled_floats(1 << 20, 3) == (1 << 18) * 32  # 4 segments per tile
 
 
+def test_tiled16_chain_errors(L):
+    S3 = 32 // 3 - 1  # 9 segments per 128-byte tile of 16-bit texels in 3D
+    assert L.bz_piecewise_tiled16_halfs(1 << 20, 3) == -(-(1 << 20) // S3) * 64
+    assert L.bz_piecewise_tiled16_halfs(9, 3) == 64 and L.bz_piecewise_tiled16_halfs(10, 3) == 128
+    assert L.bz_piecewise_tiled16_halfs(31, 1) == 64 and L.bz_piecewise_tiled16_halfs(7, 4) == 64
+    assert L.bz_piecewise_tiled16_halfs(0, 3) == 0 and L.bz_piecewise_tiled16_halfs(10, 5) == 0
+    assert L.bz_tile_piecewise16(FAKE, 4, 3, bz.F32, FAKE, None) == bz.ERR_DTYPE
+    assert L.bz_tile_piecewise16(FAKE, 4, 3, 7, FAKE, None) == bz.ERR_DTYPE
+    assert L.bz_tile_piecewise16(FAKE, 4, 5, bz.F16, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_tile_piecewise16(FAKE, 4, 3, bz.F16, FAKE + 64, None) == bz.ERR_ALIGN
+    assert L.bz_tile_piecewise16(None, 4, 3, bz.BF16, FAKE, None) == bz.ERR_NULL
+    assert L.bz_tile_piecewise16(None, 0, 3, bz.F16, None, None) == bz.OK
+    assert L.bz_eval_piecewise_tiled16(FAKE, bz.F32, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_DTYPE
+    assert L.bz_eval_piecewise_tiled16(FAKE, bz.F16, 4, 0, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_tiled16(FAKE, bz.F16, 0, 3, FAKE, 10, FAKE, None) == bz.ERR_SHAPE
+    assert L.bz_eval_piecewise_tiled16(FAKE + 64, bz.BF16, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_tiled16(FAKE, bz.F16, 4, 3, FAKE + 2, 10, FAKE, None) == bz.ERR_ALIGN
+    assert L.bz_eval_piecewise_tiled16(None, bz.F16, 4, 3, FAKE, 10, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_piecewise_tiled16(FAKE, bz.F16, 4, 3, FAKE, 0, FAKE, None) == bz.OK
+
+
 def test_texture_errors(L):
     assert [L.bz_texture_texels(d, 0) for d in (1, 2, 3, 8, 9)] == [0, 4, 8, 28, 0]
     assert [L.bz_texture_texels(d, 2) for d in (1, 2, 3, 4, 7, 8)] == [0, 4, 4, 8, 8, 0]

@@ -25,6 +25,7 @@ def test_chain_bytes():
     # grid (n_seg+1) x 2 x dim floats, T in, dim floats out per query
     assert bench.chain_bytes(1 << 20, 3, 1 << 24) == ((1 << 20) + 1) * 24 + (1 << 24) * 16
     assert bench.chain_bytes(1, 1, 0) == 16
+    assert bench.chain_bytes(1 << 20, 3, 1 << 24, es=2) == ((1 << 20) + 1) * 12 + (1 << 24) * 16
 
 
 def test_particle_frame_bytes():
@@ -90,6 +91,7 @@ def _synthetic_records():
     forms = {m: {"us": r(), "G/s": r(), "frac": r()} for m in bench.FORMS}
     head = {"value": r(), "ms_per_step": r(), "gpu_ms_per_step": r(), "eager_ms_per_step": r(), "forms": forms,
             "x16": {m: {"G/s": r(), "frac": r()} for m in bench.FORMS},
+            "launch_floor": {"us": r(), "bytes": 12582912, "of_dominant": r()},
             "roofline": {"bound": "hbm", "achieved": r(), "peak": 8000.0, "unit": "GB/s", "frac": r(),
                          "traffic": r(), "kernel": "k_curves<seiler>", "bytes_per_launch": 12780544},
             "max_err_bbox": {m: r() for m in bench.FORMS},
@@ -103,7 +105,8 @@ def _synthetic_records():
                                "sample": "16384 random objects x 16 t, FP64"}
     batched["fp16_speedup"] = r()
     chain = {"us": r(), "G/s": r(), "frac": r(), "traffic_over_algorithmic": r(), "traffic_frac": r(),
-             "max_err_bbox": r()}
+             "max_err_bbox": r(), "fp16": {"us": r(), "G/s": r(), "frac": r(), "max_diff_vs_fp32_bbox": r(),
+                                          "max_err_bbox": r()}}
     suite = {w: {"value": r(), "roofline": {"frac": r()}, **{k: {"value": r(), "roofline": {"frac": r()}}
                                                             for k in ("a", "bb", "ccc", "dddd")}}
              for w in ("plain", "cubic_chain", "texemu", "batched", "patches", "volumes", "fit", "particles")}
@@ -123,6 +126,7 @@ def test_final_record_is_compact_and_complete():
         assert set(rec["roofline"]) >= {"bound", "achieved", "peak", "unit", "frac", "traffic"}
         assert "plain" in rec["config"]["workload"] and "graph" in rec["config"]["timing"]
         assert {"fp32", "fp16"} <= set(rec["batched"])
+        assert set(rec["launch_floor"]) == {"us", "bytes", "of_dominant"}
         if summary is None:  # the contract's part alone fits well inside the limit
             assert len(line) <= bench.RECORD_MAX_BYTES, len(line)
 

@@ -122,6 +122,82 @@ def test_tiled_full_chain_config(orc):
     assert np.abs(got - ref).max() / _chain_extent(chain) <= TOL_F32
 
 
+# ---------------------------------------------------------------- 16-bit texels
+UNIT16 = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}  # unit roundoff of round-to-nearest-even
+
+
+def _round16(x, dtype):
+    """FP32 values rounded to FP16 / BF16 (nearest even), as FP64; and the bits."""
+    x = np.asarray(x, np.float32)
+    if dtype == "f16":
+        h = x.astype(np.float16)
+        return h.astype(np.float64), h.view(np.uint16)
+    u = x.view(np.uint32).astype(np.uint64)
+    b = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64), b
+
+
+def _tiles16_reference(grid, dtype):
+    """Expected 16-bit tile bits: columns j*S .. j*S+S of the grid, S = 32/dim - 1."""
+    n_seg, _, dim = grid.shape[0] - 1, 2, grid.shape[2]
+    S = 32 // dim - 1
+    n_tiles = -(-n_seg // S)
+    bits = _round16(grid, dtype)[1]
+    tiles = np.zeros((n_tiles, 64), np.uint16)
+    for j in range(n_tiles):
+        cols = bits[j * S: min(j * S + S + 1, n_seg + 1)]
+        tiles[j, :cols.size] = cols.reshape(-1)
+    return tiles.reshape(-1)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("n_seg,dim", [(1, 3), (9, 3), (10, 3), (1000, 3), (77, 1), (300, 2), (129, 4)])
+def test_tiled16_layout_and_eval(orc, dtype, n_seg, dim):
+    """16-bit texel tiles: layout bit-exact; results against the oracle's
+    chain evaluation on its own grid rounded to the texel type (they differ
+    only where the FP64 texel sits on an FP32 rounding tie, by at most one
+    16-bit unit of a free texel, whose weight is at most 1/4), and the
+    stated bound against the exact chain: u times the largest |texel|."""
+    import torch
+    chain, T = bz_synth.chain_walk(n_seg=n_seg, dim=dim, n_q=3001, seed=11 * n_seg + dim)
+    grid = bz.encode_piecewise(to_dev(chain))
+    tiles = bz.tile_piecewise16(grid, torch.float16 if dtype == "f16" else torch.bfloat16)
+    torch.cuda.synchronize()
+    bits = tiles.view(torch.int16).cpu().numpy().view(np.uint16)  # the raw texel bits
+    np.testing.assert_array_equal(bits, _tiles16_reference(host(grid), dtype))
+    T = np.concatenate([T, np.array([0, n_seg, -1, n_seg + 3, np.nan], np.float32),
+                        np.arange(n_seg + 1, dtype=np.float32)])
+    got = host(bz.eval_piecewise_tiled16(tiles, n_seg, dim, to_dev(T)))
+    ok = ~np.isnan(T)
+    rg = _round16(orc.piecewise_encode(chain).astype(np.float32), dtype)[0]
+    u, xmax, ext = UNIT16[dtype], float(np.abs(rg).max()), _chain_extent(chain)
+    ref_r = orc.piecewise_eval(rg, T[ok])
+    assert np.abs(got[:, ok] - ref_r).max() <= 0.5 * u * xmax + TOL_F32 * ext
+    ref = orc.chain_eval(chain, T[ok])
+    assert np.abs(got[:, ok] - ref).max() <= u * xmax + TOL_F32 * ext
+    assert np.isnan(got[:, ~ok]).all()
+
+
+def test_tiled16_full_chain_config(orc):
+    """The bench's chain (2^20 segments, 2^24 random T) with FP16 texels:
+    every query against the FP32 tiles (the difference is the texel
+    rounding alone, within u times the largest |texel| of the chain), and a
+    seeded sample of 2^18 queries against the oracle's chain."""
+    import torch
+    chain, T = bz_synth.chain_walk()
+    n_seg = (chain.shape[0] - 1) // 2
+    grid = bz.encode_piecewise(to_dev(chain))
+    T_d = to_dev(T)
+    got = bz.eval_piecewise_tiled16(bz.tile_piecewise16(grid, torch.float16), n_seg, 3, T_d)
+    f32 = bz.eval_piecewise_tiled(bz.tile_piecewise(grid), n_seg, 3, T_d)
+    xmax = float(grid.abs().max().item())
+    assert float((got - f32).abs().max().item()) <= UNIT16["f16"] * xmax + 1e-6 * xmax
+    pick = np.random.default_rng(5).choice(T.size, 1 << 18, replace=False)
+    ref = orc.chain_eval(chain, T[pick])
+    g = host(got)[:, pick]
+    assert np.abs(g - ref).max() <= UNIT16["f16"] * xmax + TOL_F32 * _chain_extent(chain)
+
+
 def test_chains_across_launch_chunks(orc):
     """2^30 + 777 queries in 2D: the chain evaluators launch at most 2^30
     queries at a time, so the last 777 come in a second launch that reads T
