@@ -1102,6 +1102,20 @@ def suite_chain(torch, bz, bz_synth, args):
     rec["hbm_probe"] = probe
     if args.layout == "tiled":
         rec["gather_ceiling"] = gather_ceiling(torch, bz, tiles, args.n_q, kern_ms)
+        # the same tiles with FP16 texels: 2.25x fewer bytes, one line per query
+        tiles16 = bz.tile_piecewise16(grid, torch.float16)
+        out16 = torch.empty_like(out)
+        ms16 = timed(lambda: bz.eval_piecewise_tiled16(tiles16, args.n_seg, dim, T_d, out=out16), torch, iters=200,
+                     warmup=20)
+        nb16 = chain_bytes(args.n_seg, dim, args.n_q, es=2)
+        bz.eval_piecewise_tiled(tiles, args.n_seg, dim, T_d, out=out)
+        ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
+        ceiling16 = gather_ceiling(torch, bz, tiles16.view(torch.float32), args.n_q, ms16, vec16=2)
+        rec["fp16_texels"] = {"kernel_ms": ms16, "value": args.n_q / (ms16 * 1e-3) / 1e9,
+                              "roofline": hbm_roof(nb16, ms16), "algorithmic_bytes": nb16,
+                              "tiles_MB": tiles16.numel() * 2 / 1e6, "gather_ceiling": ceiling16,
+                              "max_diff_vs_fp32_bbox": float((out16 - out).abs().max().item()) / ext}
+        del tiles16, out16
     if roof["traffic"]:
         rate = roof["traffic"] / (kern_ms * 1e-3) / 1e9
         rec["actual_traffic"] = {"bytes_per_launch": roof["traffic"], "over_algorithmic": roof["traffic"] / nbytes,
