@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "G curve-point evals/s and % HBM roofline, plain FP32 vs batched/FP16 at max err"
-COUNTER_FILES = {"grid": "chain_eval_counters.json", "tiled": "chain_eval_tiled_counters.json"}
+CHAIN_COUNTERS = "chain_eval_counters.json"  # keys: grid, tiled, tiled16
 
 
 def log(msg):
@@ -897,7 +897,7 @@ def chain_record(torch, bz, bz_synth, cpu, n_seg=1 << 20, n_q=1 << 24):
     ms = timed(lambda: bz.eval_piecewise_tiled(tiles, n_seg, 3, T_d, out=out), torch, iters=20)
     nbytes = chain_bytes(n_seg, 3, n_q)
     rec = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"]}
-    traffic = recorded_traffic(COUNTER_FILES["tiled"], {"n_seg": n_seg, "n_q": n_q})
+    traffic = recorded_traffic(CHAIN_COUNTERS, {"n_seg": n_seg, "n_q": n_q}, "tiled")
     if traffic:
         rec["traffic_over_algorithmic"] = traffic / nbytes
         rec["traffic_frac"] = traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -909,6 +909,9 @@ def chain_record(torch, bz, bz_synth, cpu, n_seg=1 << 20, n_q=1 << 24):
     ext = float((chain.max(axis=0) - chain.min(axis=0)).max())
     rec["fp16"] = {"us": ms16 * 1e3, "G/s": n_q / (ms16 * 1e-3) / 1e9, "frac": hbm_roof(nb16, ms16)["frac"],
                    "max_diff_vs_fp32_bbox": float((out16 - out).abs().max().item()) / ext}
+    traffic16 = recorded_traffic(CHAIN_COUNTERS, {"n_seg": n_seg, "n_q": n_q}, "tiled16")
+    if traffic16:
+        rec["fp16"]["traffic_over_algorithmic"] = traffic16 / nb16
     if cpu:
         import oracle
         m = 1 << 20
@@ -1090,7 +1093,7 @@ def suite_chain(torch, bz, bz_synth, args):
     kern_ms = timed(steps[args.layout], torch, iters=200, warmup=20)
     nbytes = chain_bytes(args.n_seg, dim, args.n_q)
     roof = hbm_roof(nbytes, kern_ms)
-    roof["traffic"] = recorded_traffic(COUNTER_FILES[args.layout], {"n_seg": args.n_seg, "n_q": args.n_q})
+    roof["traffic"] = recorded_traffic(CHAIN_COUNTERS, {"n_seg": args.n_seg, "n_q": args.n_q}, args.layout)
     rec = {"workload": "C0 piecewise quadratic chain, zig-zag encoded (E=(B+C)/2), %d segments, %d uniform random "
                        "global T, 3D, FP32" % (args.n_seg, args.n_q),
            "layout": args.layout, "kernel_ms": kern_ms, "value": args.n_q / (kern_ms * 1e-3) / 1e9,

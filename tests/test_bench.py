@@ -60,11 +60,12 @@ def test_plain_bytes():
 
 def test_recorded_traffic_is_bound_to_its_workload():
     wl = {"n_seg": 1 << 20, "n_q": 1 << 24}
-    t = bench.recorded_traffic("chain_eval_tiled_counters.json", wl)
-    with open(os.path.join(ROOT, "profiles", "chain_eval_tiled_counters.json")) as f:
+    with open(os.path.join(ROOT, "profiles", bench.CHAIN_COUNTERS)) as f:
         d = json.load(f)
-    assert t in (None, d["traffic_bytes_per_dispatch"])  # None once the kernel source has changed
-    assert bench.recorded_traffic("chain_eval_tiled_counters.json", {"n_seg": 1 << 12, "n_q": 1 << 16}) is None
+    for layout in ("grid", "tiled", "tiled16"):
+        t = bench.recorded_traffic(bench.CHAIN_COUNTERS, wl, layout)
+        assert t in (None, d["traffic_bytes_per_dispatch"][layout])  # None once a kernel source has changed
+        assert bench.recorded_traffic(bench.CHAIN_COUNTERS, {"n_seg": 1 << 12, "n_q": 1 << 16}, layout) is None
     assert bench.recorded_traffic("no_such_file.json", wl) is None
 
 
