@@ -21,6 +21,12 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in p.stderr and p.stdout == ""
 
 
+def test_alu_roof_reports_both_peaks():
+    r = bench.alu_roof(39.3216)
+    assert r["bound"] == "alu" and abs(r["peak"] - 78.6432) < 1e-9 and abs(r["frac"] - 0.5) < 1e-12
+    assert r["published_peak"] == 157.3 and abs(r["frac_of_published"] - 39.3216 / 157.3) < 1e-12
+
+
 def test_chain_bytes():
     # grid (n_seg+1) x 2 x dim floats, T in, dim floats out per query
     assert bench.chain_bytes(1 << 20, 3, 1 << 24) == ((1 << 20) + 1) * 24 + (1 << 24) * 16
