@@ -140,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_nurbs_extract(int n_nurbs, const int
 // bucket m then lies in segments tab[m].s .. tab[m+1].s, because the bucket
 // function is monotone.  Returns false if an entry is out of range (which the
 // construction excludes; checked before anything reaches the device).
+// with_table false: the headers alone (16-bit plans search the breakpoints).
 bool build_nurbs_tables(const std::vector<int32_t> &seg_first, const std::vector<float> &brk,
-                        std::vector<NurbsHead> &head, std::vector<NurbsTab> &tab) {
+                        std::vector<NurbsHead> &head, std::vector<NurbsTab> &tab, bool with_table) {
     const size_t n = seg_first.size() - 1;
     head.resize(n);
     tab.clear();
@@ -159,6 +160,10 @@ bool build_nurbs_tables(const std::vector<int32_t> &seg_first, const std::vector
         const int M = 2 * h.nseg;
         h.inv_h = static_cast<float>(M) / (h.hi - h.lo);
         if (!std::isfinite(h.inv_h)) h.inv_h = 0.0f;  // one bucket holds every segment
+        if (!with_table) {
+            head[r] = h;
+            continue;
+        }
         bk.resize(h.nseg + 1);
         for (int i = 0; i <= h.nseg; ++i) bk[i] = nurbs_bucket(b[i], h.lo, h.inv_h, M);
         int i = 0;
@@ -526,9 +531,11 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         if (!rc) {
             std::vector<NurbsHead> nh;
             std::vector<NurbsTab> nt;
-            if (!build_nurbs_tables(seg_first, brk, nh, nt)) rc = fail(BZ_ERR_INTERNAL, "%s: NURBS span table", fn);
+            // the span table serves FP32 plans only (see NurbsHead)
+            if (!build_nurbs_tables(seg_first, brk, nh, nt, dtype == BZ_F32))
+                rc = fail(BZ_ERR_INTERNAL, "%s: NURBS span table", fn);
             if (!rc) rc = dev_upload(&p->nhead, nh, s);
-            if (!rc) rc = dev_upload(&p->ntab, nt, s);
+            if (!rc && !nt.empty()) rc = dev_upload(&p->ntab, nt, s);
         }
         if (!rc) rc = build_tiles(p, 4, n_t % 4 == 0 ? 4 : 1, kDefaultWindow, s);
         if (!rc) rc = dmalloc(&p->ctrl_s, ctrl_elems * es);

@@ -28,12 +28,19 @@ struct Tile {
     uint32_t pad;
 };
 
-// Span lookup of a NURBS query.  The parameter range [lo, hi] of NURBS r is cut
-// into M = 2*nseg equal buckets; a parameter of bucket m lies in one of the
-// segments tab[m].s .. tab[m+1].s (indices relative to the NURBS), and when
-// those are two segments, tab[m].split (the breakpoint between them) decides.
-// More than two candidates (two or more breakpoints in one bucket) fall back
-// to a binary search over the breakpoints of that range.
+// Span lookup of a NURBS query, two ways (the persistent kernel takes the
+// faster for its storage type, measured on a mixed batch in steady state):
+// - bucket table (FP32 storage): the parameter range [lo, hi] of NURBS r is
+//   cut into M = 2*nseg equal buckets; a parameter of bucket m lies in one of
+//   the segments tab[m].s .. tab[m+1].s (indices relative to the NURBS), and
+//   when those are two segments, tab[m].split (the breakpoint between them)
+//   decides.  More than two candidates (two or more breakpoints in one
+//   bucket) fall back to a binary search over the breakpoints of that range.
+// - binary search over the NURBS's nseg+1 breakpoints (16-bit storage): a line
+//   or two that the 16 queries of a NURBS share, where the table costs one
+//   more random line per query.  With FP32 control rows streaming past, the
+//   search's dependent probes miss the cache and the table is faster; with
+//   16-bit rows they hit, and the search is.
 struct NurbsHead {
     int32_t s0;    // first segment of the NURBS in the plan's segment array
     int32_t nseg;  // segments (non-empty knot spans)
@@ -76,7 +83,7 @@ struct BatchArgs {
     uint32_t n_tiles;          // tiles of the persistent launch
     uint32_t n_signed;         // tiles of signed-weight rationals, after those (a launch of their own)
     const NurbsHead *nhead;    // [n_nurbs], NURBS ranked in sorted order
-    const NurbsTab *ntab;      // span lookup tables, 2*nseg+1 entries per NURBS
+    const NurbsTab *ntab;      // span lookup tables, 2*nseg+1 entries per NURBS (FP32 storage only)
     const float *brk;          // breakpoints, nseg+1 per NURBS, from NurbsHead::brk0
     const float *seg;          // [n_segs][4][dim+1] homogeneous
     const float *t;
@@ -412,7 +419,7 @@ __device__ __forceinline__ void run_curve_tile4(const BatchArgs &a, const Tile &
 typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
-template <int DIM>
+template <int DIM, bool SEARCH>
 __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     constexpr int H = DIM + 1;  // homogeneous coordinates; a segment is 4*H floats = H vectors
     const uint32_t nq = static_cast<uint32_t>(tl.ci.count) * a.n_t;
@@ -436,33 +443,71 @@ __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &t
     }
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) q[s] = static_cast<int64_t>(a.perm[tl.ci.first + slot[s]]) * a.n_t + j[s];
+    // the search's first probe depends only on the header: loaded beside t, it
+    // brings the breakpoints' line in while the parameter is on its way
     float u[kMaxQpt];
+    [[maybe_unused]] float first[kMaxQpt];
+    if constexpr (SEARCH) {
+#pragma unroll
+        for (int s = 0; s < kMaxQpt; ++s) first[s] = a.brk[h[s].brk0 + (h[s].nseg >> 1)];
+    }
 #pragma unroll
     for (int s = 0; s < kMaxQpt; ++s) {
         const float v = a.t[q[s]];
         float c = v < h[s].lo ? h[s].lo : v;  // NaN passes
         u[s] = c > h[s].hi ? h[s].hi : c;
     }
-    i4u e[kMaxQpt];  // table entries m and m+1: {s, split bits, s, split bits}
-#pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        const int m = nurbs_bucket(u[s], h[s].lo, h[s].inv_h, 2 * h[s].nseg);
-        e[s] = *reinterpret_cast<const i4u *>(a.ntab + h[s].tab0 + m);
-    }
     int32_t sg[kMaxQpt];
+    if constexpr (SEARCH) {
+        // the last breakpoint <= u among the first nseg, by a binary search on
+        // [sg, sg + cnt) stepped for all of a lane's queries together (u is
+        // clamped to [lo, hi]; a NaN u stays in segment 0 and gives NaN)
+        int32_t cnt[kMaxQpt];
 #pragma unroll
-    for (int s = 0; s < kMaxQpt; ++s) {
-        int lo = e[s][0], hi = e[s][2];
-        if (hi - lo <= 1) {
-            sg[s] = (hi > lo && __int_as_float(e[s][1]) <= u[s]) ? hi : lo;
-        } else {  // two or more breakpoints inside the bucket
-            const float *b = a.brk + h[s].brk0;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (b[mid] <= u[s]) lo = mid;
-                else hi = mid - 1;
+        for (int s = 0; s < kMaxQpt; ++s) {
+            const int n = h[s].nseg, half = n >> 1;
+            const bool up = n > 1 && first[s] <= u[s];
+            sg[s] = up ? half : 0;
+            cnt[s] = n > 1 ? (up ? n - half : half) : n;
+        }
+        bool more = true;
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int s = 0; s < kMaxQpt; ++s) {
+                if (cnt[s] > 1) {
+                    const int half = cnt[s] >> 1;
+                    if (a.brk[h[s].brk0 + sg[s] + half] <= u[s]) {
+                        sg[s] += half;
+                        cnt[s] -= half;
+                    } else {
+                        cnt[s] = half;
+                    }
+                    more = more || cnt[s] > 1;
+                }
             }
-            sg[s] = lo;
+        }
+    } else {
+        i4u e[kMaxQpt];  // table entries m and m+1: {s, split bits, s, split bits}
+#pragma unroll
+        for (int s = 0; s < kMaxQpt; ++s) {
+            const int m = nurbs_bucket(u[s], h[s].lo, h[s].inv_h, 2 * h[s].nseg);
+            e[s] = *reinterpret_cast<const i4u *>(a.ntab + h[s].tab0 + m);
+        }
+#pragma unroll
+        for (int s = 0; s < kMaxQpt; ++s) {
+            int lo = e[s][0], hi = e[s][2];
+            if (hi - lo <= 1) {
+                sg[s] = (hi > lo && __int_as_float(e[s][1]) <= u[s]) ? hi : lo;
+            } else {  // two or more breakpoints inside the bucket
+                const float *b = a.brk + h[s].brk0;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (b[mid] <= u[s]) lo = mid;
+                    else hi = mid - 1;
+                }
+                sg[s] = lo;
+            }
         }
     }
     f2u br[kMaxQpt];
@@ -494,12 +539,13 @@ __device__ __forceinline__ void run_nurbs_tile(const BatchArgs &a, const Tile &t
     }
 }
 
+template <bool SEARCH>
 __device__ __forceinline__ void run_nurbs_tile_dim(const BatchArgs &a, const Tile &tl, float *__restrict__ out) {
     switch (a.dim) {
-        case 1: run_nurbs_tile<1>(a, tl, out); break;
-        case 2: run_nurbs_tile<2>(a, tl, out); break;
-        case 3: run_nurbs_tile<3>(a, tl, out); break;
-        default: run_nurbs_tile<4>(a, tl, out); break;
+        case 1: run_nurbs_tile<1, SEARCH>(a, tl, out); break;
+        case 2: run_nurbs_tile<2, SEARCH>(a, tl, out); break;
+        case 3: run_nurbs_tile<3, SEARCH>(a, tl, out); break;
+        default: run_nurbs_tile<4, SEARCH>(a, tl, out); break;
     }
 }
 
@@ -655,7 +701,7 @@ __device__ __forceinline__ void run_tile(const BatchArgs &a, unsigned int tile, 
     if (tl.ci.kind == 0) dispatch_degree<false, F, T, VQ>(a, tl, out);
     else if (tl.ci.kind == 1) dispatch_degree<true, F, T, VQ>(a, tl, out);
     else if (tl.ci.kind == 4) dispatch_patch<F, T, VQ>(a, tl, out);
-    else run_nurbs_tile_dim(a, tl, out);
+    else run_nurbs_tile_dim<!std::is_same<T, float>::value>(a, tl, out);
 }
 
 // Dynamic schedule: workgroups pull tiles from an atomic counter (the next

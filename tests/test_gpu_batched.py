@@ -92,10 +92,13 @@ def test_nurbs_clamp_and_ends(orc):
     np.testing.assert_allclose(got, ref, atol=2e-6)
 
 
-def test_nurbs_clustered_knots(orc):
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
+def test_nurbs_clustered_knots(orc, dtype):
     """Interior knots packed into a narrow cluster put many breakpoints in one
-    bucket of the span lookup (the binary-search fallback); parameters at, just
-    beside and between the clustered breakpoints, and at random."""
+    bucket of the span lookup (FP32 storage: the bucket table's binary-search
+    fallback; 16-bit storage: the search over all breakpoints); parameters at,
+    just beside and between the clustered breakpoints, and at random.  16-bit
+    plans against the oracle on their rounded control points and weights."""
     b = bz_synth.mixed_batch(n_bezier=0, n_nurbs=240, n_t=16, seed=12)
     rng = np.random.default_rng(13)
     for o in range(b.n_obj):
@@ -118,9 +121,12 @@ def test_nurbs_clustered_knots(orc):
         t[8:12] = np.nextafter(t[8:12], np.float32(1))
         t[12:] = rng.uniform(0.0, 1.0, 4)
         b.t[o] = t
-    plan, _ = _plan(b)
+    plan, dev = _plan(b, dtype=dtype)
     got = host(plan(to_dev(b.t)))
-    assert _err(got, orc.batch_eval(b), _extents(b), 16) <= TOL_F32
+    rb = bz_synth.Batch(**{**b.__dict__})
+    rb.ctrl = dev["ctrl"].float().cpu().numpy()
+    rb.w = dev["w"].float().cpu().numpy()
+    assert _err(got, orc.batch_eval(rb), _extents(rb), 16) <= TOL_F32
 
 
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
