@@ -82,8 +82,9 @@ def recorded_traffic(name, workload, key=None):
 
 
 def alu_roof(tflops):
-    """FP32 VALU roofline of a rate: against the non-packed peak this build can
-    reach, and against the published (packed) peak beside it."""
+    """FP32 VALU roofline of a rate: against the non-packed peak that the
+    library, compiled without packed-FP32 instructions, can reach, and against
+    the published (packed) peak beside it."""
     return {"bound": "alu", "achieved": tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": tflops / FP32_VALU_PEAK_TFLOPS, "published_peak": FP32_PUBLISHED_TFLOPS,
             "frac_of_published": tflops / FP32_PUBLISHED_TFLOPS}
