@@ -766,16 +766,19 @@ def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=2
     rec = {"value": 3 * n_q / (ms_per_step * 1e-3) / 1e9, "ms_per_step": ms_per_step,
            "gpu_ms_per_step": gpu_ms_per_step, "eager_ms_per_step": eager_ms, "forms": forms, "roofline": roof,
            "launch_floor": floor}
-    # 16x the curves (65536 x 256 = 2^24 points per form): past the launch-bound regime
-    c16 = torch.from_numpy(bz_synth.plain_curves(n_curves=16 * n_curves, n_t=n_t)[0]).cuda()
+    # 16x the curves with random t per curve (65536 x 256 = 2^24 points per
+    # form, 4 bytes in and 12 out per point): past the launch-bound regime
+    c16h, t16h = bz_synth.random_curves(16 * n_curves, 3, 3, n_t, seed=1001 + 16)
+    c16, t16 = torch.from_numpy(c16h).cuda(), torch.from_numpy(t16h).cuda()
     o16 = torch.empty((3, 16 * n_q), device="cuda")
-    n16 = plain_bytes(16 * n_curves, 3, 3, n_t)
-    x16 = {}
+    n16 = o16.numel() * 4 + c16.numel() * 4 + t16.numel() * 4
+    gs, fr = [], []
     for m in FORMS:
-        ms = timed(lambda: bz.eval_bezier(c16, t_d, m, out=o16), torch, iters=20)
-        x16[m] = {"G/s": 16 * n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(n16, ms)["frac"]}
-    rec["x16"] = x16
-    del c16, o16
+        ms = timed(lambda: bz.eval_bezier(c16, t16, m, out=o16), torch, iters=20)
+        gs.append(16 * n_q / (ms * 1e-3) / 1e9)
+        fr.append(hbm_roof(n16, ms)["frac"])
+    rec["x16_random_t"] = {"G/s": gs, "frac": fr}  # in the order of FORMS
+    del c16, t16, o16
     if cpu:
         import oracle
         log("headline: CPU baseline (oracle, three forms)")
@@ -963,7 +966,8 @@ def compact_record(head, batched, chain, steps, warmup, n_curves, n_t, suite_fil
                    "n_curves": n_curves, "n_t": n_t, "dim": 3, "degree": 3},
         "roofline": head["roofline"],
     }
-    for k in ("cpu_baseline", "max_err_bbox", "forms", "launch_floor", "x16", "gpu_ms_per_step", "eager_ms_per_step"):
+    for k in ("cpu_baseline", "max_err_bbox", "forms", "launch_floor", "x16_random_t", "gpu_ms_per_step",
+              "eager_ms_per_step"):
         if k in head:
             rec[k] = head[k]
     if batched:
@@ -1071,7 +1075,7 @@ def main():
     rec = compact_record(head, batched, chain, args.steps, args.warmup, args.n_curves, 256, suite_file, summary)
     line = json.dumps(rec, separators=(",", ":"))
     if len(line) > RECORD_MAX_BYTES:  # drop the least important parts rather than overflow
-        for k in ("suite", "x16", "forms"):
+        for k in ("suite", "x16_random_t", "forms"):
             rec.pop(k, None)
             line = json.dumps(rec, separators=(",", ":"))
             if len(line) <= RECORD_MAX_BYTES:

@@ -97,7 +97,7 @@ def _synthetic_records():
     r = lambda: float(rng.random() * 1e3 + 1e-7)  # noqa: E731
     forms = {m: {"us": r(), "G/s": r(), "frac": r()} for m in bench.FORMS}
     head = {"value": r(), "ms_per_step": r(), "gpu_ms_per_step": r(), "eager_ms_per_step": r(), "forms": forms,
-            "x16": {m: {"G/s": r(), "frac": r()} for m in bench.FORMS},
+            "x16_random_t": {"G/s": [r() for _ in bench.FORMS], "frac": [r() for _ in bench.FORMS]},
             "launch_floor": {"us": r(), "bytes": 12582912, "of_dominant": r()},
             "roofline": {"bound": "hbm", "achieved": r(), "peak": 8000.0, "unit": "GB/s", "frac": r(),
                          "traffic": r(), "kernel": "k_curves<seiler>", "bytes_per_launch": 12780544},
@@ -134,14 +134,15 @@ def test_final_record_is_compact_and_complete():
         assert "plain" in rec["config"]["workload"] and "graph" in rec["config"]["timing"]
         assert {"fp32", "fp16"} <= set(rec["batched"])
         assert set(rec["launch_floor"]) == {"us", "bytes", "of_dominant"}
-        if summary is None:  # the contract's part alone fits well inside the limit
+        if summary is None:  # the contract's part alone fits well inside the limit, x16 included
             assert len(line) <= bench.RECORD_MAX_BYTES, len(line)
+            assert "x16_random_t" in rec
 
 
 def test_main_trims_the_line_to_the_limit():
     head, batched, chain, suite = _synthetic_records()
     rec = bench.compact_record(head, batched, chain, 20, 5, 4096, 256, "f.json", bench.suite_summary(suite))
-    for k in ("suite", "x16", "forms"):
+    for k in ("suite", "x16_random_t", "forms"):
         if len(json.dumps(rec, separators=(",", ":"))) <= bench.RECORD_MAX_BYTES:
             break
         rec.pop(k, None)
