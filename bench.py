@@ -794,7 +794,7 @@ def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=2
         _, sec, reps = oracle_timed(oracle_step, budget_s=10.0, max_reps=200)
         rec["cpu_baseline"] = {"value": 3 * n_q / sec / 1e9, "unit": "G evals/s", "cores": oracle.max_threads(),
                                "kind": "oracle",
-                               "sample": "the whole workload (3 forms x %d x %d, FP64), %d repetitions"
+                               "sample": "3 forms x %d x %d points, FP64, %d reps"
                                          % (n_curves, n_t, reps), "host": host_cpu()}
     return rec
 
@@ -848,7 +848,7 @@ def batched_record(torch, bz, bz_synth, cpu, n_sample=16384):
                 rsub = dataclasses.replace(sub)
                 rsub.ctrl = torch.from_numpy(sub.ctrl).to(dt).float().numpy()
                 rsub.w = torch.from_numpy(sub.w).to(dt).float().numpy()
-                e["max_err_bbox_vs_rounded_inputs"] = max_err_bbox(got, oracle.batch_eval(rsub), ext, b.n_t)
+                e["max_err_bbox_vs_rounded"] = max_err_bbox(got, oracle.batch_eval(rsub), ext, b.n_t)
         plan.close()
         del ctrl, w
         res[name] = e
@@ -959,15 +959,13 @@ def compact_record(head, batched, chain, steps, warmup, n_curves, n_t, suite_fil
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plain: %d cubic 3D Bezier curves x %d uniform t, FP32, by de Casteljau, Bernstein "
-                               "and Seiler" % (n_curves, n_t),
-                   "timing": "step = one HIP-graph replay of the 3 launches (3 x %d evals), wall clock"
+        "config": {"workload": "plain FP32: %d cubic 3D Bezier curves x %d uniform t, 3 forms" % (n_curves, n_t),
+                   "timing": "step = 1 HIP-graph replay of 3 launches (3 x %d evals), wall"
                              % (n_curves * n_t),
                    "n_curves": n_curves, "n_t": n_t, "dim": 3, "degree": 3},
         "roofline": head["roofline"],
     }
-    for k in ("cpu_baseline", "max_err_bbox", "forms", "launch_floor", "x16_random_t", "gpu_ms_per_step",
-              "eager_ms_per_step"):
+    for k in ("cpu_baseline", "max_err_bbox", "forms", "launch_floor", "x16_random_t", "gpu_ms_per_step"):
         if k in head:
             rec[k] = head[k]
     if batched:

@@ -52,7 +52,11 @@ typedef enum {
 
 typedef enum { BZ_F32 = 0, BZ_F16 = 1, BZ_BF16 = 2 } bz_dtype; /* control-point / weight storage */
 
-typedef enum { BZ_DECASTELJAU = 0, BZ_BERNSTEIN = 1, BZ_SEILER = 2 } bz_method;
+/* BZ_AUTO lets the library pick the form: the Bernstein form, the fastest of
+ * the three measured at degree 3 (or within the run-to-run spread) and O(d)
+ * per coordinate against de Casteljau's O(d^2) at higher degrees, at the same
+ * accuracy. */
+typedef enum { BZ_DECASTELJAU = 0, BZ_BERNSTEIN = 1, BZ_SEILER = 2, BZ_AUTO = 3 } bz_method;
 
 typedef enum { BZ_T_SHARED = 0, BZ_T_PER_OBJECT = 1 } bz_tmode;
 
@@ -77,8 +81,8 @@ const char *bz_last_error(void);
  * interpolation; Sec. 5: the Bernstein polynomial form).
  * ctrl: [n_curves][dim][degree+1] in ctrl_dtype.  t: see t_mode.
  * method: BZ_DECASTELJAU (d(d+1)/2 lerps), BZ_BERNSTEIN (basis + d+1 FMAs per
- * coordinate) or BZ_SEILER (difference terms derived per evaluation, then
- * d lerps).  out: [dim][n_curves*n_t] FP32.
+ * coordinate), BZ_SEILER (difference terms derived per evaluation, then
+ * d lerps) or BZ_AUTO.  out: [dim][n_curves*n_t] FP32.
  */
 int bz_eval_bezier(const void *ctrl, int ctrl_dtype, int64_t n_curves, int degree, int dim, const float *t,
                    int64_t n_t, int t_mode, int method, float *out, bz_stream stream);
@@ -372,7 +376,7 @@ int bz_eval_tensor_seiler(const float *sc, int64_t n_obj, int du, int dv, int dw
  * whose v[n_obj][n_t] holds the patches' second parameters (only the rows of
  * patch objects are read), and bz_batch_eval returns BZ_ERR_NULL for it.
  * method:
- * BZ_DECASTELJAU or BZ_BERNSTEIN.  Rational objects whose weights are all
+ * BZ_DECASTELJAU, BZ_BERNSTEIN or BZ_AUTO.  Rational objects whose weights are all
  * positive are evaluated in FP32 (their conditioning number is 1).  Rational
  * objects with a weight that is zero, negative or NaN form classes of their
  * own whose every query takes the conditioning test of bz_eval_rational with

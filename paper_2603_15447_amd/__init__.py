@@ -20,11 +20,11 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "bz.h")
 
 OK, ERR_NULL, ERR_SHAPE, ERR_DTYPE, ERR_UNSUPPORTED, ERR_ALIGN, ERR_HIP, ERR_NOMEM, ERR_INTERNAL = range(9)
 F32, F16, BF16 = 0, 1, 2
-DECASTELJAU, BERNSTEIN, SEILER = 0, 1, 2
+DECASTELJAU, BERNSTEIN, SEILER, AUTO = 0, 1, 2, 3
 T_SHARED, T_PER_OBJECT = 0, 1
 TP_VALU, TP_MFMA_F32, TP_MFMA_BF16, TP_MFMA_F16, TP_MFMA_F16X3 = 0, 1, 2, 3, 4
 
-METHODS = {"decasteljau": DECASTELJAU, "bernstein": BERNSTEIN, "seiler": SEILER}
+METHODS = {"decasteljau": DECASTELJAU, "bernstein": BERNSTEIN, "seiler": SEILER, "auto": AUTO}
 ENGINES = {"valu": TP_VALU, "mfma_f32": TP_MFMA_F32, "mfma_bf16": TP_MFMA_BF16, "mfma_f16": TP_MFMA_F16,
            "mfma_f16x3": TP_MFMA_F16X3}
 TEX_MODES = {"decasteljau": 0, "hybrid": 1, "seiler": 2}

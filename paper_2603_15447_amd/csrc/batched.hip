@@ -357,6 +357,7 @@ int bz_batch_plan_create(int64_t n_obj, const uint16_t *kind_degree, const int64
         if (n_obj < 0 || n_t < 0) return fail(BZ_ERR_SHAPE, "%s: negative count", fn);
         if (dim < 1 || dim > kMaxDim) return fail(BZ_ERR_SHAPE, "%s: dim %d", fn, dim);
         if (dtype_size(dtype) == 0) return fail(BZ_ERR_DTYPE, "%s: dtype %d", fn, dtype);
+        if (method == BZ_AUTO) method = BZ_BERNSTEIN;
         if (method != BZ_DECASTELJAU && method != BZ_BERNSTEIN) return fail(BZ_ERR_UNSUPPORTED, "%s: method %d", fn, method);
         if (n_obj > (int64_t(1) << 31) - 1 || (n_obj > 0 && n_t > ((int64_t(1) << 32) - 1) / std::max<int64_t>(n_obj, 1)))
             return fail(BZ_ERR_SHAPE, "%s: n_obj*n_t must stay below 2^32", fn);

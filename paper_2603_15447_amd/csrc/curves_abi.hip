@@ -114,6 +114,7 @@ int bz_eval_bezier(const void *ctrl, int ctrl_dtype, int64_t n_curves, int degre
         int rc = check_common("bz_eval_bezier", n_curves, degree, dim, n_t, t_mode);
         if (rc) return rc;
         if (dtype_size(ctrl_dtype) == 0) return fail(BZ_ERR_DTYPE, "bz_eval_bezier: dtype %d", ctrl_dtype);
+        if (method == BZ_AUTO) method = BZ_BERNSTEIN;
         if (method != BZ_DECASTELJAU && method != BZ_BERNSTEIN && method != BZ_SEILER)
             return fail(BZ_ERR_UNSUPPORTED, "bz_eval_bezier: method %d", method);
         if (n_curves == 0 || n_t == 0) return BZ_OK;
@@ -132,6 +133,7 @@ int bz_eval_rational(const void *ctrl, const void *w, int dtype, int64_t n_curve
         int rc = check_common("bz_eval_rational", n_curves, degree, dim, n_t, t_mode);
         if (rc) return rc;
         if (dtype_size(dtype) == 0) return fail(BZ_ERR_DTYPE, "bz_eval_rational: dtype %d", dtype);
+        if (method == BZ_AUTO) method = BZ_BERNSTEIN;
         if (method != BZ_DECASTELJAU && method != BZ_BERNSTEIN && method != BZ_SEILER)
             return fail(BZ_ERR_UNSUPPORTED, "bz_eval_rational: method %d", method);
         if (n_curves == 0 || n_t == 0) return BZ_OK;

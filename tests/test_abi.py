@@ -49,6 +49,11 @@ def test_bezier_other_errors(L):
     assert L.bz_eval_bezier(FAKE, 0, -1, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.ERR_SHAPE
     # F16 storage needs only 2-byte alignment
     assert L.bz_eval_bezier(ODD, 1, 0, 3, 3, FAKE, 8, 0, 0, FAKE, None) == bz.OK
+    # BZ_AUTO passes the method check (and then fails on the NULL ctrl); 4 is no method
+    assert L.bz_eval_bezier(None, 0, 4, 3, 3, FAKE, 8, 0, bz.AUTO, FAKE, None) == bz.ERR_NULL
+    assert L.bz_eval_bezier(None, 0, 4, 3, 3, FAKE, 8, 0, 4, FAKE, None) == bz.ERR_UNSUPPORTED
+    assert L.bz_eval_rational(None, FAKE, 0, 4, 3, 3, FAKE, 8, 0, bz.AUTO, 64.0, FAKE, None, None) == bz.ERR_NULL
+    assert L.bz_eval_rational(None, FAKE, 0, 4, 3, 3, FAKE, 8, 0, 4, 64.0, FAKE, None, None) == bz.ERR_UNSUPPORTED
 
 
 def test_zero_size_calls_launch_nothing(L):

@@ -103,10 +103,10 @@ def _synthetic_records():
                          "traffic": r(), "kernel": "k_curves<seiler>", "bytes_per_launch": 12780544},
             "max_err_bbox": {m: r() for m in bench.FORMS},
             "cpu_baseline": {"value": r(), "unit": "G evals/s", "cores": 16, "kind": "oracle",
-                             "sample": "the whole workload (3 forms x 4096 x 256, FP64), 12 repetitions",
+                             "sample": "3 forms x 4096 x 256 points, FP64, 200 reps",
                              "host": "AMD EPYC 9575F 64-Core Processor"}}
     batched = {n: {"us": r(), "G/s": r(), "frac": r(), "bytes": 477089864, "max_err_bbox": r(),
-                   "max_err_bbox_vs_rounded_inputs": r(), "config": [3072, 4, "static", 4, 131072]}
+                   "max_err_bbox_vs_rounded": r(), "config": [3072, 4, "static", 4, 131072]}
                for n in ("fp32", "fp16")}
     batched["cpu_baseline"] = {"value": r(), "unit": "G evals/s", "cores": 16, "kind": "oracle",
                                "sample": "16384 random objects x 16 t, FP64"}

@@ -25,6 +25,27 @@ def test_curves_all_degrees(orc, degree, method):
         assert err <= TOL_F32, (degree, dim, method, err)
 
 
+def test_auto_method_is_the_bernstein_form():
+    """BZ_AUTO resolves to the Bernstein form: bit-identical results for
+    integral and rational curves (low and high degree) and for a batch plan."""
+    for degree in (3, 12):
+        ctrl, t = bz_synth.random_curves(29, degree, 3, 40, seed=77 + degree)
+        c, tt = to_dev(ctrl), to_dev(t)
+        np.testing.assert_array_equal(host(bz.eval_bezier(c, tt, "auto")), host(bz.eval_bezier(c, tt, "bernstein")))
+        w = to_dev(np.random.default_rng(degree).uniform(0.5, 2.0, (29, degree + 1)))
+        np.testing.assert_array_equal(host(bz.eval_rational(c, w, tt, "auto")),
+                                      host(bz.eval_rational(c, w, tt, "bernstein")))
+    b = bz_synth.mixed_batch(n_bezier=300, n_nurbs=20, n_t=8, seed=5)
+    dv = lambda x: torch.from_numpy(x).cuda()  # noqa: E731
+    outs = []
+    for m in ("auto", "bernstein"):
+        plan = bz.BatchPlan(dv(b.kind_degree.astype(np.int16)), dv(b.cp_offset), to_dev(b.ctrl), to_dev(b.w), 3,
+                            dv(b.knot_offset), to_dev(b.knots), 8, m)
+        outs.append(host(plan(to_dev(b.t))))
+        plan.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_config_plain_full_size(orc, method):
     """4096 cubic 3D curves x 256 shared t (1M points), every point checked."""
