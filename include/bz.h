@@ -396,7 +396,8 @@ int bz_batch_eval_uv(bz_plan plan, const float *t, const float *v, float *out, b
  * objects with every class's tiles for a window together, heaviest class
  * first: neighbouring objects' parameter rows and points, which share cache
  * lines, are then read and written closer in time, and heavy and light
- * classes alternate through the launch) x 2 lane mappings (one query per lane, or --
+ * classes alternate through the launch; for FP32 storage, in either order,
+ * the NURBS tiles are spread evenly among the others) x 2 lane mappings (one query per lane, or --
  * when n_t is a multiple of 4 -- four consecutive parameters of one object per
  * lane) x 3 tile sizes (1, 2 or 4 sub-tiles of 256 lanes per tile) x 2
  * schedules (atomic tile counter, static round robin) x 4 grid sizes (4, 8,

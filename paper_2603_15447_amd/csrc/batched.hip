@@ -328,6 +328,26 @@ int build_tiles(bz_plan_s *p, uint32_t qpt, uint32_t vq, uint32_t window, hipStr
             }
         }
     }
+    // FP32 plans: NURBS tiles (a chain of dependent random loads per query,
+    // cold in steady state) spread evenly through the others instead of one
+    // run per window or class, so every stretch of the launch overlaps a few
+    // of them with the streaming Bezier tiles (measured faster for FP32
+    // storage, whose NURBS queries go through the bucket table, and no
+    // faster for 16-bit storage)
+    if (p->dtype == BZ_F32) {
+        std::vector<Tile> nb, rest;
+        for (const Tile &t : tiles) (t.ci.kind == 2 ? nb : rest).push_back(t);
+        if (!nb.empty() && !rest.empty()) {
+            tiles.clear();
+            const uint64_t R = rest.size(), N = nb.size();
+            size_t k = 0;
+            for (uint64_t i = 0; i < R; ++i) {  // NURBS tile k goes before other tile floor(k*R/N)
+                for (; k < N && k * R / N <= i; ++k) tiles.push_back(nb[k]);
+                tiles.push_back(rest[i]);
+            }
+            for (; k < N; ++k) tiles.push_back(nb[k]);
+        }
+    }
     const size_t n_main = tiles.size();
     for (int c : signed_cls) emit(c, 0, static_cast<uint64_t>(cls[c].count) * nt);
     if (p->tiles) BZ_CHECK_HIP(hipStreamSynchronize(s));
