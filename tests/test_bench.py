@@ -96,7 +96,8 @@ def _synthetic_records():
     rng = np.random.default_rng(0)
     r = lambda: float(rng.random() * 1e3 + 1e-7)  # noqa: E731
     forms = {m: {"us": r(), "G/s": r(), "frac": r()} for m in bench.FORMS}
-    head = {"value": r(), "ms_per_step": r(), "gpu_ms_per_step": r(), "eager_ms_per_step": r(), "forms": forms,
+    head = {"value": r(), "ms_per_step": r(), "gpu_ms_per_step": r(), "replay_ms_per_step": r(),
+            "eager_ms_per_step": r(), "forms": forms,
             "x16_random_t": {"G/s": [r() for _ in bench.FORMS], "frac": [r() for _ in bench.FORMS]},
             "launch_floor": {"us": r(), "bytes": 12582912, "of_dominant": r()},
             "roofline": {"bound": "hbm", "achieved": r(), "peak": 8000.0, "unit": "GB/s", "frac": r(),
