@@ -110,11 +110,12 @@ def timed(fn, torch, iters=20, warmup=3):
     return event_time_ms(fn, iters, torch)
 
 
-def graph_time_ms(fn, torch, launches=50, replays=5):
+def graph_time_ms(fn, torch, launches=50, replays=5, trials=1):
     """Device time per launch of fn() with launch overhead removed: `launches`
     back-to-back calls captured once into a HIP graph (the library launches
     on torch's current stream, which is the capture stream here), the graph
-    replayed `replays` times between HIP events.  For kernels of a few
+    replayed `replays` times between HIP events; with trials > 1, the median
+    over that many such timings of the same graph.  For kernels of a few
     microseconds, where issuing each launch from Python costs more than the
     kernel itself."""
     for _ in range(3):
@@ -128,14 +129,17 @@ def graph_time_ms(fn, torch, launches=50, replays=5):
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(s)
-    for _ in range(replays):
-        g.replay()
-    b.record(s)
-    b.synchronize()
-    ms = a.elapsed_time(b) / (replays * launches)
+    times = []
+    for _ in range(trials):
+        a.record(s)
+        for _ in range(replays):
+            g.replay()
+        b.record(s)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / (replays * launches))
     del g
-    return ms
+    times.sort()
+    return times[len(times) // 2]
 
 
 def hbm_roof(nbytes, ms):
@@ -760,12 +764,13 @@ def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=2
     torch.cuda.synchronize()
     replay_ms = (time.perf_counter() - t0) * 1e3 / steps
     del g
-    # each form's kernel on its own: a HIP graph of 50 launches replayed,
-    # timed with HIP events on the launch stream (the kernels last a few us)
+    # each form's kernel on its own: a HIP graph of 50 launches replayed 10
+    # times between HIP events on the launch stream (the kernels last a few
+    # us), the median of five such timings
     nbytes = plain_bytes(n_curves, 3, 3, n_t)
     forms = {}
     for m in FORMS:
-        ms = graph_time_ms(lambda: bz.eval_bezier(c_d, t_d, m, out=outs[m]), torch, launches=50, replays=10)
+        ms = graph_time_ms(lambda: bz.eval_bezier(c_d, t_d, m, out=outs[m]), torch, launches=50, replays=10, trials=5)
         forms[m] = {"us": ms * 1e3, "G/s": n_q / (ms * 1e-3) / 1e9, "frac": hbm_roof(nbytes, ms)["frac"]}
     dom = max(FORMS, key=lambda m: forms[m]["us"])
     roof = hbm_roof(nbytes, forms[dom]["us"] * 1e-3)
@@ -775,7 +780,8 @@ def headline_plain(torch, bz, bz_synth, steps, warmup, cpu, n_curves=4096, n_t=2
     # what a launch of this size costs at best: a write-only kernel storing the
     # same output bytes (one 16-byte vector per thread), timed the same way
     wbuf = torch.empty(3 * n_q, device="cuda")
-    floor_ms = graph_time_ms(lambda: bz.hbm_probe("write", wbuf, wbuf, blocks_per_cu=0), torch, launches=50, replays=10)
+    floor_ms = graph_time_ms(lambda: bz.hbm_probe("write", wbuf, wbuf, blocks_per_cu=0), torch, launches=50, replays=10,
+                             trials=5)
     del wbuf
     floor = {"us": floor_ms * 1e3, "bytes": 12 * n_q, "of_dominant": floor_ms * 1e3 / forms[dom]["us"]}
     rec = {"value": 3 * n_q / (ms_per_step * 1e-3) / 1e9, "ms_per_step": ms_per_step,
